@@ -1,0 +1,126 @@
+"""Line-by-line opacity table (oracle; test infrastructure only).
+
+Secondary path: transit's first pass computes, per molecule, a cross-section table
+on the output wavenumber grid at the atmosphere's layer pressures and over a grid of
+temperatures (Sec. 3, Sec. 4); each line is a Voigt profile (Sec. 6.1.1, Eqs. 2-11)
+point-sampled at the output wavenumbers rather than bin-averaged (Sec. 4).
+
+This oracle evaluates the Voigt profile of every line at every grid point inside
+its cutoff window, directly from the Faddeeva function (scipy.special.wofz, the
+routine BARTTest itself compares against, Sec. 6.1.1), with no profile table,
+no strength summing and no strength cutoff.
+"""
+from __future__ import annotations
+
+import math
+import numpy as np
+from scipy.special import wofz
+
+from .constants import K_B, M_U, C_LIGHT, C2, ATM_BAR, T_REF
+
+CUTOFF_HWHM = 25.0
+
+
+def partition_ratio(temp: float) -> float:
+    """Q(T_ref)/Q(T) for the power-law partition function Q ~ T^1.5 of the synthetic
+    species (real partition-function tables are not available)."""
+    return (T_REF / temp) ** 1.5
+
+
+def line_strength(s296, nu0, elow, temp: float):
+    """S(T) = S_296 Q(296)/Q(T) exp(-c2 E''/T)/exp(-c2 E''/296)
+              (1 - exp(-c2 nu0/T)) / (1 - exp(-c2 nu0/296))."""
+    boltz = np.exp(-C2 * elow / temp) / np.exp(-C2 * elow / T_REF)
+    stim = (1.0 - np.exp(-C2 * nu0 / temp)) / (1.0 - np.exp(-C2 * nu0 / T_REF))
+    return s296 * partition_ratio(temp) * boltz * stim
+
+
+def doppler_sigma(nu0, mass_amu, temp: float):
+    """Gaussian standard deviation of Eq. 2 for thermal Doppler broadening:
+    sigma = (nu0 / c) sqrt(k_B T / m)."""
+    return nu0 / C_LIGHT * np.sqrt(K_B * temp / (mass_amu * M_U))
+
+
+def lorentz_gamma(gamma296, temp: float, p_bar: float):
+    """Lorentz half width of Eq. 3: gamma = gamma_296 (p / 1 atm) (296 / T)^0.5."""
+    return gamma296 * (p_bar / ATM_BAR) * (T_REF / temp) ** 0.5
+
+
+def voigt_hwhm(sigma, gamma):
+    """Voigt half width at half maximum (Olivero & Longbothum 1977):
+    0.5346 gamma + sqrt(0.2166 gamma^2 + 2 ln2 sigma^2)."""
+    return 0.5346 * gamma + np.sqrt(0.2166 * gamma ** 2 + 2.0 * math.log(2.0) * sigma ** 2)
+
+
+def voigt(dnu, sigma, gamma):
+    """Voigt profile V(nu; sigma, gamma) = Re w(z) / (sigma sqrt(2 pi)),
+    z = (nu + i gamma)/(sigma sqrt 2)  (Eqs. 4-11)."""
+    z = (dnu + 1j * gamma) / (sigma * math.sqrt(2.0))
+    return wofz(z).real / (sigma * math.sqrt(2.0 * math.pi))
+
+
+def gaussian(dnu, sigma):
+    """Eq. 2."""
+    return np.exp(-dnu ** 2 / (2.0 * sigma ** 2)) / (sigma * math.sqrt(2.0 * math.pi))
+
+
+def lorentzian(dnu, gamma):
+    """Eq. 3."""
+    return gamma / (math.pi * (dnu ** 2 + gamma ** 2))
+
+
+def line_window(nu_start: float, dnu: float, n_nu: int, nu0, hw):
+    """Grid indices k with |nu_k - nu0| <= CUTOFF_HWHM * hw (inclusive), as [k_lo, k_hi)."""
+    half = CUTOFF_HWHM * hw
+    # one index of slack either side; the caller applies the exact inclusive test
+    k_lo = np.ceil((nu0 - half - nu_start) / dnu).astype(np.int64) - 1
+    k_hi = np.floor((nu0 + half - nu_start) / dnu).astype(np.int64) + 2
+    k_lo = np.clip(k_lo, 0, n_nu)
+    k_hi = np.clip(k_hi, 0, n_nu)
+    return k_lo, k_hi
+
+
+def cell_cross_section(lines, temp: float, p_bar: float, nu_start: float, dnu: float,
+                       n_nu: int, chunk: int = 4096) -> np.ndarray:
+    """One (T, p) cell of the table: sigma[k] = sum_lines S(T) V(nu_k - nu0) over the
+    grid points inside each line's window (cm^2 / molecule)."""
+    out = np.zeros(n_nu, dtype=np.float64)
+    s_t = line_strength(lines.s296, lines.nu0, lines.elow, temp)
+    sig = doppler_sigma(lines.nu0, lines.mass_amu, temp)
+    gam = lorentz_gamma(lines.gamma296, temp, p_bar)
+    hw = voigt_hwhm(sig, gam)
+    k_lo, k_hi = line_window(nu_start, dnu, n_nu, lines.nu0, hw)
+    for c0 in range(0, len(lines), chunk):
+        sl = slice(c0, c0 + chunk)
+        cnt = np.maximum(k_hi[sl] - k_lo[sl], 0)
+        if cnt.sum() == 0:
+            continue
+        owner = np.repeat(np.arange(cnt.size), cnt)
+        first = np.repeat(k_lo[sl], cnt)
+        offs = np.arange(cnt.sum()) - np.repeat(np.cumsum(cnt) - cnt, cnt)
+        k = first + offs
+        d = (nu_start + dnu * k) - lines.nu0[sl][owner]
+        inside = np.abs(d) <= CUTOFF_HWHM * hw[sl][owner]
+        val = s_t[sl][owner] * voigt(d, sig[sl][owner], gam[sl][owner])
+        np.add.at(out, k[inside], val[inside])
+    return out
+
+
+def opacity_table(lines, temps, p_bar, nu_start: float, dnu: float, n_nu: int) -> np.ndarray:
+    """Full table sigma[T][p][nu] by brute force over lines and cells."""
+    out = np.zeros((len(temps), len(p_bar), n_nu), dtype=np.float64)
+    for it, t in enumerate(temps):
+        for ip, p in enumerate(p_bar):
+            out[it, ip] = cell_cross_section(lines, float(t), float(p), nu_start, dnu, n_nu)
+    return out
+
+
+def point_cross_section(lines, temp: float, p_bar: float, nu: float) -> float:
+    """sigma at one wavenumber: the sum over every line whose window contains nu."""
+    s_t = line_strength(lines.s296, lines.nu0, lines.elow, temp)
+    sig = doppler_sigma(lines.nu0, lines.mass_amu, temp)
+    gam = lorentz_gamma(lines.gamma296, temp, p_bar)
+    hw = voigt_hwhm(sig, gam)
+    d = nu - lines.nu0
+    m = np.abs(d) <= CUTOFF_HWHM * hw
+    return float(np.sum(s_t[m] * voigt(d[m], sig[m], gam[m])))

@@ -1,0 +1,126 @@
+"""Transmission radiative transfer of the forward model (oracle; test infrastructure only).
+
+Steps a3-a6 of the hot path (Sec. 3: transit interpolates the pre-computed opacity
+table to each layer's temperature, the table lives on the layer pressures and the
+output wavenumber grid; Sec. 6.1: the transmission calculation takes slant path
+lengths at several altitudes, the optical depth and transmission along them,
+multiplies by 2 pi r and integrates over altitude; the result is a transmission
+modulation spectrum that the spectrum integrator bins into channels).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .atmosphere import atmosphere, FLAG_T_CLAMP, FLAG_RADIUS
+
+
+def interp_index(t_grid: np.ndarray, temp: float):
+    """Linear-in-T interpolation bracket: k = largest index with T_k <= T, clamped to
+    [0, NT-2]; weight w = (T - T_k)/(T_{k+1} - T_k) clamped to [0, 1].
+    Returns (k, w, clamped)."""
+    nt = t_grid.size
+    k = int(np.searchsorted(t_grid, temp, side="right")) - 1
+    k = min(max(k, 0), nt - 2)
+    w = (temp - t_grid[k]) / (t_grid[k + 1] - t_grid[k])
+    clamped = not (t_grid[0] <= temp <= t_grid[-1])
+    w = min(max(w, 0.0), 1.0)
+    return k, w, clamped
+
+
+def extinction(sigma: np.ndarray, t_grid: np.ndarray, temp: np.ndarray, n_species: np.ndarray,
+               cia: np.ndarray | None = None, cia_t_grid: np.ndarray | None = None,
+               n_h2: np.ndarray | None = None):
+    """Step a3. sigma[S][NT][L][Nnu] in cm^2/molecule on the layer pressures;
+    e_l(nu) = sum_i n_{i,l} sigma_i(T_l, p_l, nu)
+              + n_{H2,l}^2 K(T_l, nu)            (CIA, cm^5 molecule^-2)
+    with sigma and K interpolated linearly in T. Returns (e[L][Nnu], flags)."""
+    S, NT, L, NNU = sigma.shape
+    e = np.zeros((L, NNU), dtype=np.float64)
+    flags = 0
+    for l in range(L):
+        k, w, clamped = interp_index(t_grid, temp[l])
+        if clamped:
+            flags |= FLAG_T_CLAMP
+        for i in range(S):
+            s_lo = sigma[i, k, l].astype(np.float64)
+            s_hi = sigma[i, k + 1, l].astype(np.float64)
+            e[l] += n_species[i, l] * ((1.0 - w) * s_lo + w * s_hi)
+        if cia is not None:
+            kc, wc, clamped = interp_index(cia_t_grid, temp[l])
+            if clamped:
+                flags |= FLAG_T_CLAMP
+            c_lo = cia[kc].astype(np.float64)
+            c_hi = cia[kc + 1].astype(np.float64)
+            e[l] += n_h2[l] ** 2 * ((1.0 - wc) * c_lo + wc * c_hi)
+    return e, flags
+
+
+def chord_path(radius: np.ndarray, j: int, l: int) -> float:
+    """Half-chord length from the tangent point of impact parameter b_j = r_j to the
+    sphere of radius r_l (l >= j): s = sqrt(r_l^2 - r_j^2), written as a product of a
+    difference and a sum to avoid cancellation."""
+    return float(np.sqrt((radius[l] - radius[j]) * (radius[l] + radius[j])))
+
+
+def optical_depth(radius: np.ndarray, ext: np.ndarray) -> np.ndarray:
+    """Step a4. Chord optical depth at impact parameter b_j = r_j: the trapezoid in path
+    length along both halves of the chord,
+    tau_j = sum_{l=j}^{L-2} (s_{j,l+1} - s_{j,l}) (e_l + e_{l+1}),  tau_{L-1} = 0."""
+    L, NNU = ext.shape
+    tau = np.zeros((L, NNU), dtype=np.float64)
+    for j in range(L):
+        for l in range(j, L - 1):
+            ds = chord_path(radius, j, l + 1) - chord_path(radius, j, l)
+            tau[j] += ds * (ext[l] + ext[l + 1])
+    return tau
+
+
+def transit_depth(radius: np.ndarray, tau: np.ndarray, rs_cm: float) -> np.ndarray:
+    """Step a5. Transit depth: an opaque disk inside the deepest layer plus the
+    absorbed fraction of each annulus, trapezoid in impact parameter,
+    depth = [r_0^2 + 2 int_{r_0}^{r_top} (1 - exp(-tau(b))) b db] / Rs^2
+          = [r_0^2 + sum_j (r_{j+1} - r_j)(f_j r_j + f_{j+1} r_{j+1})] / Rs^2,
+    f = 1 - exp(-tau)."""
+    L, NNU = tau.shape
+    f = -np.expm1(-tau)
+    acc = np.full(NNU, radius[0] ** 2, dtype=np.float64)
+    for j in range(L - 1):
+        acc += (radius[j + 1] - radius[j]) * (f[j] * radius[j] + f[j + 1] * radius[j + 1])
+    return acc / rs_cm ** 2
+
+
+def bin_spectrum(depth: np.ndarray, bin_width: int) -> np.ndarray:
+    """Step a6 (spectrum integrator). Channels with perfect transmission over their
+    range (Sec. 6.3): the mean of each group of ``bin_width`` consecutive points;
+    a ragged tail shorter than a bin is dropped."""
+    nb = depth.size // bin_width
+    return depth[: nb * bin_width].reshape(nb, bin_width).mean(axis=1)
+
+
+def chi_squared(model: np.ndarray, data: np.ndarray, err: np.ndarray) -> float:
+    """Step a6. chi^2 = sum ((model - data) / err)^2 (Sec. 3: MC3 computes chi^2)."""
+    return float(np.sum(((model - data) / err) ** 2))
+
+
+def forward(params: np.ndarray, setup, sigma: np.ndarray, cia: np.ndarray | None = None,
+            data: np.ndarray | None = None, err: np.ndarray | None = None):
+    """Steps a1-a6 for one parameter vector. Returns a dict with the spectrum, the
+    intermediate arrays, binned depths and chi^2 (when data are given), and flags.
+    A sample whose radii are invalid gets a NaN spectrum."""
+    atm = atmosphere(params, setup.p_bar, setup.mass_amu, setup.tp_mode, setup.planet)
+    flags = atm["flags"]
+    ext, f = extinction(sigma, setup.temps, atm["temp"], atm["n_species"],
+                        cia, setup.cia_temps, atm["n_h2"])
+    flags |= f
+    if flags & FLAG_RADIUS:
+        nan = np.full(setup.nu.size, np.nan)
+        out = dict(atm=atm, ext=ext, tau=None, depth=nan, flags=flags)
+    else:
+        tau = optical_depth(atm["radius"], ext)
+        depth = transit_depth(atm["radius"], tau, setup.planet.rs_cm)
+        out = dict(atm=atm, ext=ext, tau=tau, depth=depth, flags=flags)
+    if setup.bin_width:
+        out["binned"] = bin_spectrum(out["depth"], setup.bin_width)
+        if data is not None:
+            out["chi2"] = chi_squared(out["binned"], data, err)
+    return out

@@ -1,0 +1,250 @@
+"""Pins of the oracle's atmosphere and transmission arithmetic against closed forms,
+limits and invariants (Sec. 3, Sec. 6.1, Sec. 6.2)."""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate
+from scipy.special import expn
+
+from oracle import atmosphere as atm
+from oracle import rt
+from oracle.constants import K_B, M_U, BAR
+import workloads as wl
+
+PL = wl.Planet()
+
+
+def _radii_geometric(L, r0=8.0e9, r_top=8.5e9):
+    return np.linspace(r0, r_top, L)
+
+
+# ------------------------------------------------------------------ chord optical depth
+def test_uniform_extinction_gives_exact_chord():
+    # uniform e: tau_j = 2 e sqrt(R_top^2 - b_j^2), exactly for the trapezoid in s
+    L = 37
+    r = np.sort(8.0e9 + 4.0e8 * np.random.default_rng(3).random(L))
+    e = np.full((L, 3), [1e-9, 3e-7, 2e-5])
+    tau = rt.optical_depth(r, e)
+    exact = 2 * e[0][None, :] * np.sqrt(r[-1] ** 2 - r[:, None] ** 2)
+    np.testing.assert_allclose(tau, exact, rtol=1e-12, atol=0)
+
+
+def test_tau_monotone_in_impact_parameter():
+    # extinction non-increasing outward -> tau non-increasing in b
+    L = 40
+    r = _radii_geometric(L)
+    e = np.exp(-np.arange(L) / 4.0)[:, None] * np.array([[1e-6, 1e-3]])
+    tau = rt.optical_depth(r, e)
+    assert np.all(np.diff(tau, axis=0) <= 0.0)
+    assert np.all(tau[-1] == 0.0)
+
+
+def test_tau_single_layer_slab():
+    # extinction only in one shell [r_m, r_{m+1}]: the ray tangent at r_m crosses the
+    # shell over its full chord; trapezoid pieces reduce to s_{m,m+1} (e_m + e_{m+1})
+    L, m = 10, 4
+    r = _radii_geometric(L)
+    e = np.zeros((L, 1))
+    e[m] = 2e-7
+    tau = rt.optical_depth(r, e)
+    s = math.sqrt(r[m + 1] ** 2 - r[m] ** 2)
+    assert tau[m, 0] == pytest.approx(s * 2e-7, rel=1e-13)
+    assert np.all(tau[m + 1:] == 0.0)
+
+
+# ------------------------------------------------------------------ transit depth
+def test_opaque_disk_depth():
+    # no extinction -> depth = (r_0 / Rs)^2 exactly
+    L = 25
+    r = _radii_geometric(L)
+    tau = np.zeros((L, 4))
+    d = rt.transit_depth(r, tau, PL.rs_cm)
+    np.testing.assert_allclose(d, (r[0] / PL.rs_cm) ** 2, rtol=1e-15)
+
+
+def test_saturated_depth():
+    # tau -> infinity below the top layer -> depth = r_{L-2} r_{L-1} / Rs^2
+    L = 25
+    r = _radii_geometric(L)
+    tau = np.full((L, 2), 1e6)
+    tau[-1] = 0.0
+    d = rt.transit_depth(r, tau, PL.rs_cm)
+    np.testing.assert_allclose(d, r[-2] * r[-1] / PL.rs_cm ** 2, rtol=1e-14)
+
+
+def test_uniform_extinction_depth_converges_at_order_1p5():
+    # closed form for uniform e: Rs^2 depth = R_top^2 - 2 [1 - (1 + kU) e^{-kU}] / k^2,
+    # k = 2e, U = sqrt(R_top^2 - r_0^2). tau(b) ~ sqrt(R_top - b) near the top, so the
+    # trapezoid in b converges as h^1.5 (error ratio 2^1.5 per halving), not h^2
+    r0, rt_ = 8.0e9, 8.05e9
+    e = 2e-9
+    k, U = 2 * e, math.sqrt(rt_ ** 2 - r0 ** 2)
+    exact = (rt_ ** 2 - 2 * (1 - (1 + k * U) * math.exp(-k * U)) / k ** 2) / PL.rs_cm ** 2
+    errs = []
+    for L in (400, 800, 1600):
+        r = np.linspace(r0, rt_, L)
+        tau = (2 * e * np.sqrt(rt_ ** 2 - r ** 2))[:, None]   # exact chords (pinned above)
+        d = rt.transit_depth(r, tau, PL.rs_cm)[0]
+        errs.append(abs(d - exact) / (exact - (r0 / PL.rs_cm) ** 2))
+    assert errs[-1] < 2e-5
+    assert errs[0] / errs[1] == pytest.approx(2 ** 1.5, rel=0.03)
+    assert errs[1] / errs[2] == pytest.approx(2 ** 1.5, rel=0.03)
+
+
+def test_depth_bounds():
+    L = 30
+    r = _radii_geometric(L)
+    tau = np.abs(np.random.default_rng(1).normal(size=(L, 50))) * 3
+    d = rt.transit_depth(r, tau, PL.rs_cm)
+    assert np.all(d >= (r[0] / PL.rs_cm) ** 2)
+    assert np.all(d <= (r[-1] / PL.rs_cm) ** 2)
+
+
+def test_thin_limit_linearity():
+    # transmission analogue of f05abundance (Sec. 6.1.2, Table 3): for tau << 1 the
+    # absorbed part of the depth scales with abundance; the ratio falls slightly below the
+    # abundance ratio, by an amount of the order of tau (second-order term of 1 - e^-tau)
+    L = 30
+    r = _radii_geometric(L)
+    shape = np.exp(-np.arange(L) / 5.0)[:, None]
+    base = rt.transit_depth(r, np.zeros((L, 1)), PL.rs_cm)[0]
+    e1 = 1e-13 * shape
+    d1 = rt.transit_depth(r, rt.optical_depth(r, e1), PL.rs_cm)[0] - base
+    taumax = rt.optical_depth(r, e1).max()
+    for f in range(2, 11):
+        df = rt.transit_depth(r, rt.optical_depth(r, f * e1), PL.rs_cm)[0] - base
+        ratio = df / d1
+        assert ratio < f
+        assert f - ratio < f * f * taumax
+
+
+# ------------------------------------------------------------------ extinction
+def test_extinction_interpolation_exact_for_linear_tables():
+    S, L, N = 2, 5, 7
+    tg = np.array([500.0, 900.0, 1500.0, 2500.0])
+    a = np.random.default_rng(2).random((S, 1, L, N)) * 1e-22
+    b = np.random.default_rng(3).random((S, 1, L, N)) * 1e-25
+    sigma = a + b * tg[None, :, None, None]
+    temp = np.array([500.0, 777.0, 1499.0, 2000.0, 2500.0])
+    n = np.random.default_rng(4).random((S, L)) * 1e15
+    e, flags = rt.extinction(sigma, tg, temp, n)
+    expect = np.einsum("sl,sln->ln", n, a[:, 0] + b[:, 0] * temp[None, :, None])
+    np.testing.assert_allclose(e, expect, rtol=1e-13)
+    assert flags == 0
+
+
+def test_extinction_clamps_and_flags():
+    tg = np.array([500.0, 1000.0])
+    sigma = np.array([[[[1.0]], [[3.0]]]])          # [1][2][1][1]
+    e, f = rt.extinction(sigma, tg, np.array([200.0]), np.array([[2.0]]))
+    assert e[0, 0] == 2.0 and f & atm.FLAG_T_CLAMP
+    e, f = rt.extinction(sigma, tg, np.array([4000.0]), np.array([[2.0]]))
+    assert e[0, 0] == 6.0 and f & atm.FLAG_T_CLAMP
+    e, f = rt.extinction(sigma, tg, np.array([1000.0]), np.array([[2.0]]))
+    assert e[0, 0] == 6.0 and f == 0
+
+
+def test_cia_scales_with_density_squared():
+    tg = np.array([500.0, 1000.0])
+    sigma = np.zeros((1, 2, 1, 3))
+    cia = np.array([[1e-45, 2e-45, 3e-45], [3e-45, 4e-45, 5e-45]])
+    e1, _ = rt.extinction(sigma, tg, np.array([750.0]), np.zeros((1, 1)), cia, tg,
+                          np.array([1e19]))
+    e2, _ = rt.extinction(sigma, tg, np.array([750.0]), np.zeros((1, 1)), cia, tg,
+                          np.array([2e19]))
+    np.testing.assert_allclose(e2, 4 * e1, rtol=1e-15)
+    np.testing.assert_allclose(e1[0], 1e38 * np.array([2e-45, 3e-45, 4e-45]), rtol=1e-14)
+
+
+def test_binning():
+    d = np.arange(95, dtype=float)
+    b = rt.bin_spectrum(d, 10)
+    assert b.size == 9
+    np.testing.assert_allclose(b, np.arange(9) * 10 + 4.5)
+
+
+# ------------------------------------------------------------------ atmosphere
+def test_isothermal_radii_closed_form():
+    # T, mu constant: 1/r = 1/R_ref + k_B T / (GM mu m_u) ln(p / p_ref)
+    p = wl.layer_pressures(50)
+    T = 1234.0
+    mu = 2.5
+    r, f = atm.radii(p, np.full(p.size, T), mu, 1.1 * wl.R_JUP_CM, PL)
+    gm = PL.g_nom * PL.r_nom_cm ** 2
+    inv = 1 / (1.1 * wl.R_JUP_CM) + K_B * T / (gm * mu * M_U) * np.log(p / PL.p_ref_bar)
+    np.testing.assert_allclose(r, 1 / inv, rtol=1e-14)
+    assert f == 0
+    assert np.all(np.diff(r) > 0)
+
+
+def test_radii_linear_profile_exact():
+    # T linear in ln p: the trapezoid integral is exact
+    p = wl.layer_pressures(31)
+    lnp = np.log(p)
+    T = 1000.0 + 30.0 * (lnp - math.log(PL.p_ref_bar))
+    mu = 2.3
+    r, _ = atm.radii(p, T, mu, 1.2 * wl.R_JUP_CM, PL)
+    gm = PL.g_nom * PL.r_nom_cm ** 2
+    x = lnp - math.log(PL.p_ref_bar)
+    integral = 1000.0 * x + 15.0 * x ** 2
+    inv = 1 / (1.2 * wl.R_JUP_CM) + K_B / (gm * mu * M_U) * integral
+    np.testing.assert_allclose(r, 1 / inv, rtol=1e-13)
+
+
+def test_expn2_against_its_integral():
+    for x in (1e-6, 0.03, 0.7, 3.0, 20.0):
+        val, _ = integrate.quad(lambda t: math.exp(-x * t) / t ** 2, 1, np.inf, epsrel=1e-13)
+        assert expn(2, x) == pytest.approx(val, rel=1e-11)
+
+
+def test_line2013_top_of_atmosphere_limit():
+    # tau -> 0: xi -> 2/3 + 2 gamma / 3, T^4 -> T_int^4 / 2 + 3/4 T_irr^4 [...]
+    tp = np.array([-3.0, -0.5, 0.3, 0.4, 0.9])
+    p = np.array([1e-14])
+    T = atm.temperature_line2013(p, tp, PL)[0]
+    g1, g2, al, be = 10 ** -0.5, 10 ** 0.3, 0.4, 0.9
+    tirr = be * math.sqrt(PL.rstar_cm / (2 * PL.a_cm)) * PL.tstar
+    t4 = PL.tint ** 4 / 2 + 0.75 * tirr ** 4 * ((1 - al) * (2 / 3 + 2 * g1 / 3)
+                                                 + al * (2 / 3 + 2 * g2 / 3))
+    assert T == pytest.approx(t4 ** 0.25, rel=1e-9)
+
+
+def test_line2013_deep_limit():
+    # gamma tau >> 1: xi -> 2/3 + 2/(3 gamma); the internal term grows as 3/4 T_int^4 tau
+    tp = np.array([0.0, 0.5, 0.8, 0.3, 1.1])
+    p = np.array([100.0])
+    T = atm.temperature_line2013(p, tp, PL)[0]
+    tau = 1.0 * 100.0 * BAR / PL.g_nom
+    g1, g2, al, be = 10 ** 0.5, 10 ** 0.8, 0.3, 1.1
+    tirr = be * math.sqrt(PL.rstar_cm / (2 * PL.a_cm)) * PL.tstar
+    t4 = (0.75 * PL.tint ** 4 * (2 / 3 + tau)
+          + 0.75 * tirr ** 4 * ((1 - al) * (2 / 3 + 2 / (3 * g1)) + al * (2 / 3 + 2 / (3 * g2))))
+    assert T == pytest.approx(t4 ** 0.25, rel=1e-12)
+
+
+def test_irradiation_temperature_matches_hot_jupiter():
+    # beta = 1 for the HD 189733 b-like system gives T_irr ~ 1190 K (the "~1100 K"
+    # mean temperatures of the comparison tests, Table 1)
+    tirr = math.sqrt(PL.rstar_cm / (2 * PL.a_cm)) * PL.tstar
+    assert 1150 < tirr < 1220
+
+
+def test_composition_filler():
+    x, xh2, xhe, mu, f = atm.composition(np.array([-30.0]), np.array([18.0]), PL)
+    assert mu == pytest.approx(0.85 * 2.01588 + 0.15 * 4.002602, rel=1e-12)
+    assert f == 0
+    x, xh2, xhe, mu, f = atm.composition(np.array([-0.1, -0.2]), np.array([18.0, 44.0]), PL)
+    assert f & atm.FLAG_SUM_X and xh2 == 0.0 and xhe == 0.0
+
+
+def test_forward_isothermal_monotone_and_bounded():
+    s = wl.config1()
+    s.nu = s.nu[:40]
+    sigma = wl.random_opacity_table(1, s.temps, s.p_bar.size, s.nu, seed=5)
+    out = rt.forward(wl.config1_params(), s, sigma)
+    r = out["atm"]["radius"]
+    assert out["flags"] == 0
+    assert np.all(np.diff(out["tau"], axis=0) <= 0)
+    assert np.all(out["depth"] >= (r[0] / s.planet.rs_cm) ** 2)
+    assert np.all(out["depth"] <= (r[-1] / s.planet.rs_cm) ** 2)

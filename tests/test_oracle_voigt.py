@@ -1,0 +1,155 @@
+"""Pins of the oracle's line-shape and opacity arithmetic (Sec. 6.1.1, Eqs. 2-11)."""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate, optimize
+
+from oracle import opacity as op
+from workloads import LineList
+
+
+def test_voigt_gaussian_limit():
+    # gamma -> 0: V -> G (Eq. 2)
+    sig = 0.013
+    x = np.linspace(-5 * sig, 5 * sig, 101)
+    v = op.voigt(x, sig, 1e-12 * sig)
+    g = op.gaussian(x, sig)
+    assert np.max(np.abs(v - g) / g) < 1e-8
+
+
+def test_voigt_lorentzian_limit():
+    # sigma -> 0: V -> L (Eq. 3)
+    gam = 0.07
+    x = np.linspace(-20 * gam, 20 * gam, 101)
+    v = op.voigt(x, 1e-9 * gam, gam)
+    lz = op.lorentzian(x, gam)
+    assert np.max(np.abs(v - lz) / lz) < 1e-8
+
+
+@pytest.mark.parametrize("sig,gam,x", [(0.01, 0.002, 0.0), (0.01, 0.02, 0.013),
+                                       (0.03, 0.01, -0.09), (0.005, 0.05, 0.4)])
+def test_voigt_is_the_convolution(sig, gam, x):
+    # Eq. 10: V(nu) = int G(nu') L(nu - nu') dnu', evaluated by adaptive quadrature
+    f = lambda t: op.gaussian(t, sig) * op.lorentzian(x - t, gam)
+    val, _ = integrate.quad(f, -40 * sig, 40 * sig, points=[0.0, x], epsabs=0, epsrel=1e-12,
+                            limit=500)
+    assert op.voigt(np.array([x]), sig, gam)[0] == pytest.approx(val, rel=1e-9)
+
+
+def test_voigt_unit_area():
+    # the profile is normalised; the Lorentz tails beyond +-X carry 1 - (2/pi) atan(X/gamma)
+    sig, gam = 0.02, 0.01
+    X = 400.0
+    x = np.linspace(-X, X, 4_000_001)
+    area = np.trapezoid(op.voigt(x, sig, gam), x)
+    tail = 1.0 - 2.0 / math.pi * math.atan(X / gam)
+    assert area + tail == pytest.approx(1.0, abs=2e-7)
+
+
+@pytest.mark.parametrize("sig,gam", [(0.01, 0.0), (0.0, 0.05), (0.01, 0.01), (0.003, 0.03)])
+def test_voigt_hwhm_olivero(sig, gam):
+    # Olivero & Longbothum (1977) quote ~0.02 % accuracy against the true Voigt HWHM
+    hw = op.voigt_hwhm(sig, gam)
+    if gam == 0.0:
+        true = math.sqrt(2 * math.log(2)) * sig
+    elif sig == 0.0:
+        true = gam
+    else:
+        peak = op.voigt(np.array([0.0]), sig, gam)[0]
+        true = optimize.brentq(lambda x: op.voigt(np.array([x]), sig, gam)[0] - peak / 2,
+                               1e-9, 10 * (sig + gam), xtol=1e-15)
+    assert hw == pytest.approx(true, rel=2.5e-4)
+
+
+def test_line_strength_reference_temperature():
+    s = op.line_strength(np.array([1e-21]), np.array([2000.0]), np.array([1500.0]), 296.0)
+    assert s[0] == pytest.approx(1e-21, rel=1e-15)
+
+
+def test_line_strength_boltzmann_ratio():
+    # with nu0 large the stimulated-emission factor is ~1; ratio of two lines at the same
+    # nu0 differing in E'' by dE follows exp(-c2 dE (1/T - 1/296))
+    T = 1500.0
+    s = op.line_strength(np.array([1.0, 1.0]), np.array([4000.0, 4000.0]),
+                         np.array([0.0, 1000.0]), T)
+    assert s[1] / s[0] == pytest.approx(math.exp(-1.4387769 * 1000.0 * (1 / T - 1 / 296.0)),
+                                        rel=1e-13)
+
+
+def test_widths_reference_conditions():
+    assert op.lorentz_gamma(0.07, 296.0, 1.01325) == pytest.approx(0.07, rel=1e-15)
+    # textbook Doppler half width: HWHM = 3.581e-7 nu0 sqrt(T / M[amu])
+    sig = op.doppler_sigma(2000.0, 18.0, 296.0)
+    hw = math.sqrt(2 * math.log(2)) * sig
+    assert hw == pytest.approx(3.581e-7 * 2000.0 * math.sqrt(296.0 / 18.0), rel=2e-4)
+
+
+def _single_line(nu0=2000.1, s=1e-20, g=0.07, e=300.0, m=18.015):
+    return LineList(np.array([nu0]), np.array([s]), np.array([g]), np.array([e]),
+                    np.array([m]))
+
+
+def test_single_line_cell_is_strength_times_profile():
+    # f01oneline idea (Table 1): a one-line table equals S(T) V(nu - nu0) inside the window
+    ln = _single_line()
+    T, p = 1442.58, 0.33516          # the f04broadening layer (Sec. 6.1.1)
+    nu_start, dnu, n = 1990.0, 0.005, 4001
+    cell = op.cell_cross_section(ln, T, p, nu_start, dnu, n)
+    nu = nu_start + dnu * np.arange(n)
+    s_t = op.line_strength(ln.s296, ln.nu0, ln.elow, T)[0]
+    sig = op.doppler_sigma(ln.nu0, ln.mass_amu, T)[0]
+    gam = op.lorentz_gamma(ln.gamma296, T, p)[0]
+    hw = op.voigt_hwhm(sig, gam)
+    inside = np.abs(nu - ln.nu0[0]) <= 25 * hw
+    # reference from the convolution integral at a few points
+    for k in np.flatnonzero(inside)[:: max(1, inside.sum() // 7)]:
+        x = nu[k] - ln.nu0[0]
+        f = lambda t: op.gaussian(t, sig) * op.lorentzian(x - t, gam)
+        val, _ = integrate.quad(f, -40 * sig, 40 * sig, points=[0.0, x], epsabs=0,
+                                epsrel=1e-12, limit=500)
+        assert cell[k] == pytest.approx(s_t * val, rel=1e-8)
+    assert np.all(cell[~inside] == 0.0)
+    assert np.all(cell[inside] > 0.0)
+
+
+def test_two_lines_add():
+    # f06blending idea (Table 1): two lines ~0.04 cm^-1 apart sampled every 0.005 cm^-1
+    a = _single_line(nu0=2000.00)
+    b = _single_line(nu0=2000.04, s=3e-21, e=900.0)
+    both = LineList(*(np.concatenate([getattr(a, f), getattr(b, f)])
+                      for f in ("nu0", "s296", "gamma296", "elow", "mass_amu")))
+    args = (1000.0, 0.01, 1999.5, 0.005, 201)
+    ca = op.cell_cross_section(a, *args)
+    cb = op.cell_cross_section(b, *args)
+    cab = op.cell_cross_section(both, *args)
+    np.testing.assert_allclose(cab, ca + cb, rtol=1e-14, atol=0)
+
+
+def test_sampled_line_area_matches_truncated_profile():
+    # a Lorentz-dominated line on a fine grid integrates to S times the profile mass
+    # inside +-25 HWHM, which for a Lorentzian is (2/pi) atan(25 HWHM / gamma)
+    ln = _single_line(g=0.08)
+    T, p = 1000.0, 50.0
+    nu_start, dnu, n = 1800.0, 0.002, 200_001
+    cell = op.cell_cross_section(ln, T, p, nu_start, dnu, n)
+    s_t = op.line_strength(ln.s296, ln.nu0, ln.elow, T)[0]
+    sig = op.doppler_sigma(ln.nu0, ln.mass_amu, T)[0]
+    gam = op.lorentz_gamma(ln.gamma296, T, p)[0]
+    hw = op.voigt_hwhm(sig, gam)
+    expected = s_t * 2.0 / math.pi * math.atan(25 * hw / gam)
+    assert cell.sum() * dnu == pytest.approx(expected, rel=2e-4)
+
+
+def test_cell_matches_pointwise_sum():
+    # brute force point by point over a tiny random list equals the chunked cell routine
+    g = np.random.default_rng(7)
+    n = 40
+    ln = LineList(g.uniform(2000, 2010, n), 10 ** g.uniform(-25, -19, n),
+                  g.uniform(0.05, 0.1, n), g.uniform(0, 5000, n), g.uniform(18, 44, n))
+    T, p = 1700.0, 3.0
+    nu_start, dnu, nn = 1995.0, 0.05, 401
+    cell = op.cell_cross_section(ln, T, p, nu_start, dnu, nn, chunk=7)
+    for k in range(0, nn, 13):
+        assert cell[k] == pytest.approx(op.point_cross_section(ln, T, p, nu_start + dnu * k),
+                                        rel=1e-12, abs=1e-300)
