@@ -1,0 +1,309 @@
+"""Python binding of libbartmi, the MI355X transmission forward model.
+
+Argument marshalling only: every step of the forward model, the opacity build and the
+surrogate runs in the library's HIP kernels. PyTorch provides device memory and
+streams. The library must be built (``python -m paper_2104_12522_amd.build``); there
+is no fallback: importing works without it, but every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+from . import _abi
+from ._abi import (BM_OK, BM_F32, BM_F64, BM_FLAG_T_CLAMP, BM_FLAG_SUM_X, BM_FLAG_RADIUS,
+                   BM_FLAG_NONFINITE, BM_TP_ISOTHERMAL, BM_TP_LINE2013, BM_MAX_SPECIES,
+                   BmPlanet, BmModel)
+
+__all__ = [
+    "lib", "Model", "atmosphere", "extinction", "optical_depth", "transit_depth", "bin_chi2",
+    "forward_batch", "Forward", "opacity_table_build", "voigt", "BM_F32", "BM_F64",
+    "BM_FLAG_T_CLAMP", "BM_FLAG_SUM_X", "BM_FLAG_RADIUS", "BM_FLAG_NONFINITE",
+    "BM_TP_ISOTHERMAL", "BM_TP_LINE2013",
+]
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libbartmi.so")
+
+
+class BartmiError(RuntimeError):
+    pass
+
+
+def lib() -> C.CDLL:
+    return _abi.load(LIB_PATH)
+
+
+def _check(status: int, what: str) -> None:
+    if status != BM_OK:
+        msg = lib().bm_status_string(status).decode()
+        raise BartmiError(f"{what}: {msg} ({status})")
+
+
+def _stream(stream=None) -> C.c_void_p:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t: torch.Tensor | None) -> C.c_void_p:
+    if t is None:
+        return C.c_void_p(None)
+    if not t.is_cuda:
+        raise BartmiError("tensor must live on the GPU")
+    if not t.is_contiguous():
+        raise BartmiError("tensor must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+def _dtype_code(dt: torch.dtype) -> int:
+    if dt == torch.float32:
+        return BM_F32
+    if dt == torch.float64:
+        return BM_F64
+    raise BartmiError(f"unsupported dtype {dt}")
+
+
+def _dev(x, dtype=torch.float64, device="cuda") -> torch.Tensor:
+    if isinstance(x, torch.Tensor):
+        return x.to(device=device, dtype=dtype).contiguous()
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype, device=device)
+
+
+def planet_struct(planet) -> BmPlanet:
+    """A bm_planet from any object with the planet attributes (see workloads.Planet)."""
+    return BmPlanet(planet.rs_cm, planet.tstar, planet.rstar_cm, planet.a_cm, planet.tint,
+                    planet.g_nom, planet.r_nom_cm, planet.p_ref_bar, planet.h2_frac,
+                    planet.m_h2_amu, planet.m_he_amu)
+
+
+class Model:
+    """A forward-model instance: device tables and grids plus the bm_model struct that
+    borrows them. Keeps the tensors alive as long as the model is."""
+
+    def __init__(self, sigma: torch.Tensor, temps, p_bar, mass_amu, tp_mode: int, planet,
+                 cia: torch.Tensor | None = None, cia_temps=None, bin_width: int = 0,
+                 data=None, err=None, device="cuda"):
+        if sigma.dim() != 4:
+            raise BartmiError("sigma must be [S][NT][L][Nnu]")
+        self.sigma = sigma.to(device).contiguous()
+        self.dtype = self.sigma.dtype
+        S, NT, L, NNU = self.sigma.shape
+        self.temps = _dev(temps, device=device)
+        self.p_bar = _dev(p_bar, device=device)
+        self.cia = None if cia is None else cia.to(device=device, dtype=self.dtype).contiguous()
+        self.cia_temps = None if cia_temps is None else _dev(cia_temps, device=device)
+        self.data = None if data is None else _dev(data, device=device)
+        self.err = None if err is None else _dev(err, device=device)
+        self.planet = planet
+        st = BmModel()
+        st.dtype = _dtype_code(self.dtype)
+        st.n_species, st.n_temp, st.n_layers, st.n_nu = S, NT, L, NNU
+        st.n_temp_cia = 0 if self.cia is None else self.cia.shape[0]
+        st.tp_mode = tp_mode
+        st.bin_width = bin_width
+        st.sigma = _ptr(self.sigma)
+        st.temp = _ptr(self.temps)
+        st.cia = _ptr(self.cia)
+        st.temp_cia = _ptr(self.cia_temps)
+        st.p_bar = _ptr(self.p_bar)
+        st.data = _ptr(self.data)
+        st.err = _ptr(self.err)
+        m = np.zeros(BM_MAX_SPECIES)
+        m[:S] = np.asarray(mass_amu, dtype=np.float64)
+        for i in range(BM_MAX_SPECIES):
+            st.mass_amu[i] = float(m[i])
+        st.planet = planet_struct(planet)
+        self.struct = st
+
+    @property
+    def n_species(self):
+        return self.struct.n_species
+
+    @property
+    def n_layers(self):
+        return self.struct.n_layers
+
+    @property
+    def n_nu(self):
+        return self.struct.n_nu
+
+    @property
+    def n_params(self) -> int:
+        return lib().bm_n_params(C.byref(self.struct))
+
+    @property
+    def n_bins(self) -> int:
+        w = self.struct.bin_width
+        return self.n_nu // w if w > 0 else 0
+
+    def set_observation(self, data, err):
+        self.data = _dev(data, device=self.sigma.device)
+        self.err = _dev(err, device=self.sigma.device)
+        self.struct.data = _ptr(self.data)
+        self.struct.err = _ptr(self.err)
+
+
+# ------------------------------------------------------------------------------- steps
+def atmosphere(model: Model, params: torch.Tensor, stream=None):
+    """Steps a1-a2 for B samples: returns temp [B][L], n_species [B][S][L], n_h2 [B][L],
+    radius [B][L] (double) and flags [B] (int32)."""
+    params = _dev(params, device=model.sigma.device)
+    if params.dim() == 1:
+        params = params[None]
+    B, P = params.shape
+    L, S = model.n_layers, model.n_species
+    dev = params.device
+    temp = torch.empty(B, L, dtype=torch.float64, device=dev)
+    nsp = torch.empty(B, S, L, dtype=torch.float64, device=dev)
+    nh2 = torch.empty(B, L, dtype=torch.float64, device=dev)
+    rad = torch.empty(B, L, dtype=torch.float64, device=dev)
+    flags = torch.empty(B, dtype=torch.int32, device=dev)
+    _check(lib().bm_atmosphere(C.byref(model.struct), _ptr(params), P, B, _ptr(temp), _ptr(nsp),
+                               _ptr(nh2), _ptr(rad), _ptr(flags), _stream(stream)), "bm_atmosphere")
+    return dict(temp=temp, n_species=nsp, n_h2=nh2, radius=rad, flags=flags)
+
+
+def extinction(model: Model, temp, n_species, n_h2=None, stream=None):
+    """Step a3 for one atmosphere: ext [L][Nnu] in the model dtype, flags (int32 [1])."""
+    dev = model.sigma.device
+    temp = _dev(temp, device=dev)
+    n_species = _dev(n_species, device=dev)
+    n_h2 = None if n_h2 is None else _dev(n_h2, device=dev)
+    ext = torch.empty(model.n_layers, model.n_nu, dtype=model.dtype, device=dev)
+    flags = torch.zeros(1, dtype=torch.int32, device=dev)
+    _check(lib().bm_extinction(C.byref(model.struct), _ptr(temp), _ptr(n_species), _ptr(n_h2),
+                               _ptr(ext), _ptr(flags), _stream(stream)), "bm_extinction")
+    return ext, flags
+
+
+def optical_depth(radius, ext: torch.Tensor, stream=None) -> torch.Tensor:
+    """Step a4: tau [L][Nnu] from radii [L] and extinction [L][Nnu]."""
+    radius = _dev(radius, device=ext.device)
+    ext = ext.contiguous()
+    L, N = ext.shape
+    tau = torch.empty_like(ext)
+    _check(lib().bm_optical_depth(_ptr(radius), _ptr(ext), L, N, _dtype_code(ext.dtype), _ptr(tau),
+                                  _stream(stream)), "bm_optical_depth")
+    return tau
+
+
+def transit_depth(radius, tau: torch.Tensor, rs_cm: float, stream=None) -> torch.Tensor:
+    """Step a5: depth [Nnu] (double)."""
+    radius = _dev(radius, device=tau.device)
+    tau = tau.contiguous()
+    L, N = tau.shape
+    depth = torch.empty(N, dtype=torch.float64, device=tau.device)
+    _check(lib().bm_transit_depth(_ptr(radius), _ptr(tau), L, N, _dtype_code(tau.dtype),
+                                  C.c_double(rs_cm), _ptr(depth), _stream(stream)), "bm_transit_depth")
+    return depth
+
+
+def bin_chi2(depth: torch.Tensor, bin_width: int, data=None, err=None, stream=None):
+    """Step a6: binned [B][Nnu/w] and chi2 [B] (None without data)."""
+    if depth.dim() == 1:
+        depth = depth[None]
+    depth = depth.contiguous()
+    B, N = depth.shape
+    nb = N // bin_width
+    binned = torch.empty(B, nb, dtype=torch.float64, device=depth.device)
+    chi2 = None
+    if data is not None:
+        data = _dev(data, device=depth.device)
+        err = _dev(err, device=depth.device)
+        chi2 = torch.empty(B, dtype=torch.float64, device=depth.device)
+    _check(lib().bm_bin_chi2(_ptr(depth), B, N, bin_width, _ptr(data), _ptr(err), _ptr(binned),
+                             _ptr(chi2), _stream(stream)), "bm_bin_chi2")
+    return binned, chi2
+
+
+# ------------------------------------------------------------------------------- fused
+class Forward:
+    """Reusable fused forward model (steps a1-a6) for a fixed batch layout: owns the
+    workspace and output buffers so repeated calls allocate nothing."""
+
+    def __init__(self, models, batch: int, instance=None, binned: bool = False,
+                 chi2: bool = False, device="cuda"):
+        self.models = list(models) if isinstance(models, (list, tuple)) else [models]
+        n = len(self.models)
+        self._structs = (BmModel * n)(*[m.struct for m in self.models])
+        self.B = batch
+        if instance is None:
+            self._inst = None
+            inst = [0] * batch
+        else:
+            inst = [int(i) for i in instance]
+            if len(inst) != batch:
+                raise BartmiError("instance must have one entry per sample")
+            self._inst = (C.c_int32 * batch)(*inst)
+        self.instance = inst
+        self.n_nu = [self.models[i].n_nu for i in inst]
+        self.n_bins = [self.models[i].n_bins for i in inst]
+        self.depth_off = np.concatenate([[0], np.cumsum(self.n_nu)]).astype(np.int64)
+        self.bin_off = np.concatenate([[0], np.cumsum(self.n_bins)]).astype(np.int64)
+        ws = lib().bm_workspace_size(self._structs, n, self._inst, batch)
+        if ws == 0 and batch > 0:
+            raise BartmiError("bm_workspace_size rejected the models / batch")
+        self.workspace = torch.zeros(max(int(ws), 256), dtype=torch.uint8, device=device)
+        self.depth = torch.empty(int(self.depth_off[-1]), dtype=torch.float64, device=device)
+        self.binned = (torch.empty(int(self.bin_off[-1]), dtype=torch.float64, device=device)
+                       if (binned or chi2) else None)
+        self.chi2 = torch.empty(batch, dtype=torch.float64, device=device) if chi2 else None
+        self.flags = torch.empty(batch, dtype=torch.int32, device=device)
+        self.param_stride = max(m.n_params for m in self.models)
+
+    def __call__(self, params: torch.Tensor, stream=None):
+        if params.shape[0] != self.B or params.dtype != torch.float64 or not params.is_contiguous():
+            raise BartmiError("params must be a contiguous float64 [B][P] device tensor")
+        _check(lib().bm_forward_batch(self._structs, len(self.models), self._inst, _ptr(params),
+                                      params.shape[1], self.B, _ptr(self.depth), _ptr(self.binned),
+                                      _ptr(self.chi2), _ptr(self.flags), _ptr(self.workspace),
+                                      C.c_size_t(self.workspace.numel()), _stream(stream)),
+               "bm_forward_batch")
+        return self
+
+    def spectrum(self, b: int) -> torch.Tensor:
+        return self.depth[self.depth_off[b]:self.depth_off[b + 1]]
+
+    def binned_spectrum(self, b: int) -> torch.Tensor:
+        return self.binned[self.bin_off[b]:self.bin_off[b + 1]]
+
+
+def forward_batch(models, params: torch.Tensor, instance=None, binned=False, chi2=False,
+                  stream=None) -> Forward:
+    params = _dev(params)
+    if params.dim() == 1:
+        params = params[None]
+    f = Forward(models, params.shape[0], instance, binned=binned, chi2=chi2, device=params.device)
+    return f(params, stream)
+
+
+# ------------------------------------------------------------------------------- opacity
+def opacity_table_build(lines, temps, p_bar, nu_start: float, dnu: float, n_nu: int,
+                        cutoff_hwhm: float = 25.0, dtype=torch.float32, device="cuda",
+                        out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Cross-section table [NT][NP][Nnu] of one species. ``lines`` has attributes nu0,
+    s296, gamma296, elow, mass_amu (numpy or torch, sorted by nu0)."""
+    arrs = [_dev(getattr(lines, f), device=device) for f in
+            ("nu0", "s296", "gamma296", "elow", "mass_amu")]
+    n = int(arrs[0].numel())
+    temps = np.ascontiguousarray(np.asarray(temps, dtype=np.float64))
+    p_bar = np.ascontiguousarray(np.asarray(p_bar, dtype=np.float64))
+    if out is None:
+        out = torch.empty(len(temps), len(p_bar), n_nu, dtype=dtype, device=device)
+    dp = C.POINTER(C.c_double)
+    _check(lib().bm_opacity_table_build(*[_ptr(a) for a in arrs], n, temps.ctypes.data_as(dp),
+                                        len(temps), p_bar.ctypes.data_as(dp), len(p_bar),
+                                        C.c_double(nu_start), C.c_double(dnu), n_nu,
+                                        C.c_double(cutoff_hwhm), _dtype_code(out.dtype),
+                                        _ptr(out), _stream(stream)), "bm_opacity_table_build")
+    return out
+
+
+def voigt(x: torch.Tensor, sigma: float, gamma: float, stream=None) -> torch.Tensor:
+    x = _dev(x)
+    out = torch.empty_like(x)
+    _check(lib().bm_voigt(_ptr(x), x.numel(), C.c_double(sigma), C.c_double(gamma), _ptr(out),
+                          _stream(stream)), "bm_voigt")
+    return out

@@ -1,0 +1,72 @@
+"""ctypes declarations mirroring include/bartmi.h."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+BM_OK, BM_EINVAL, BM_ESHAPE, BM_EHIP, BM_ENOSPACE = 0, -1, -2, -3, -4
+BM_F32, BM_F64 = 0, 1
+BM_FLAG_T_CLAMP, BM_FLAG_SUM_X, BM_FLAG_RADIUS, BM_FLAG_NONFINITE = 1, 2, 4, 8
+BM_TP_ISOTHERMAL, BM_TP_LINE2013 = 0, 1
+BM_MAX_SPECIES, BM_MAX_LAYERS, BM_MAX_TEMPS = 8, 256, 64
+
+
+class BmPlanet(C.Structure):
+    _fields_ = [(n, C.c_double) for n in (
+        "rs_cm", "tstar", "rstar_cm", "a_cm", "tint", "g_nom", "r_nom_cm", "p_ref_bar",
+        "h2_frac", "m_h2_amu", "m_he_amu")]
+
+
+class BmModel(C.Structure):
+    _fields_ = [
+        ("dtype", C.c_int32), ("n_species", C.c_int32), ("n_temp", C.c_int32),
+        ("n_layers", C.c_int32), ("n_nu", C.c_int32), ("n_temp_cia", C.c_int32),
+        ("tp_mode", C.c_int32), ("bin_width", C.c_int32),
+        ("sigma", C.c_void_p), ("temp", C.c_void_p), ("cia", C.c_void_p),
+        ("temp_cia", C.c_void_p), ("p_bar", C.c_void_p), ("data", C.c_void_p),
+        ("err", C.c_void_p),
+        ("mass_amu", C.c_double * BM_MAX_SPECIES),
+        ("planet", BmPlanet),
+    ]
+
+
+_VP = C.c_void_p
+_I = C.c_int
+_D = C.c_double
+_I64 = C.c_int64
+_PM = C.POINTER(BmModel)
+
+PROTOTYPES = {
+    "bm_status_string": (C.c_char_p, [_I]),
+    "bm_version": (_I, []),
+    "bm_n_params": (_I, [_PM]),
+    "bm_atmosphere": (_I, [_PM, _VP, _I, _I, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "bm_extinction": (_I, [_PM, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "bm_optical_depth": (_I, [_VP, _VP, _I, _I, _I, _VP, _VP]),
+    "bm_transit_depth": (_I, [_VP, _VP, _I, _I, _I, _D, _VP, _VP]),
+    "bm_bin_chi2": (_I, [_VP, _I, _I, _I, _VP, _VP, _VP, _VP, _VP]),
+    "bm_workspace_size": (C.c_size_t, [_PM, _I, C.POINTER(C.c_int32), _I]),
+    "bm_forward_batch": (_I, [_PM, _I, C.POINTER(C.c_int32), _VP, _I, _I, _VP, _VP, _VP, _VP, _VP,
+                              C.c_size_t, _VP]),
+    "bm_opacity_table_build": (_I, [_VP, _VP, _VP, _VP, _VP, _I64, C.POINTER(C.c_double), _I,
+                                    C.POINTER(C.c_double), _I, _D, _D, _I, _D, _I, _VP, _VP]),
+    "bm_voigt": (_I, [_VP, _I64, _D, _D, _VP, _VP]),
+}
+
+_cache: dict[str, C.CDLL] = {}
+
+
+def load(path: str) -> C.CDLL:
+    if path in _cache:
+        return _cache[path]
+    if not os.path.exists(path):
+        raise RuntimeError(
+            f"{path} is missing: build the HIP library first "
+            "(python -m paper_2104_12522_amd.build); there is no fallback")
+    lib = C.CDLL(path)
+    for name, (res, args) in PROTOTYPES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _cache[path] = lib
+    return lib

@@ -1,0 +1,85 @@
+"""The C-ABI library loads and exports every function include/bartmi.h declares; the host
+logic that needs no GPU (status strings, argument and shape validation) behaves as
+documented. No compute calls: these run without a GPU."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bartmi.h")
+LIB = os.path.join(ROOT, "paper_2104_12522_amd", "libbartmi.so")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(bm_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        import paper_2104_12522_amd.build as b
+        b.build()
+    return C.CDLL(LIB)
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for required in ("bm_opacity_table_build", "bm_extinction", "bm_optical_depth",
+                     "bm_transit_depth", "bm_forward_batch", "bm_atmosphere", "bm_bin_chi2",
+                     "bm_workspace_size"):
+        assert required in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    missing = [n for n in _declared() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_prototypes_cover_header():
+    from paper_2104_12522_amd import _abi
+    assert set(_declared()) <= set(_abi.PROTOTYPES)
+
+
+def test_status_strings_and_version(lib):
+    lib.bm_status_string.restype = C.c_char_p
+    assert lib.bm_status_string(0) == b"ok"
+    assert b"shape" in lib.bm_status_string(-2)
+    assert lib.bm_version() >= 100
+
+
+def test_shape_errors_return_before_any_gpu_work(lib):
+    # these argument checks happen on the host and must not touch the GPU
+    VP = C.c_void_p
+    dummy = VP(16)
+    assert lib.bm_optical_depth(dummy, dummy, 1, 10, 0, dummy, None) == -2       # L < 2
+    assert lib.bm_optical_depth(dummy, dummy, 300, 10, 0, dummy, None) == -2     # L > 256
+    assert lib.bm_optical_depth(None, dummy, 10, 10, 0, dummy, None) == -1
+    assert lib.bm_optical_depth(dummy, dummy, 10, 10, 7, dummy, None) == -1      # bad dtype
+    lib.bm_transit_depth.argtypes = [VP, VP, C.c_int, C.c_int, C.c_int, C.c_double, VP, VP]
+    assert lib.bm_transit_depth(dummy, dummy, 10, 10, 0, -1.0, dummy, None) == -1
+    assert lib.bm_bin_chi2(dummy, 1, 10, 0, None, None, dummy, None, None) == -2
+    assert lib.bm_bin_chi2(dummy, 1, 5, 10, None, None, dummy, None, None) == -2  # no full bin
+
+
+def test_model_validation(lib):
+    from paper_2104_12522_amd._abi import BmModel
+    m = BmModel()
+    m.dtype, m.n_species, m.n_temp, m.n_layers, m.n_nu = 0, 4, 20, 100, 1000
+    m.tp_mode = 1
+    m.p_bar = C.c_void_p(64)
+    lib.bm_n_params.argtypes = [C.POINTER(BmModel)]
+    assert lib.bm_n_params(C.byref(m)) == 10
+    lib.bm_workspace_size.restype = C.c_size_t
+    lib.bm_workspace_size.argtypes = [C.POINTER(BmModel), C.c_int, C.c_void_p, C.c_int]
+    assert lib.bm_workspace_size(C.byref(m), 1, None, 4) == 0        # no tables: rejected
+    m.sigma = C.c_void_p(64)
+    m.temp = C.c_void_p(64)
+    one = lib.bm_workspace_size(C.byref(m), 1, None, 1)
+    assert one > 100 * 100 * 4                                      # holds the chord weights
+    assert lib.bm_workspace_size(C.byref(m), 1, None, 7) == 7 * one
+    m.n_species = 9
+    assert lib.bm_workspace_size(C.byref(m), 1, None, 1) == 0

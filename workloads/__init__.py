@@ -68,7 +68,7 @@ class LineList:
 
 def line_list(n_lines: int, seed: int, nu_min: float = 1000.0, nu_max: float = 5000.0,
               mass_amu: float | None = 18.015, mass_range=(18.0, 44.0)) -> LineList:
-    """Synthetic line list: centres U[nu_min, nu_max], log10 S U[-25,-19],
+    """Synthetic line list sorted by centre: centres U[nu_min, nu_max], log10 S U[-25,-19],
     Lorentz HWHM U[0.05, 0.1] cm^-1, E'' U[0, 5000] cm^-1. ``mass_amu=None``
     draws a per-line mass U[mass_range] (the opacity-build stress case)."""
     g = rng(seed)
@@ -80,7 +80,8 @@ def line_list(n_lines: int, seed: int, nu_min: float = 1000.0, nu_max: float = 5
         mass = g.uniform(mass_range[0], mass_range[1], n_lines)
     else:
         mass = np.full(n_lines, float(mass_amu))
-    return LineList(nu0, s296, gam, elow, mass)
+    order = np.argsort(nu0, kind="stable")   # line lists are distributed sorted by centre
+    return LineList(nu0[order], s296[order], gam[order], elow[order], mass[order])
 
 
 # --------------------------------------------------------------------------------------
@@ -97,24 +98,25 @@ def cia_table(temps: np.ndarray, nu: np.ndarray) -> np.ndarray:
 
 
 def random_opacity_table(n_species: int, temps: np.ndarray, n_layers: int, nu: np.ndarray,
-                         seed: int, line_density: float = 0.02) -> np.ndarray:
+                         seed: int, line_density: float = 0.02, dtype=np.float64) -> np.ndarray:
     """Cross-section table [S][NT][L][Nnu] (cm^2/molecule) with line-like spikes on a
     continuum, smooth in T and in pressure. Used where the forward model needs a table
     that neither the GPU nor the oracle produced (forward-model parity at full size)."""
     g = rng(seed)
     nT, nnu = len(temps), len(nu)
-    out = np.empty((n_species, nT, n_layers, nnu), dtype=np.float64)
-    tnorm = (np.asarray(temps) - temps[0]) / max(temps[-1] - temps[0], 1.0)
-    lay = np.linspace(0.0, 1.0, n_layers)
+    out = np.empty((n_species, nT, n_layers, nnu), dtype=dtype)
+    tnorm = ((np.asarray(temps, dtype=np.float64) - temps[0])
+             / max(temps[-1] - temps[0], 1.0)).astype(dtype)
+    lay = np.linspace(0.0, 1.0, n_layers, dtype=dtype)
     for s in range(n_species):
-        base = 10.0 ** g.uniform(-27.0, -24.0, nnu)            # continuum-ish, per nu
-        spikes = (g.random(nnu) < line_density) * 10.0 ** g.uniform(-22.0, -19.0, nnu)
-        tdep = 0.5 + g.random(nnu)                              # per-nu temperature slope
-        pdep = 0.3 + 0.7 * g.random(nnu)                        # per-nu pressure smoothing
+        base = (10.0 ** g.uniform(-27.0, -24.0, nnu)).astype(dtype)       # continuum, per nu
+        spikes = ((g.random(nnu) < line_density)
+                  * 10.0 ** g.uniform(-22.0, -19.0, nnu)).astype(dtype)
+        tdep = (0.5 + g.random(nnu)).astype(dtype)                         # per-nu T slope
+        pdep = (0.3 + 0.7 * g.random(nnu)).astype(dtype)                   # per-nu p smoothing
+        prof = base[None, :] + spikes[None, :] * (1 - 0.5 * pdep[None, :] * lay[:, None])
         for it in range(nT):
-            fac_t = (1.0 + tdep * tnorm[it])
-            for l in range(n_layers):
-                out[s, it, l] = (base + spikes * (1.0 - 0.5 * pdep * lay[l])) * fac_t
+            out[s, it] = prof * (1 + tdep * tnorm[it])[None, :]
     return out
 
 
