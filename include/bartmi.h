@@ -23,7 +23,7 @@
  *    cm^5/molecule^2 for collision-induced absorption, cm^-1 for extinction; pressures
  *    in bar.
  *  - `dtype` (BM_F32 or BM_F64) is the element type of opacity tables, extinction and
- *    optical depth. Transit depths, radii, temperatures and densities are always
+ *    optical depth (CIA tables are always double). Transit depths, radii, temperatures and densities are always
  *    double. Geometry (radii, chord lengths) is computed in double; in BM_F32 mode the
  *    chord weights are rounded once to float and the impact-parameter integral is
  *    accumulated in double.
@@ -95,7 +95,7 @@ typedef struct bm_planet {
 /* A forward-model instance: tables, grids, observation and constants. Pointers are
  * borrowed. One call may mix up to 4 distinct models (all of one dtype). */
 typedef struct bm_model {
-    int32_t dtype;        /* BM_F32 or BM_F64: element type of sigma and cia              */
+    int32_t dtype;        /* BM_F32 or BM_F64: element type of sigma                        */
     int32_t n_species;    /* S, 1..BM_MAX_SPECIES                                          */
     int32_t n_temp;       /* NT, 2..BM_MAX_TEMPS, temperatures of the opacity tables       */
     int32_t n_layers;     /* L, 2..BM_MAX_LAYERS                                           */
@@ -105,7 +105,8 @@ typedef struct bm_model {
     int32_t bin_width;    /* channel width in wavenumber points for binning; 0 = none      */
     const void* sigma;    /* device [S][NT][L][Nnu] cross sections on the layer pressures  */
     const double* temp;   /* device [NT], strictly increasing                               */
-    const void* cia;      /* device [NTc][Nnu] H2-H2 CIA coefficient, or NULL               */
+    const double* cia;    /* device [NTc][Nnu] H2-H2 CIA coefficient, or NULL. Always double:
+                             values ~1e-45 cm^5/molecule^2 are not representable in float */
     const double* temp_cia; /* device [NTc], strictly increasing, or NULL                   */
     const double* p_bar;  /* device [L], layer pressures, strictly decreasing               */
     const double* data;   /* device [Nnu/bin_width] observed channel depths, or NULL        */

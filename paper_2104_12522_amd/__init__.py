@@ -92,7 +92,8 @@ class Model:
         S, NT, L, NNU = self.sigma.shape
         self.temps = _dev(temps, device=device)
         self.p_bar = _dev(p_bar, device=device)
-        self.cia = None if cia is None else cia.to(device=device, dtype=self.dtype).contiguous()
+        # CIA coefficients (~1e-45 cm^5/molecule^2) are kept in double whatever the dtype
+        self.cia = None if cia is None else _dev(cia, device=device)
         self.cia_temps = None if cia_temps is None else _dev(cia_temps, device=device)
         self.data = None if data is None else _dev(data, device=device)
         self.err = None if err is None else _dev(err, device=device)

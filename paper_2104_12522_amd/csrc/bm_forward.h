@@ -5,17 +5,38 @@
 
 namespace bm {
 
-constexpr int kAtmThreads = BM_MAX_LAYERS;  // one thread per layer in the atmosphere kernels
-constexpr int kRows = 8;                    // chord-weight rows per register block
+constexpr int kAtmThreads = BM_MAX_LAYERS;  // threads for one-sample atmosphere work (>= L)
+constexpr int kPrepThreads = 1024;          // record-preparation workgroup
+constexpr int kRows = 8;                    // chord-weight rows per register block (FP64 path)
 constexpr int kTileNu = kWave;              // wavenumbers per forward workgroup (one per lane)
 constexpr int kMaxModels = 4;               // distinct models in one fused launch
 constexpr int kMaxSegments = 16;            // runs of same-model samples in one launch
+
+// FP32 chord contraction on the matrix cores: v_mfma_f32_16x16x4f32 multiplies a 16x4
+// block of chord weights (rows j, layers l) by a 4x16 block of extinction (layers l,
+// wavenumbers). Row block J holds rows [16J, 16J+16) and runs over layers [16J, L).
+// The k-steps of a row block are padded with zero weights to a multiple of kMfmaChunk.
+constexpr int kMfmaM = 16;
+constexpr int kMfmaK = 4;
+constexpr int kMfmaChunk = 4;
+
+__host__ __device__ inline int mfma_row_blocks(int L) { return (L - 1 + kMfmaM - 1) / kMfmaM; }
+__host__ __device__ inline int mfma_ksteps(int L, int J) {
+    const int raw = (L - kMfmaM * J + kMfmaK - 1) / kMfmaK;
+    return (raw + kMfmaChunk - 1) / kMfmaChunk * kMfmaChunk;
+}
+__host__ __device__ inline int mfma_kstep_offset(int L, int J) {
+    int o = 0;
+    for (int i = 0; i < J; ++i) o += mfma_ksteps(L, i);
+    return o;
+}
+__host__ __device__ inline int mfma_total_ksteps(int L) { return mfma_kstep_offset(L, mfma_row_blocks(L)); }
 
 // Device view of a bm_model (passed by value in kernel arguments).
 struct ModelDev {
     const void* sigma;
     const double* temp;
-    const void* cia;
+    const double* cia;
     const double* temp_cia;
     const double* p_bar;
     const double* data;
@@ -28,11 +49,13 @@ struct ModelDev {
 // A run of consecutive samples that use the same model.
 struct Segment {
     int model;
-    int first;           // first sample index
+    int first;           // first sample index (relative to the launch)
     int count;           // samples in the run
     int tiles;           // wavenumber tiles per sample
-    int tile_begin;      // first global tile index of the run
-    int pad;
+    int tile_begin;      // first workgroup index of the run
+    int tiles_per_xcd;   // tiles owned by each XCD (tile-major, XCD-aware order)
+    int tile_w;          // wavenumbers per tile (a whole number of channels when binning)
+    int fused_bins;      // 1: each tile bins its own channels; 0: no binning in the kernel
     size_t ws_off;       // byte offset of the run's first record in the workspace
     size_t rec_bytes;    // bytes per sample record
     size_t depth_off;    // offset (elements) of the run's first spectrum in `depth`
@@ -43,20 +66,30 @@ struct LaunchPlan {
     ModelDev model[kMaxModels];
     Segment seg[kMaxSegments];
     int n_seg;
-    int total_tiles;
+    int total_wgs;
+    int max_ntc;   // largest CIA temperature grid among the models (LDS staging rows)
     __device__ int segment_of_sample(int b) const {
         int s = 0;
         for (int i = 1; i < n_seg; ++i)
             if (b >= seg[i].first) s = i;
         return s;
     }
-    __device__ int segment_of_tile(int t) const {
+    __device__ int segment_of_wg(int t) const {
         int s = 0;
         for (int i = 1; i < n_seg; ++i)
             if (t >= seg[i].tile_begin) s = i;
         return s;
     }
 };
+
+// Workgroups of a segment: count * 8 * tiles_per_xcd. Workgroup g (local index) runs on
+// XCD g % 8 (round-robin dispatch); the k-th workgroup of an XCD takes tile
+// xcd * tiles_per_xcd + k / count of sample k % count, so each XCD sweeps a contiguous
+// wavenumber range and all samples of one tile run back to back on the same L2.
+constexpr int kXcds = 8;
+__host__ __device__ inline int segment_wgs(int count, int tiles) {
+    return count * kXcds * ((tiles + kXcds - 1) / kXcds);
+}
 
 struct RecordHeader {
     double base;     // r_0^2
@@ -69,6 +102,13 @@ struct RecordHeader {
 inline __host__ __device__ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 inline __host__ __device__ int row_blocks(int L) { return (L + kRows - 1) / kRows; }
 
+// chord-weight entries of one sample: MFMA A fragments (FP32) or 8-row blocks (FP64)
+template <typename T>
+__host__ __device__ inline size_t chord_weight_entries(int L) {
+    if (sizeof(T) == 4) return (size_t)mfma_total_ksteps(L) * kWave;
+    return (size_t)row_blocks(L) * L * kRows;
+}
+
 // Byte layout of one sample record for compute type T.
 template <typename T>
 struct RecordLayout {
@@ -79,11 +119,11 @@ struct RecordLayout {
         kidx = o;  o = align_up(o + sizeof(int32_t) * L, 64);
         kcidx = o; o = align_up(o + sizeof(int32_t) * L, 64);
         w = o;     o = align_up(o + sizeof(T) * L, 64);
-        wc = o;    o = align_up(o + sizeof(T) * L, 64);
-        bfac = o;  o = align_up(o + sizeof(T) * L, 64);
+        wc = o;    o = align_up(o + sizeof(double) * L, 64);
+        bfac = o;  o = align_up(o + sizeof(double) * L, 64);
         afac = o;  o = align_up(o + sizeof(T) * L * S, 64);
         cw = o;    o = align_up(o + sizeof(double) * L, 64);
-        wb = o;    o = align_up(o + sizeof(T) * (size_t)row_blocks(L) * L * kRows, 256);
+        wb = o;    o = align_up(o + sizeof(T) * chord_weight_entries<T>(L), 256);
         total = o;
     }
 };
@@ -94,26 +134,32 @@ struct RecordView {
     int32_t* kidx;
     int32_t* kcidx;
     T* w;
-    T* wc;
-    T* bfac;
-    T* afac;   // [S][L]
-    double* cw;
-    T* wb;     // [nb][L][kRows]
-    int nb;
+    double* wc;    // CIA interpolation weight
+    double* bfac;  // n_H2^2 (overflows float: the CIA term is formed in double)
+    T* afac;       // [S][L] absorber number densities
+    double* cw;    // impact-parameter weight of f_j
+    T* wb;         // chord weights (layout: chord_weight_entries)
+    double* chi2part;  // [tiles] chi^2 of each tile's channels (after the fixed layout)
     __host__ __device__ RecordView(char* base, int S, int L) {
         RecordLayout<T> lay(S, L);
         hdr = (RecordHeader*)(base + lay.hdr);
         kidx = (int32_t*)(base + lay.kidx);
         kcidx = (int32_t*)(base + lay.kcidx);
         w = (T*)(base + lay.w);
-        wc = (T*)(base + lay.wc);
-        bfac = (T*)(base + lay.bfac);
+        wc = (double*)(base + lay.wc);
+        bfac = (double*)(base + lay.bfac);
         afac = (T*)(base + lay.afac);
         cw = (double*)(base + lay.cw);
         wb = (T*)(base + lay.wb);
-        nb = row_blocks(L);
+        chi2part = (double*)(base + lay.total);
     }
 };
+
+// bytes of one sample record including the per-tile chi^2 partials
+template <typename T>
+__host__ __device__ inline size_t record_bytes_t(int S, int L, int tiles) {
+    return RecordLayout<T>(S, L).total + align_up(sizeof(double) * (size_t)tiles, 256);
+}
 
 // host helpers (forward.hip)
 int validate_model(const bm_model& m, bool need_tables);

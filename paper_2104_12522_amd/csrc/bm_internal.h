@@ -30,50 +30,90 @@ constexpr int kWave = 64;
     } while (0)
 
 // ---- E2 exponential integral -------------------------------------------------------------
-// E1 by its power series for x <= 1 (Abramowitz & Stegun 5.1.11) and E_n by the even
-// continued fraction for x > 1 (A&S 5.1.22), evaluated backwards at fixed depth.
-__host__ __device__ inline double expint_e2(double x) {
-    if (x <= 0.0) return 1.0;
-    if (x <= 1.0) {
-        // E1(x) = -gamma - ln x - sum_{k>=1} (-x)^k / (k k!)
-        double term = 1.0, sum = 0.0;
+// x <= 2.5: E2 = e^-x - x E1, E1 by its power series (Abramowitz & Stegun 5.1.11),
+//           E1(x) = -gamma - ln x - sum_{k>=1} (-x)^k / (k k!), 24 terms in Horner form;
+// x >  2.5: E2 by the even continued fraction (A&S 5.1.22),
+//           E2 = e^-x / (x + 2 - 1*2 / (x + 4 - 2*3 / (x + 6 - ...))),
+//           through its convergents P_n / Q_n (three-term recurrence, one division) at
+//           depth 8 + 75/x (about 1e-14 relative).
+struct E1SeriesCoef {
+    double c[24];  // c[k-1] = (-1)^k / (k k!)
+    constexpr E1SeriesCoef() : c() {
+        double fact = 1.0;
         for (int k = 1; k <= 24; ++k) {
-            term *= -x / k;
-            sum += term / k;
+            fact *= k;
+            c[k - 1] = ((k & 1) ? -1.0 : 1.0) / (k * fact);
         }
-        double e1 = -kEulerGamma - log(x) - sum;
-        return exp(-x) - x * e1;  // E2 = e^-x - x E1
     }
-    // E_2(x) = e^-x / (x + 2 - 1*2 / (x + 4 - 2*3 / (x + 6 - ...)))
-    const int depth = 60;
-    double t = x + 2.0 + 2.0 * depth;
-    for (int m = depth; m >= 1; --m) {
-        t = x + 2.0 + 2.0 * (m - 1) - (double)m * (double)(m + 1) / t;
+};
+
+// ex = exp(-x) supplied by the caller (it is shared with the profile's other term)
+__host__ __device__ inline double expint_e2_ex(double x, double ex) {
+    if (x <= 0.0) return 1.0;
+    if (x <= 2.5) {
+        constexpr E1SeriesCoef cs;
+        double s = cs.c[23];
+        for (int k = 22; k >= 0; --k) s = fma(s, x, cs.c[k]);
+        s *= x;  // sum_{k>=1} c_k x^k
+        double e1 = -kEulerGamma - log(x) - s;
+        return ex - x * e1;
     }
-    return exp(-x) / t;
+    // denominator b_1 - a_2/(b_2 - a_3/(...)), b_m = x + 2m, a_m = (m-1) m
+    const int depth = 8 + (int)(75.0 / x);
+    double p0 = 1.0, p1 = x + 2.0, q0 = 0.0, q1 = 1.0;
+    for (int m = 2; m <= depth; ++m) {
+        const double bm = x + 2.0 * m, am = (double)(m - 1) * m;
+        const double p2 = bm * p1 - am * p0, q2 = bm * q1 - am * q0;
+        p0 = p1; p1 = p2; q0 = q1; q1 = q2;
+    }
+    return ex * q1 / p1;
 }
+
+__host__ __device__ inline double expint_e2(double x) { return expint_e2_ex(x, exp(-x)); }
+
+__host__ __device__ inline double pow10_(double x) { return exp2(x * 3.32192809488736234787); }
 
 // ---- Line et al. (2013) five-parameter temperature profile ------------------------------
-__host__ __device__ inline double line2013_xi(double gamma, double tau) {
-    double gt = gamma * tau;
-    return 2.0 / 3.0 + 2.0 / (3.0 * gamma) * (1.0 + (gt * 0.5 - 1.0) * exp(-gt)) +
-           2.0 * gamma / 3.0 * (1.0 - tau * tau * 0.5) * expint_e2(gt);
+// Per-sample constants of the profile, evaluated once per sample.
+struct Line2013Consts {
+    double kappa_over_g;   // kappa / g_nom
+    double g1, g2;         // gamma_1, gamma_2
+    double alpha;
+    double tirr4, tint4;   // T_irr^4, T_int^4
+};
+
+__host__ __device__ inline Line2013Consts line2013_consts(const double* tp, const bm_planet& pl) {
+    Line2013Consts c;
+    c.kappa_over_g = pow10_(tp[0]) / pl.g_nom;
+    c.g1 = pow10_(tp[1]);
+    c.g2 = pow10_(tp[2]);
+    c.alpha = tp[3];
+    const double tirr = tp[4] * sqrt(pl.rstar_cm / (2.0 * pl.a_cm)) * pl.tstar;
+    c.tirr4 = (tirr * tirr) * (tirr * tirr);
+    c.tint4 = (pl.tint * pl.tint) * (pl.tint * pl.tint);
+    return c;
 }
 
-__host__ __device__ inline double line2013_temperature(double p_bar, const double* tp,
-                                                       const bm_planet& pl) {
-    double kappa = pow(10.0, tp[0]);
-    double g1 = pow(10.0, tp[1]);
-    double g2 = pow(10.0, tp[2]);
-    double alpha = tp[3], beta = tp[4];
-    double tau = kappa * (p_bar * kBar) / pl.g_nom;
-    double tirr = beta * sqrt(pl.rstar_cm / (2.0 * pl.a_cm)) * pl.tstar;
-    double tirr4 = tirr * tirr * tirr * tirr;
-    double tint4 = pl.tint * pl.tint * pl.tint * pl.tint;
-    double t4 = 0.75 * tint4 * (2.0 / 3.0 + tau) +
-                0.75 * tirr4 * (1.0 - alpha) * line2013_xi(g1, tau) +
-                0.75 * tirr4 * alpha * line2013_xi(g2, tau);
+// xi(gamma, tau) = 2/3 + 2/(3 gamma) [1 + (gamma tau / 2 - 1) e^{-gamma tau}]
+//                  + (2 gamma / 3)(1 - tau^2 / 2) E2(gamma tau)
+__host__ __device__ inline double line2013_xi(double gamma, double tau) {
+    const double gt = gamma * tau;
+    const double ex = exp(-gt);
+    return 2.0 / 3.0 + 2.0 / (3.0 * gamma) * (1.0 + (gt * 0.5 - 1.0) * ex) +
+           2.0 * gamma / 3.0 * (1.0 - tau * tau * 0.5) * expint_e2_ex(gt, ex);
+}
+
+// T^4 = 3/4 T_int^4 (2/3 + tau) + 3/4 T_irr^4 [(1 - alpha) xi(gamma_1) + alpha xi(gamma_2)],
+// tau = kappa p / g
+__host__ __device__ inline double line2013_temperature_c(double p_bar, const Line2013Consts& c) {
+    const double tau = c.kappa_over_g * (p_bar * kBar);
+    const double t4 = 0.75 * c.tint4 * (2.0 / 3.0 + tau) + 0.75 * c.tirr4 * (1.0 - c.alpha) * line2013_xi(c.g1, tau) +
+                      0.75 * c.tirr4 * c.alpha * line2013_xi(c.g2, tau);
     return sqrt(sqrt(t4));
+}
+
+__host__ __device__ inline double line2013_temperature(double p_bar, const double* tp, const bm_planet& pl) {
+    return line2013_temperature_c(p_bar, line2013_consts(tp, pl));
 }
 
 // ---- linear-in-T interpolation bracket --------------------------------------------------
@@ -82,6 +122,7 @@ __host__ __device__ inline double line2013_temperature(double p_bar, const doubl
 __host__ __device__ inline bool interp_bracket(const double* grid, int n, double t, int* k_out,
                                                double* w_out) {
     int k = 0;
+#pragma unroll 8
     for (int i = 1; i < n; ++i)
         if (grid[i] <= t) k = i;
     if (k > n - 2) k = n - 2;

@@ -12,7 +12,7 @@ def small_config2(n_nu=1000, n_layers=100, seed=11, dnu=0.5):
     s = wl.config2(n_nu=n_nu, n_layers=n_layers, dnu=dnu)
     sigma = wl.random_opacity_table(s.n_species, s.temps, n_layers, s.nu, seed=seed,
                                     dtype=np.float32)
-    cia = wl.cia_table(s.cia_temps, s.nu).astype(np.float32)
+    cia = wl.cia_table(s.cia_temps, s.nu)
     return s, sigma, cia
 
 

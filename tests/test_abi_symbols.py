@@ -79,7 +79,7 @@ def test_model_validation(lib):
     m.sigma = C.c_void_p(64)
     m.temp = C.c_void_p(64)
     one = lib.bm_workspace_size(C.byref(m), 1, None, 1)
-    assert one > 100 * 100 * 4                                      # holds the chord weights
+    assert one > 100 * 101 // 2 * 4                                # holds the chord-weight triangle
     assert lib.bm_workspace_size(C.byref(m), 1, None, 7) == 7 * one
     m.n_species = 9
     assert lib.bm_workspace_size(C.byref(m), 1, None, 1) == 0

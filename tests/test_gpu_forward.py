@@ -132,6 +132,8 @@ def test_fused_fp64_config1_parity():
 @pytest.mark.parametrize("n_nu", [1000, 1, 63, 65, 129])
 def test_fused_fp32_config2_parity(n_nu):
     s, sigma, cia = small_config2(n_nu=n_nu)
+    if n_nu < s.bin_width:
+        s.bin_width = 0            # no complete channel: binning is rejected by the library
     params = wl.line2013_prior(4).draw(4, seed=100 + n_nu)
     ppm = _check_fused(s, sigma, cia, params, rtol=1e-4)
     print(f"n_nu={n_nu}: max |depth error| = {ppm:.3g} ppm")
@@ -206,7 +208,7 @@ def test_fused_full_size_sampled_against_oracle():
     wavenumber columns one by one."""
     s = wl.config2()
     sigma = wl.random_opacity_table(4, s.temps, 100, s.nu, seed=77, dtype=np.float32)
-    cia = wl.cia_table(s.cia_temps, s.nu).astype(np.float32)
+    cia = wl.cia_table(s.cia_temps, s.nu)
     model = gpu_model(s, sigma, cia)
     params = wl.line2013_prior(4).draw(2, seed=78)
     f = bm.forward_batch(model, torch.as_tensor(params, device="cuda"), binned=True)
@@ -223,3 +225,26 @@ def test_fused_full_size_sampled_against_oracle():
         # binning is checked against the GPU's own full spectrum (property at any size)
         full = _np(f.spectrum(b))
         np.testing.assert_allclose(_np(f.binned_spectrum(b)), full.reshape(-1, 30).mean(1), rtol=1e-14)
+
+
+def test_fused_channels_wider_than_a_tile():
+    # 100-point channels do not fit one 64-wavenumber tile: a separate binning pass
+    s, sigma, cia = small_config2(n_nu=1030)
+    s.bin_width = 100
+    nb = s.nu.size // s.bin_width
+    g = np.random.default_rng(18)
+    data = 0.024 + 1e-4 * g.random(nb)
+    err = np.full(nb, 60e-6)
+    params = wl.line2013_prior(4).draw(3, seed=17)
+    _check_fused(s, sigma, cia, params, rtol=1e-4, data=data, err=err)
+
+
+@pytest.mark.parametrize("bw", [1, 7, 64])
+def test_fused_channel_widths(bw):
+    s, sigma, cia = small_config2(n_nu=777)
+    s.bin_width = bw
+    nb = s.nu.size // bw
+    data = np.full(nb, 0.025)
+    err = np.full(nb, 1e-4)
+    params = wl.line2013_prior(4).draw(2, seed=19 + bw)
+    _check_fused(s, sigma, cia, params, rtol=1e-4, data=data, err=err)
