@@ -174,15 +174,72 @@ int bm_bin_chi2(const double* depth, int B, int n_nu, int bin_width, const doubl
  * skip; needs bin_width > 0 in every used model), chi2 (device double [B] against each
  * model's data/err; NULL to skip; needs binned and data/err in every used model), flags
  * (device int32 [B]).
- * The workspace (device, `workspace_bytes` >= bm_workspace_size(...)) must be zero-
- * filled before its first use; every call leaves its counters at zero again. Calls
- * sharing one workspace must be ordered on one stream. */
+ * `active` (device int32 [B], or NULL = all) skips samples whose entry is 0: their
+ * depth, binned, chi2 and flags entries are left untouched (delayed acceptance runs the
+ * exact model only for the proposals its first stage passed, with static shapes).
+ * The workspace (device, `workspace_bytes` >= bm_workspace_size(...)) holds per-sample
+ * records; it needs no initialisation. Calls sharing one workspace must be ordered on
+ * one stream. Only kernels are enqueued (no memset or copy), so a call can be captured
+ * in a HIP graph. */
 size_t bm_workspace_size(const bm_model* models, int n_models, const int32_t* instance,
                          int B);
 int bm_forward_batch(const bm_model* models, int n_models, const int32_t* instance,
-                     const double* params, int param_stride, int B, double* depth,
-                     double* binned, double* chi2, int32_t* flags, void* workspace,
-                     size_t workspace_bytes, void* stream);
+                     const double* params, int param_stride, int B, const int32_t* active,
+                     double* depth, double* binned, double* chi2, int32_t* flags,
+                     void* workspace, size_t workspace_bytes, void* stream);
+
+/* ---- DE-MCz sampler with delayed acceptance ----------------------------------------------
+ * Sec. 3 and Sec. 5: MC3's differential-evolution samplers (DEMC, ter Braak 2006; the
+ * archive-based DEMCzs, ter Braak & Vrugt 2008), here in archive form for a whole
+ * generation of chains at once, so every chain's forward model of a generation is one
+ * batched bm_forward_batch call. Proposal y = x + gamma (z_r1 - z_r2) + e from two
+ * distinct archive rows, gamma = 2.38/sqrt(2d) (1 every 10th generation), e ~
+ * N(0, (eps_scale width)^2); log posterior -chi^2/2 in the uniform prior box;
+ * Metropolis acceptance. Delayed acceptance (Christen & Fox 2005): a surrogate chi^2
+ * screens proposals (stage 1) and the exact model decides among the survivors with the
+ * corrected ratio (stage 2), which keeps the exact posterior.
+ * Random numbers: SplitMix64 outputs addressed by (generation, chain, slot) counters.
+ * All pointers are device pointers owned by the caller; the sampler state lives in them,
+ * including the generation and archive counters, so a generation can be graph-captured
+ * and replayed. */
+typedef struct bm_demcz {
+    int32_t n_chains;   /* C, 1..1024                                                       */
+    int32_t n_params;   /* d, 1..32                                                         */
+    int32_t z_cap;      /* archive capacity in rows (>= 2)                                  */
+    int32_t thin;       /* append the C chain states to the archive every `thin` generations */
+    int32_t hist_cap;   /* generations the history buffer can hold (0 when history is NULL) */
+    int32_t pad;
+    uint64_t seed;      /* random stream                                                     */
+    double eps_scale;   /* jitter sd as a fraction of each prior width (e.g. 1e-6)           */
+    double* x;          /* [C][d] current states                                             */
+    double* lp;         /* [C] log posterior of the current states                           */
+    double* lp_surr;    /* [C] surrogate log posterior of the current states, or NULL        */
+    double* prop;       /* [C][d] proposals written by bm_demcz_propose                      */
+    double* z;          /* [z_cap][d] archive of past states                                 */
+    int64_t* counters;  /* [2]: generation, archive rows in use                              */
+    int64_t* n_accept;  /* [C][2]: stage-1 passes (delayed acceptance), acceptances          */
+    double* history;    /* [hist_cap][C][d] states after each generation, or NULL            */
+    const double* lo;   /* [d] prior box lower bounds                                        */
+    const double* hi;   /* [d] prior box upper bounds                                        */
+} bm_demcz;
+
+/* Chains at uniform prior draws, archive with z_init further draws, counters reset. */
+int bm_demcz_init(const bm_demcz* s, int z_init, void* stream);
+/* Log posterior (and surrogate log posterior) of the current states from their chi^2
+ * (device [C]; either may be NULL) and forward-model flags (device [C] or NULL). */
+int bm_demcz_set_lp(const bm_demcz* s, const double* chi2, const int32_t* flags,
+                    const double* chi2_surr, void* stream);
+/* Proposals of the current generation into s->prop. */
+int bm_demcz_propose(const bm_demcz* s, void* stream);
+/* Metropolis acceptance of the proposals given their chi^2 [C] and flags [C] (or NULL);
+ * records history, appends to the archive, advances the generation. */
+int bm_demcz_accept(const bm_demcz* s, const double* chi2, const int32_t* flags, void* stream);
+/* Delayed acceptance stage 1: active[c] = 1 when proposal c passes the surrogate test. */
+int bm_da_screen(const bm_demcz* s, const double* chi2_surr, int32_t* active, void* stream);
+/* Delayed acceptance stage 2 for the active proposals (exact chi^2 [C], flags [C] or
+ * NULL, surrogate chi^2 [C]); bookkeeping as bm_demcz_accept. */
+int bm_da_accept(const bm_demcz* s, const double* chi2, const int32_t* flags,
+                 const double* chi2_surr, const int32_t* active, void* stream);
 
 /* ---- opacity table build (secondary path) -----------------------------------------------
  * Sec. 3 and Sec. 4 (first pass: a per-molecule cross-section table on the output

@@ -1,0 +1,153 @@
+"""Reference DE-MCz sampler with delayed acceptance (oracle; test infrastructure only).
+
+Sec. 3, Sec. 4 item 10, Sec. 5: BART's MC3 samples with differential-evolution MCMC;
+the archive form (DEMCzs of ter Braak & Vrugt 2008) proposes from past states. The
+step definitions follow ter Braak & Vrugt (2008) and, for the two-stage acceptance,
+Christen & Fox (2005); the random numbers are SplitMix64 outputs (Steele, Lea & Flood
+2014) addressed by (generation, chain, slot) counters, written here from that
+definition in plain Python integers.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+MASK64 = (1 << 64) - 1
+GOLDEN = 0x9E3779B97F4A7C15
+SLOTS = 64
+SLOT_R1, SLOT_R2, SLOT_U, SLOT_U1, SLOT_NORMAL = 0, 1, 2, 3, 8
+INIT_XOR = 0xA5A5A5A5A5A5A5A5
+
+
+def splitmix64(seed: int, k: int) -> int:
+    """Output k (0-based) of the SplitMix64 stream with the given seed."""
+    z = (seed + (k + 1) * GOLDEN) & MASK64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & MASK64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & MASK64
+    return z ^ (z >> 31)
+
+
+def u01(seed: int, k: int) -> float:
+    """Uniform in [0, 1) from the top 53 bits."""
+    return (splitmix64(seed, k) >> 11) * 2.0 ** -53
+
+
+def counter(g: int, c: int, n_chains: int, slot: int) -> int:
+    return ((g * n_chains + c) * SLOTS + slot)
+
+
+def normal(seed: int, g: int, c: int, n_chains: int, j: int) -> float:
+    """Box-Muller on the uniform pair (2j, 2j+1) of the normal slots."""
+    u1 = u01(seed, counter(g, c, n_chains, SLOT_NORMAL + 2 * j))
+    u2 = u01(seed, counter(g, c, n_chains, SLOT_NORMAL + 2 * j + 1))
+    return math.sqrt(-2.0 * math.log(1.0 - u1)) * math.cos(2.0 * math.pi * u2)
+
+
+def init_state(seed: int, n_chains: int, z_init: int, lo, hi):
+    """Archive of z_init uniform prior draws, then C chain starts, from the init stream."""
+    lo = np.asarray(lo, dtype=np.float64)
+    hi = np.asarray(hi, dtype=np.float64)
+    d = lo.size
+    draws = np.empty((z_init + n_chains, d))
+    for i in range(z_init + n_chains):
+        for p in range(d):
+            draws[i, p] = lo[p] + (hi[p] - lo[p]) * u01(seed ^ INIT_XOR, i * SLOTS + p)
+    return draws[z_init:].copy(), draws[:z_init].copy()
+
+
+def propose(x, z, m: int, g: int, seed: int, lo, hi, eps_scale: float):
+    """DE-MCz proposals of generation g: y = x + gamma (z_r1 - z_r2) + e, r1 != r2 uniform
+    over the m archive rows, gamma = 2.38/sqrt(2d) (1 every 10th generation),
+    e ~ N(0, (eps_scale * width)^2). Returns (y, r1, r2)."""
+    n_chains, d = x.shape
+    y = np.empty_like(x)
+    r1s, r2s = np.empty(n_chains, int), np.empty(n_chains, int)
+    gamma = 1.0 if g % 10 == 9 else 2.38 / math.sqrt(2.0 * d)
+    for c in range(n_chains):
+        r1 = min(int(u01(seed, counter(g, c, n_chains, SLOT_R1)) * m), m - 1)
+        r2 = min(int(u01(seed, counter(g, c, n_chains, SLOT_R2)) * (m - 1)), m - 2)
+        if r2 >= r1:
+            r2 += 1
+        r1s[c], r2s[c] = r1, r2
+        for p in range(d):
+            width = hi[p] - lo[p]
+            e = (eps_scale * width) * normal(seed, g, c, n_chains, p)
+            y[c, p] = (x[c, p] + gamma * (z[r1, p] - z[r2, p])) + e
+    return y, r1s, r2s
+
+
+def log_post(y, chi2: float, flags: int, lo, hi) -> float:
+    """-chi^2/2 inside the uniform prior box; -inf outside or for a flagged model."""
+    if not (np.all(y >= lo) and np.all(y <= hi)) or flags != 0 or not np.isfinite(chi2):
+        return -math.inf
+    return -0.5 * chi2
+
+
+def accept(x, lp, y, chi2, flags, g: int, seed: int, lo, hi):
+    """Metropolis: accept y_c with probability min(1, exp(lp(y_c) - lp(x_c)))."""
+    x, lp = x.copy(), lp.copy()
+    taken = np.zeros(len(x), bool)
+    for c in range(len(x)):
+        lpy = log_post(y[c], chi2[c], 0 if flags is None else int(flags[c]), lo, hi)
+        u = u01(seed, counter(g, c, len(x), SLOT_U))
+        if math.isfinite(lpy) and math.log(u) < lpy - lp[c]:
+            x[c], lp[c], taken[c] = y[c], lpy, True
+    return x, lp, taken
+
+
+def da_screen(y, chi2_surr, lp_surr, g: int, seed: int, lo, hi):
+    """Delayed acceptance stage 1: pass with probability min(1, exp(ls(y) - ls(x)))."""
+    act = np.zeros(len(y), np.int32)
+    for c in range(len(y)):
+        if np.all(y[c] >= lo) and np.all(y[c] <= hi) and np.isfinite(chi2_surr[c]):
+            u = u01(seed, counter(g, c, len(y), SLOT_U1))
+            act[c] = math.log(u) < -0.5 * chi2_surr[c] - lp_surr[c]
+    return act
+
+
+def da_accept(x, lp, lp_surr, y, chi2, flags, chi2_surr, active, g: int, seed: int, lo, hi):
+    """Stage 2: among stage-1 survivors accept with
+    min(1, exp((lp(y) - lp(x)) - (ls(y) - ls(x))))."""
+    x, lp, lp_surr = x.copy(), lp.copy(), lp_surr.copy()
+    for c in range(len(x)):
+        if not active[c]:
+            continue
+        lpy = log_post(y[c], chi2[c], 0 if flags is None else int(flags[c]), lo, hi)
+        lsy = -0.5 * chi2_surr[c]
+        u = u01(seed, counter(g, c, len(x), SLOT_U))
+        if math.isfinite(lpy) and math.log(u) < (lpy - lp[c]) - (lsy - lp_surr[c]):
+            x[c], lp[c], lp_surr[c] = y[c], lpy, lsy
+    return x, lp, lp_surr
+
+
+def run(loglike_chi2, n_chains: int, n_gen: int, lo, hi, seed: int, thin: int = 10,
+        eps_scale: float = 1e-6, z_init: int | None = None, surrogate_chi2=None):
+    """Full reference sampler; loglike_chi2(y[C][d]) -> chi^2[C]. With surrogate_chi2,
+    delayed acceptance. Returns the chain history [n_gen][C][d] and acceptance counts."""
+    lo = np.asarray(lo, np.float64)
+    hi = np.asarray(hi, np.float64)
+    d = lo.size
+    z_init = z_init if z_init is not None else 10 * d
+    x, z = init_state(seed, n_chains, z_init, lo, hi)
+    chi2 = loglike_chi2(x)
+    lp = np.array([log_post(x[c], chi2[c], 0, lo, hi) for c in range(n_chains)])
+    lp_surr = -0.5 * surrogate_chi2(x) if surrogate_chi2 is not None else None
+    hist = np.empty((n_gen, n_chains, d))
+    n_acc = np.zeros(n_chains, int)
+    for g in range(n_gen):
+        y, _, _ = propose(x, z, len(z), g, seed, lo, hi, eps_scale)
+        if surrogate_chi2 is None:
+            x, lp, taken = accept(x, lp, y, loglike_chi2(y), None, g, seed, lo, hi)
+            n_acc += taken
+        else:
+            cs = surrogate_chi2(y)
+            act = da_screen(y, cs, lp_surr, g, seed, lo, hi)
+            x_new, lp, lp_surr = da_accept(x, lp, lp_surr, y, loglike_chi2(y), None, cs, act, g,
+                                           seed, lo, hi)
+            n_acc += np.any(x_new != x, axis=1)
+            x = x_new
+        hist[g] = x
+        if (g + 1) % thin == 0:
+            z = np.vstack([z, x])
+    return hist, n_acc

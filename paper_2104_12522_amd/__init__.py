@@ -16,7 +16,7 @@ import torch
 from . import _abi
 from ._abi import (BM_OK, BM_F32, BM_F64, BM_FLAG_T_CLAMP, BM_FLAG_SUM_X, BM_FLAG_RADIUS,
                    BM_FLAG_NONFINITE, BM_TP_ISOTHERMAL, BM_TP_LINE2013, BM_MAX_SPECIES,
-                   BmPlanet, BmModel)
+                   BmPlanet, BmModel, BmDemcz)
 
 __all__ = [
     "lib", "Model", "atmosphere", "extinction", "optical_depth", "transit_depth", "bin_chi2",
@@ -254,13 +254,16 @@ class Forward:
         self.flags = torch.empty(batch, dtype=torch.int32, device=device)
         self.param_stride = max(m.n_params for m in self.models)
 
-    def __call__(self, params: torch.Tensor, stream=None):
+    def __call__(self, params: torch.Tensor, stream=None, active: torch.Tensor | None = None):
         if params.shape[0] != self.B or params.dtype != torch.float64 or not params.is_contiguous():
             raise BartmiError("params must be a contiguous float64 [B][P] device tensor")
+        if active is not None and (active.dtype != torch.int32 or active.numel() != self.B):
+            raise BartmiError("active must be an int32 [B] device tensor")
         _check(lib().bm_forward_batch(self._structs, len(self.models), self._inst, _ptr(params),
-                                      params.shape[1], self.B, _ptr(self.depth), _ptr(self.binned),
-                                      _ptr(self.chi2), _ptr(self.flags), _ptr(self.workspace),
-                                      C.c_size_t(self.workspace.numel()), _stream(stream)),
+                                      params.shape[1], self.B, _ptr(active), _ptr(self.depth),
+                                      _ptr(self.binned), _ptr(self.chi2), _ptr(self.flags),
+                                      _ptr(self.workspace), C.c_size_t(self.workspace.numel()),
+                                      _stream(stream)),
                "bm_forward_batch")
         return self
 

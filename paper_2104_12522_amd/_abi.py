@@ -30,6 +30,17 @@ class BmModel(C.Structure):
     ]
 
 
+class BmDemcz(C.Structure):
+    _fields_ = [
+        ("n_chains", C.c_int32), ("n_params", C.c_int32), ("z_cap", C.c_int32),
+        ("thin", C.c_int32), ("hist_cap", C.c_int32), ("pad", C.c_int32),
+        ("seed", C.c_uint64), ("eps_scale", C.c_double),
+        ("x", C.c_void_p), ("lp", C.c_void_p), ("lp_surr", C.c_void_p), ("prop", C.c_void_p),
+        ("z", C.c_void_p), ("counters", C.c_void_p), ("n_accept", C.c_void_p),
+        ("history", C.c_void_p), ("lo", C.c_void_p), ("hi", C.c_void_p),
+    ]
+
+
 _VP = C.c_void_p
 _I = C.c_int
 _D = C.c_double
@@ -47,7 +58,13 @@ PROTOTYPES = {
     "bm_bin_chi2": (_I, [_VP, _I, _I, _I, _VP, _VP, _VP, _VP, _VP]),
     "bm_workspace_size": (C.c_size_t, [_PM, _I, C.POINTER(C.c_int32), _I]),
     "bm_forward_batch": (_I, [_PM, _I, C.POINTER(C.c_int32), _VP, _I, _I, _VP, _VP, _VP, _VP, _VP,
-                              C.c_size_t, _VP]),
+                              _VP, C.c_size_t, _VP]),
+    "bm_demcz_init": (_I, [C.POINTER(BmDemcz), _I, _VP]),
+    "bm_demcz_set_lp": (_I, [C.POINTER(BmDemcz), _VP, _VP, _VP, _VP]),
+    "bm_demcz_propose": (_I, [C.POINTER(BmDemcz), _VP]),
+    "bm_demcz_accept": (_I, [C.POINTER(BmDemcz), _VP, _VP, _VP]),
+    "bm_da_screen": (_I, [C.POINTER(BmDemcz), _VP, _VP, _VP]),
+    "bm_da_accept": (_I, [C.POINTER(BmDemcz), _VP, _VP, _VP, _VP, _VP]),
     "bm_opacity_table_build": (_I, [_VP, _VP, _VP, _VP, _VP, _I64, C.POINTER(C.c_double), _I,
                                     C.POINTER(C.c_double), _I, _D, _D, _I, _D, _I, _VP, _VP]),
     "bm_voigt": (_I, [_VP, _I64, _D, _D, _VP, _VP]),

@@ -146,10 +146,11 @@ __device__ inline double chord_weight(const double* r, int L, int j, int l) {
 // slice p fills 1/P of the chord weights, slice 0 also the per-layer fields.
 template <typename T>
 __global__ void __launch_bounds__(kAtmThreads)
-    k_atm_prep(LaunchPlan plan, const double* __restrict__ params, int stride, char* __restrict__ ws,
-               int32_t* __restrict__ flags_out) {
+    k_atm_prep(LaunchPlan plan, const double* __restrict__ params, int stride, const int32_t* __restrict__ active,
+               char* __restrict__ ws, int32_t* __restrict__ flags_out) {
     __shared__ AtmShared sh;
     const int b = blockIdx.x;
+    if (active && !active[b]) return;  // sample not requested in this call
     const int slice = blockIdx.y, n_slices = gridDim.y;
     const int si = plan.segment_of_sample(b);
     const Segment& sg = plan.seg[si];
@@ -217,8 +218,8 @@ __global__ void __launch_bounds__(kAtmThreads)
     }
 }
 
-template __global__ void k_atm_prep<float>(LaunchPlan, const double*, int, char*, int32_t*);
-template __global__ void k_atm_prep<double>(LaunchPlan, const double*, int, char*, int32_t*);
+template __global__ void k_atm_prep<float>(LaunchPlan, const double*, int, const int32_t*, char*, int32_t*);
+template __global__ void k_atm_prep<double>(LaunchPlan, const double*, int, const int32_t*, char*, int32_t*);
 
 }  // namespace bm
 

@@ -167,6 +167,7 @@ ModelDev to_device_view(const bm_model& m);
 
 template <typename T>
 __global__ void k_atm_prep(LaunchPlan plan, const double* __restrict__ params, int stride,
-                           char* __restrict__ ws, int32_t* __restrict__ flags_out);
+                           const int32_t* __restrict__ active, char* __restrict__ ws,
+                           int32_t* __restrict__ flags_out);
 
 }  // namespace bm

@@ -87,8 +87,8 @@ __device__ __forceinline__ double lane_get(double v, int i) {
 
 template <typename T, int kWaves, int kS, bool kCia, bool kNonTemporal>
 __global__ void __launch_bounds__(kWaves * kWave)
-    k_forward(LaunchPlan plan, char* __restrict__ ws, double* __restrict__ depth,
-              double* __restrict__ binned, double* __restrict__ chi2) {
+    k_forward(LaunchPlan plan, char* __restrict__ ws, const int32_t* __restrict__ active,
+              double* __restrict__ depth, double* __restrict__ binned, double* __restrict__ chi2) {
     extern __shared__ __align__(16) char smem[];
     const int si = plan.segment_of_wg(blockIdx.x);
     const Segment& sg = plan.seg[si];
@@ -101,6 +101,7 @@ __global__ void __launch_bounds__(kWaves * kWave)
     const int s_in = kx % sg.count;
     if (tile >= sg.tiles) return;  // padding workgroup of the XCD split
     const int b = sg.first + s_in;
+    if (active && !active[b]) return;  // sample not requested in this call
     const int L = m.L, Nnu = m.Nnu;
     const RecordView<T> rec(ws + sg.ws_off + (size_t)s_in * sg.rec_bytes, kS, L);
     const FwdLds<T> lay(L, kWaves, plan.max_ntc);
@@ -331,9 +332,11 @@ __global__ void __launch_bounds__(kWaves * kWave)
 // chi^2 of each sample: the tiles' partials summed in a fixed tree (one workgroup per
 // sample, after the forward kernel: the kernel boundary orders the partial writes)
 template <typename T>
-__global__ void __launch_bounds__(256) k_chi2_reduce(LaunchPlan plan, char* __restrict__ ws, double* __restrict__ chi2) {
+__global__ void __launch_bounds__(256)
+    k_chi2_reduce(LaunchPlan plan, char* __restrict__ ws, const int32_t* __restrict__ active, double* __restrict__ chi2) {
     __shared__ double cp[256];
     const int b = blockIdx.x;
+    if (active && !active[b]) return;
     const Segment& sg = plan.seg[plan.segment_of_sample(b)];
     const ModelDev& m = plan.model[sg.model];
     const RecordView<T> rec(ws + sg.ws_off + (size_t)(b - sg.first) * sg.rec_bytes, m.S, m.L);
@@ -617,8 +620,8 @@ static int ensure_dynamic_lds(const void* fn, size_t bytes) {
 }
 
 template <typename T>
-static int launch_forward(const HostPlan& hp, const double* params, int stride, double* depth,
-                          double* binned, double* chi2, int32_t* flags, char* ws, hipStream_t st) {
+static int launch_forward(const HostPlan& hp, const double* params, int stride, const int32_t* active,
+                          double* depth, double* binned, double* chi2, int32_t* flags, char* ws, hipStream_t st) {
     const size_t lds = forward_lds_bytes<T>(hp.max_L, hp.max_ntc);
     if (lds > device_lds_limit()) return BM_ESHAPE;
     int st_code = BM_OK;
@@ -628,8 +631,9 @@ static int launch_forward(const HostPlan& hp, const double* params, int stride, 
         const int nb = hp.n_samples[p];
         // Segment offsets inside a plan are absolute (workspace, depth, binned); sample
         // indices are relative to the plan, so params/flags/chi2 are shifted here.
+        const int32_t* act = active ? active + b0 : nullptr;
         hipLaunchKernelGGL((k_atm_prep<T>), dim3(nb, prep_slices(hp, nb)), dim3(kAtmThreads), 0, st, lp,
-                           params + (size_t)b0 * stride, stride, ws, flags + b0);
+                           params + (size_t)b0 * stride, stride, act, ws, flags + b0);
         BM_CHECK_HIP(hipGetLastError());
         double* c2 = chi2 ? chi2 + b0 : nullptr;
         const dim3 grid(lp.total_wgs), block(kFwdWaves * kWave);
@@ -637,7 +641,7 @@ static int launch_forward(const HostPlan& hp, const double* params, int stride, 
 #define BM_FWD_LAUNCH(NS, CIA)                                                                         \
     st_code = ensure_dynamic_lds((const void*)k_forward<T, kFwdWaves, NS, CIA, true>, lds);             \
     if (st_code != BM_OK) return st_code;                                                              \
-    hipLaunchKernelGGL((k_forward<T, kFwdWaves, NS, CIA, true>), grid, block, lds, st, lp, ws, depth, binned, c2);
+    hipLaunchKernelGGL((k_forward<T, kFwdWaves, NS, CIA, true>), grid, block, lds, st, lp, ws, act, depth, binned, c2);
 #define BM_FWD_CASE(NS)                  \
     case NS:                             \
         if (hp.cia) {                    \
@@ -657,7 +661,7 @@ static int launch_forward(const HostPlan& hp, const double* params, int stride, 
             bool any_fused = false;
             for (int si = 0; si < lp.n_seg; ++si) any_fused |= lp.seg[si].fused_bins != 0;
             if (any_fused) {
-                hipLaunchKernelGGL((k_chi2_reduce<T>), dim3(nb), dim3(256), 0, st, lp, ws, c2);
+                hipLaunchKernelGGL((k_chi2_reduce<T>), dim3(nb), dim3(256), 0, st, lp, ws, act, c2);
                 BM_CHECK_HIP(hipGetLastError());
             }
         }
@@ -774,8 +778,8 @@ extern "C" size_t bm_workspace_size(const bm_model* models, int n_models, const 
 }
 
 extern "C" int bm_forward_batch(const bm_model* models, int n_models, const int32_t* instance,
-                                const double* params, int param_stride, int B, double* depth,
-                                double* binned, double* chi2, int32_t* flags, void* workspace,
+                                const double* params, int param_stride, int B, const int32_t* active,
+                                double* depth, double* binned, double* chi2, int32_t* flags, void* workspace,
                                 size_t workspace_bytes, void* stream) {
     if (!models || !params || !depth || !flags || !workspace) return BM_EINVAL;
     HostPlan hp;
@@ -791,6 +795,6 @@ extern "C" int bm_forward_batch(const bm_model* models, int n_models, const int3
     if (workspace_bytes < hp.ws_bytes) return BM_ENOSPACE;
     const hipStream_t s = (hipStream_t)stream;
     if (models[0].dtype == BM_F32)
-        return launch_forward<float>(hp, params, param_stride, depth, binned, chi2, flags, (char*)workspace, s);
-    return launch_forward<double>(hp, params, param_stride, depth, binned, chi2, flags, (char*)workspace, s);
+        return launch_forward<float>(hp, params, param_stride, active, depth, binned, chi2, flags, (char*)workspace, s);
+    return launch_forward<double>(hp, params, param_stride, active, depth, binned, chi2, flags, (char*)workspace, s);
 }
