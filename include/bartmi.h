@@ -270,6 +270,82 @@ int bm_opacity_table_build(const double* nu0, const double* s296, const double* 
 int bm_voigt(const double* x, int64_t n, double sigma, double gamma, double* out,
              void* stream);
 
+/* ---- learned surrogate for delayed acceptance --------------------------------------------
+ * Sec. 1 motivates machine-learning surrogates of the forward model and Sec. 5 asks for
+ * faster retrievals; here a multilayer perceptron maps the retrieval parameters to the
+ * (standardised) binned spectrum and only screens proposals (stage 1 of bm_da_screen), so
+ * the exact model still decides and the posterior is unchanged. Dense layers run on the
+ * matrix cores in BF16 with FP32 accumulation; master weights and Adam moments are FP32.
+ * Layer i (0 <= i < n_layers): z_i = h_i W_i^T + b_i with W_i [dims[i+1]][dims[i]]
+ * row-major; h_{i+1} = silu(z_i) = z_i / (1 + exp(-z_i)) for hidden layers; the last
+ * layer is linear. BF16 values are raw 16-bit patterns (round to nearest even).
+ * All pointers are device pointers owned by the caller. */
+#define BM_MLP_MAX_LAYERS 8
+
+/* epilogues of bm_gemm_bf16 */
+#define BM_GEMM_STORE 0      /* out_f32 = beta out_f32 + A B                               */
+#define BM_GEMM_BIAS_SILU 1  /* z = A B + bias -> out_f32 (if not NULL); silu(z) -> out_bf16 */
+#define BM_GEMM_BIAS 2       /* out_f32 = A B + bias                                       */
+#define BM_GEMM_SILU_GRAD 3  /* out_bf16 = (A B) * silu'(aux)                              */
+
+typedef struct bm_mlp {
+    int32_t n_layers;                  /* 1..BM_MLP_MAX_LAYERS                              */
+    int32_t max_batch;                 /* rows the activation buffers hold                  */
+    int32_t dims[BM_MLP_MAX_LAYERS + 1]; /* widths: dims[0] input .. dims[n_layers] output  */
+    float* w32[BM_MLP_MAX_LAYERS];     /* [dims[i+1]][dims[i]] FP32 master weights           */
+    void* w16[BM_MLP_MAX_LAYERS];      /* same shape, BF16 copy used by the kernels          */
+    float* b32[BM_MLP_MAX_LAYERS];     /* [dims[i+1]] biases                                 */
+    float* gw[BM_MLP_MAX_LAYERS];      /* weight gradients (written by bm_mlp_backward)      */
+    float* gb[BM_MLP_MAX_LAYERS];      /* bias gradients                                     */
+    float* mw[BM_MLP_MAX_LAYERS];      /* Adam first moments of the weights (start at 0)     */
+    float* vw[BM_MLP_MAX_LAYERS];      /* Adam second moments of the weights (start at 0)    */
+    float* mb[BM_MLP_MAX_LAYERS];      /* Adam moments of the biases (start at 0)            */
+    float* vb[BM_MLP_MAX_LAYERS];
+    float* z[BM_MLP_MAX_LAYERS];       /* [max_batch][dims[i+1]] hidden pre-activations
+                                          (i < n_layers - 1; the last may be NULL)           */
+    void* h[BM_MLP_MAX_LAYERS];        /* [max_batch][dims[i]] BF16 layer inputs, h[0] the
+                                          network input                                      */
+    void* dz[2];                       /* two BF16 [max_batch][max(dims[1..])] scratch rows
+                                          for back-propagated gradients                      */
+} bm_mlp;
+
+/* C[M][N] = A B in BF16 with FP32 accumulation on the matrix cores, with an epilogue.
+ * A(m, k) = A[m lda + k] (trans_a 0) or A[k lda + m] (trans_a 1); B(k, n) = B[n ldb + k]
+ * (trans_b 0, i.e. B stored as [N][K] like a weight matrix) or B[k ldb + n] (trans_b 1).
+ * bias [N] FP32; aux [M][ldaux] FP32; out_f32 [M][ldo]; out_bf16 [M][ldob]. */
+int bm_gemm_bf16(int M, int N, int K, const void* A, int lda, int trans_a, const void* B,
+                 int ldb, int trans_b, int mode, const float* bias, const float* aux,
+                 int ldaux, float* out_f32, int ldo, void* out_bf16, int ldob, float beta,
+                 void* stream);
+/* Network input h[0][b][j] = bf16((theta_rj - lo_j) / (hi_j - lo_j)) for j < P, zero for
+ * P <= j < dims[0], with r = rows[b] (device int32 [B], e.g. a shuffled minibatch) or r = b
+ * when rows is NULL; params device [*][param_stride], lo/hi device [P] doubles. */
+int bm_mlp_set_input(const bm_mlp* net, const double* params, int param_stride,
+                     const int32_t* rows, int B, int P, const double* lo, const double* hi,
+                     void* stream);
+/* Forward pass of B <= max_batch rows from h[0]; out [B][dims[n_layers]] FP32. */
+int bm_mlp_forward(const bm_mlp* net, int B, float* out, void* stream);
+/* Mean-squared-error loss on standardised targets, sum_bn (out_bn - t_bn)^2 / (B N) with
+ * t_bn = (target_rn - mean_n) / scale_n, r = rows[b] (or b when rows is NULL); target
+ * device doubles [*][N] (e.g. binned spectra), mean/scale device doubles [N] or both NULL
+ * (t = target). Per-row sums of squares into row_loss [B] (FP32) and the gradient wrt out
+ * into dz[0] (BF16). */
+int bm_mlp_loss_grad(const bm_mlp* net, int B, const float* out, const double* target,
+                     const int32_t* rows, const double* mean, const double* scale,
+                     float* row_loss, void* stream);
+/* Back-propagation from dz[0] (left by bm_mlp_loss_grad) through the activations of the
+ * last bm_mlp_forward; writes gw and gb of every layer. */
+int bm_mlp_backward(const bm_mlp* net, int B, void* stream);
+/* One Adam step (Kingma & Ba 2015) with bias correction for step >= 1; refreshes w16. */
+int bm_adam_step(const bm_mlp* net, float lr, float beta1, float beta2, float eps, int step,
+                 void* stream);
+/* w16 = bf16(w32) for every layer (after the caller initialises w32). */
+int bm_mlp_sync_bf16(const bm_mlp* net, void* stream);
+/* Surrogate chi^2 [B] (double) of standardised outputs out [B][N]: prediction_n = mean_n +
+ * scale_n out_bn, chi^2 = sum_n ((prediction_n - data_n) / err_n)^2 (device doubles [N]). */
+int bm_surrogate_chi2(const float* out, int B, int N, const double* mean, const double* scale,
+                      const double* data, const double* err, double* chi2, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

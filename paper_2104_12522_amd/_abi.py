@@ -9,6 +9,8 @@ BM_F32, BM_F64 = 0, 1
 BM_FLAG_T_CLAMP, BM_FLAG_SUM_X, BM_FLAG_RADIUS, BM_FLAG_NONFINITE = 1, 2, 4, 8
 BM_TP_ISOTHERMAL, BM_TP_LINE2013 = 0, 1
 BM_MAX_SPECIES, BM_MAX_LAYERS, BM_MAX_TEMPS = 8, 256, 64
+BM_MLP_MAX_LAYERS = 8
+BM_GEMM_STORE, BM_GEMM_BIAS_SILU, BM_GEMM_BIAS, BM_GEMM_SILU_GRAD = 0, 1, 2, 3
 
 
 class BmPlanet(C.Structure):
@@ -41,6 +43,14 @@ class BmDemcz(C.Structure):
     ]
 
 
+class BmMlp(C.Structure):
+    _fields_ = [("n_layers", C.c_int32), ("max_batch", C.c_int32),
+                ("dims", C.c_int32 * (BM_MLP_MAX_LAYERS + 1))] + [
+        (n, C.c_void_p * BM_MLP_MAX_LAYERS)
+        for n in ("w32", "w16", "b32", "gw", "gb", "mw", "vw", "mb", "vb", "z", "h")] + [
+        ("dz", C.c_void_p * 2)]
+
+
 _VP = C.c_void_p
 _I = C.c_int
 _D = C.c_double
@@ -68,6 +78,15 @@ PROTOTYPES = {
     "bm_opacity_table_build": (_I, [_VP, _VP, _VP, _VP, _VP, _I64, C.POINTER(C.c_double), _I,
                                     C.POINTER(C.c_double), _I, _D, _D, _I, _D, _I, _VP, _VP]),
     "bm_voigt": (_I, [_VP, _I64, _D, _D, _VP, _VP]),
+    "bm_gemm_bf16": (_I, [_I, _I, _I, _VP, _I, _I, _VP, _I, _I, _I, _VP, _VP, _I, _VP, _I, _VP, _I,
+                          C.c_float, _VP]),
+    "bm_mlp_set_input": (_I, [C.POINTER(BmMlp), _VP, _I, _VP, _I, _I, _VP, _VP, _VP]),
+    "bm_mlp_forward": (_I, [C.POINTER(BmMlp), _I, _VP, _VP]),
+    "bm_mlp_loss_grad": (_I, [C.POINTER(BmMlp), _I, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "bm_mlp_backward": (_I, [C.POINTER(BmMlp), _I, _VP]),
+    "bm_adam_step": (_I, [C.POINTER(BmMlp), C.c_float, C.c_float, C.c_float, C.c_float, _I, _VP]),
+    "bm_mlp_sync_bf16": (_I, [C.POINTER(BmMlp), _VP]),
+    "bm_surrogate_chi2": (_I, [_VP, _I, _I, _VP, _VP, _VP, _VP, _VP, _VP]),
 }
 
 _cache: dict[str, C.CDLL] = {}

@@ -1,0 +1,378 @@
+// The learned surrogate: a multilayer perceptron from the retrieval parameters to the
+// binned spectrum, trained and evaluated on the matrix cores in BF16 with FP32
+// accumulation (v_mfma_f32_16x16x32_bf16), FP32 master weights and Adam.
+//
+// The paper motivates machine-learning surrogates for retrievals and notes that they
+// did not reproduce the posterior exactly (Sec. 1); here the surrogate only screens
+// proposals (stage 1 of delayed acceptance) and the exact forward model decides, so the
+// posterior is unchanged.
+//
+// Layer i: z_i = h_i W_i^T + b_i (W_i is [out][in], row-major), h_{i+1} = silu(z_i) for
+// hidden layers, the last layer is linear. Backward: dz_L = d loss / d out;
+// gW_i = dz_i^T h_i, gb_i = sum_rows dz_i, dz_{i-1} = (dz_i W_i) * silu'(z_{i-1}).
+#include <cmath>
+
+#include "bm_internal.h"
+
+namespace bm {
+
+typedef short bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+__device__ __forceinline__ uint16_t f2bf(float f) {
+    // round to nearest even; NaN stays NaN
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float silu(float z) { return z / (1.0f + __expf(-z)); }
+__device__ __forceinline__ float silu_grad(float z) {
+    const float s = 1.0f / (1.0f + __expf(-z));
+    return s * (1.0f + z * (1.0f - s));
+}
+
+// ---- GEMM: C[M][N] = sum_k A(m, k) B(k, n) -------------------------------------------------
+// A(m, k) = A[m * lda + k] (trans_a = 0) or A[k * lda + m] (trans_a = 1); B(k, n) =
+// B[n * ldb + k] (trans_b = 0: B holds rows of length K, as W[out][in]) or B[k * ldb + n].
+// Tiles 64 x 64 x 32, 4 waves, each wave a 32 x 32 quadrant of 2 x 2 MFMA tiles.
+constexpr int kTM = 64, kTN = 64, kTK = 32, kPad = 8;
+
+struct GemmArgs {
+    int M, N, K;
+    const uint16_t* A;
+    int lda, trans_a;
+    const uint16_t* B;
+    int ldb, trans_b;
+    int mode;                 // BM_GEMM_* epilogue
+    const float* bias;        // [N]
+    const float* aux;         // [M][ldaux] pre-activations for silu'
+    int ldaux;
+    float* out_f32;           // [M][ldo]
+    int ldo;
+    uint16_t* out_bf16;       // [M][ldob]
+    int ldob;
+    float beta;               // out_f32 = beta * out_f32 + result (accumulating modes)
+};
+
+__global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
+    __shared__ __align__(16) uint16_t As[kTM][kTK + kPad];
+    __shared__ __align__(16) uint16_t Bs[kTN][kTK + kPad];
+    const int m0 = blockIdx.y * kTM, n0 = blockIdx.x * kTN;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    f32x4 acc[2][2];
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < g.K; k0 += kTK) {
+        // stage A and B tiles as [row][k]; out-of-range elements are zero
+        // consecutive threads walk the contiguous index of the stored operand
+        for (int e = tid; e < kTM * kTK; e += 256) {
+            const int r = g.trans_a ? e % kTM : e / kTK, kk = g.trans_a ? e / kTM : e % kTK;
+            const int m = m0 + r, k = k0 + kk;
+            uint16_t v = 0;
+            if (m < g.M && k < g.K) v = g.trans_a ? g.A[(size_t)k * g.lda + m] : g.A[(size_t)m * g.lda + k];
+            As[r][kk] = v;
+        }
+        for (int e = tid; e < kTN * kTK; e += 256) {
+            const int r = g.trans_b ? e % kTN : e / kTK, kk = g.trans_b ? e / kTN : e % kTK;
+            const int n = n0 + r, k = k0 + kk;
+            uint16_t v = 0;
+            if (n < g.N && k < g.K) v = g.trans_b ? g.B[(size_t)k * g.ldb + n] : g.B[(size_t)n * g.ldb + k];
+            Bs[r][kk] = v;
+        }
+        __syncthreads();
+        // operands: lane holds 8 consecutive k of row (lane % 16); k offset 8 (lane / 16)
+        const int kq = 8 * (lane >> 4);
+        bf16x8 a[2], b[2];
+        for (int i = 0; i < 2; ++i) a[i] = *reinterpret_cast<const bf16x8*>(&As[wm + 16 * i + (lane & 15)][kq]);
+        for (int j = 0; j < 2; ++j) b[j] = *reinterpret_cast<const bf16x8*>(&Bs[wn + 16 * j + (lane & 15)][kq]);
+        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 2; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        __syncthreads();
+    }
+    // epilogue: lane holds C[4 (lane / 16) + r][lane % 16] of each 16 x 16 tile
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
+            for (int r = 0; r < 4; ++r) {
+                const int m = m0 + wm + 16 * i + 4 * (lane >> 4) + r;
+                const int n = n0 + wn + 16 * j + (lane & 15);
+                if (m >= g.M || n >= g.N) continue;
+                float v = acc[i][j][r];
+                switch (g.mode) {
+                    case BM_GEMM_STORE:
+                        g.out_f32[(size_t)m * g.ldo + n] =
+                            (g.beta != 0.f ? g.beta * g.out_f32[(size_t)m * g.ldo + n] : 0.f) + v;
+                        break;
+                    case BM_GEMM_BIAS_SILU: {
+                        const float z = v + g.bias[n];
+                        if (g.out_f32) g.out_f32[(size_t)m * g.ldo + n] = z;
+                        g.out_bf16[(size_t)m * g.ldob + n] = f2bf(silu(z));
+                        break;
+                    }
+                    case BM_GEMM_BIAS:
+                        g.out_f32[(size_t)m * g.ldo + n] = v + g.bias[n];
+                        break;
+                    case BM_GEMM_SILU_GRAD:
+                        g.out_bf16[(size_t)m * g.ldob + n] = f2bf(v * silu_grad(g.aux[(size_t)m * g.ldaux + n]));
+                        break;
+                }
+            }
+}
+
+// column sums of a bf16 matrix [M][N] (bias gradients), fixed order per column
+__global__ void k_colsum_bf16(const uint16_t* __restrict__ x, int M, int N, float* __restrict__ out, float beta) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    float s = 0.f;
+    for (int m = 0; m < M; ++m) s += bf2f(x[(size_t)m * N + n]);
+    out[n] = (beta != 0.f ? beta * out[n] : 0.f) + s;
+}
+
+// network input: h0[b][j] = bf16((theta_j - lo_j) / (hi_j - lo_j)), zero padding to dims[0]
+__global__ void k_mlp_input(const double* __restrict__ params, int stride, const int32_t* __restrict__ rows, int B,
+                            int P, const double* __restrict__ lo, const double* __restrict__ hi, int d0,
+                            uint16_t* __restrict__ h0) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= B * d0) return;
+    const int b = i / d0, j = i % d0;
+    const int64_t r = rows ? rows[b] : b;
+    float v = 0.f;
+    if (j < P) v = (float)((params[r * stride + j] - lo[j]) / (hi[j] - lo[j]));
+    h0[i] = f2bf(v);
+}
+
+// mean-squared-error loss and its gradient wrt the (linear) output, as the last layer's dz
+__global__ void k_mse_grad(const float* __restrict__ out, const double* __restrict__ target,
+                           const int32_t* __restrict__ rows, const double* __restrict__ mean,
+                           const double* __restrict__ scale, int B, int N, uint16_t* __restrict__ dz,
+                           float* __restrict__ row_loss) {
+    __shared__ float part[256];
+    const int b = blockIdx.x;
+    const int64_t r = rows ? rows[b] : b;
+    float s = 0.f;
+    const float gscale = 2.0f / ((float)B * (float)N);
+    for (int n = threadIdx.x; n < N; n += blockDim.x) {
+        double t = target[r * N + n];
+        if (mean) t = (t - mean[n]) / scale[n];
+        const float d = out[(size_t)b * N + n] - (float)t;
+        s += d * d;
+        dz[(size_t)b * N + n] = f2bf(gscale * d);
+    }
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) row_loss[b] = part[0];
+}
+
+// Adam (Kingma & Ba 2015) on FP32 master weights, refreshing the BF16 copy
+__global__ void k_adam(float* __restrict__ w, uint16_t* __restrict__ w16, const float* __restrict__ g,
+                       float* __restrict__ m, float* __restrict__ v, int64_t n, float lr, float b1, float b2,
+                       float eps, float c1, float c2) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    w[i] = wi;
+    if (w16) w16[i] = f2bf(wi);
+}
+
+__global__ void k_to_bf16(const float* __restrict__ x, uint16_t* __restrict__ y, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = f2bf(x[i]);
+}
+
+// surrogate chi^2: the standardised output back to depths, then chi^2 against the data
+__global__ void k_surrogate_chi2(const float* __restrict__ out, int B, int N, const double* __restrict__ mean,
+                                 const double* __restrict__ scale, const double* __restrict__ data,
+                                 const double* __restrict__ err, double* __restrict__ chi2) {
+    __shared__ double part[256];
+    const int b = blockIdx.x;
+    double s = 0.0;
+    for (int n = threadIdx.x; n < N; n += blockDim.x) {
+        const double pred = mean[n] + scale[n] * (double)out[(size_t)b * N + n];
+        const double d = (pred - data[n]) / err[n];
+        s += d * d;
+    }
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) chi2[b] = part[0];
+}
+
+static int launch_gemm(const GemmArgs& a, hipStream_t st) {
+    if (a.M < 0 || a.N < 0 || a.K < 0) return BM_ESHAPE;
+    if (a.M == 0 || a.N == 0) return BM_OK;
+    dim3 grid((a.N + kTN - 1) / kTN, (a.M + kTM - 1) / kTM);
+    hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(256), 0, st, a);
+    BM_CHECK_HIP(hipGetLastError());
+    return BM_OK;
+}
+
+static int check_mlp(const bm_mlp* n, int B) {
+    if (!n || n->n_layers < 1 || n->n_layers > BM_MLP_MAX_LAYERS) return BM_EINVAL;
+    if (B < 0 || B > n->max_batch) return BM_ESHAPE;
+    for (int i = 0; i <= n->n_layers; ++i)
+        if (n->dims[i] < 1) return BM_ESHAPE;
+    for (int i = 0; i < n->n_layers; ++i) {
+        if (!n->w16[i] || !n->b32[i] || !n->h[i]) return BM_EINVAL;
+        if (i < n->n_layers - 1 && !n->z[i]) return BM_EINVAL;
+    }
+    return BM_OK;
+}
+
+}  // namespace bm
+
+using namespace bm;
+
+extern "C" int bm_gemm_bf16(int M, int N, int K, const void* A, int lda, int trans_a, const void* B, int ldb,
+                            int trans_b, int mode, const float* bias, const float* aux, int ldaux, float* out_f32,
+                            int ldo, void* out_bf16, int ldob, float beta, void* stream) {
+    if (!A || !B) return BM_EINVAL;
+    if (mode < BM_GEMM_STORE || mode > BM_GEMM_SILU_GRAD) return BM_EINVAL;
+    if ((mode == BM_GEMM_STORE || mode == BM_GEMM_BIAS) && !out_f32) return BM_EINVAL;
+    if ((mode == BM_GEMM_BIAS_SILU || mode == BM_GEMM_BIAS) && !bias) return BM_EINVAL;
+    if ((mode == BM_GEMM_BIAS_SILU || mode == BM_GEMM_SILU_GRAD) && !out_bf16) return BM_EINVAL;
+    if (mode == BM_GEMM_SILU_GRAD && !aux) return BM_EINVAL;
+    GemmArgs a{M, N, K, (const uint16_t*)A, lda, trans_a, (const uint16_t*)B, ldb, trans_b, mode, bias, aux, ldaux,
+               out_f32, ldo, (uint16_t*)out_bf16, ldob, beta};
+    return launch_gemm(a, (hipStream_t)stream);
+}
+
+extern "C" int bm_mlp_set_input(const bm_mlp* net, const double* params, int param_stride, const int32_t* rows,
+                                int B, int P, const double* lo, const double* hi, void* stream) {
+    int st = check_mlp(net, B);
+    if (st != BM_OK) return st;
+    if (!params || !lo || !hi) return BM_EINVAL;
+    if (P < 1 || P > net->dims[0] || param_stride < P) return BM_ESHAPE;
+    if (B == 0) return BM_OK;
+    const int n = B * net->dims[0];
+    hipLaunchKernelGGL(k_mlp_input, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream, params, param_stride, rows,
+                       B, P, lo, hi, net->dims[0], (uint16_t*)net->h[0]);
+    BM_CHECK_HIP(hipGetLastError());
+    return BM_OK;
+}
+
+extern "C" int bm_mlp_forward(const bm_mlp* net, int B, float* out, void* stream) {
+    int st = check_mlp(net, B);
+    if (st != BM_OK) return st;
+    if (!out) return BM_EINVAL;
+    const int L = net->n_layers;
+    for (int i = 0; i < L; ++i) {
+        const int K = net->dims[i], N = net->dims[i + 1];
+        const bool last = (i == L - 1);
+        if (!last && !net->h[i + 1]) return BM_EINVAL;
+        GemmArgs a{B, N, K, (const uint16_t*)net->h[i], K, 0, (const uint16_t*)net->w16[i], K, 0,
+                   last ? BM_GEMM_BIAS : BM_GEMM_BIAS_SILU, net->b32[i], nullptr, 0,
+                   last ? out : net->z[i], N, last ? nullptr : (uint16_t*)net->h[i + 1], N, 0.f};
+        st = launch_gemm(a, (hipStream_t)stream);
+        if (st != BM_OK) return st;
+    }
+    return BM_OK;
+}
+
+extern "C" int bm_mlp_loss_grad(const bm_mlp* net, int B, const float* out, const double* target,
+                                const int32_t* rows, const double* mean, const double* scale, float* row_loss,
+                                void* stream) {
+    int st = check_mlp(net, B);
+    if (st != BM_OK) return st;
+    if (!out || !target || !row_loss || !net->dz[0]) return BM_EINVAL;
+    if ((mean == nullptr) != (scale == nullptr)) return BM_EINVAL;
+    if (B == 0) return BM_OK;
+    hipLaunchKernelGGL(k_mse_grad, dim3(B), dim3(256), 0, (hipStream_t)stream, out, target, rows, mean, scale,
+                       B, net->dims[net->n_layers], (uint16_t*)net->dz[0], row_loss);
+    BM_CHECK_HIP(hipGetLastError());
+    return BM_OK;
+}
+
+extern "C" int bm_mlp_backward(const bm_mlp* net, int B, void* stream) {
+    int st = check_mlp(net, B);
+    if (st != BM_OK) return st;
+    const int L = net->n_layers;
+    for (int i = 0; i < L; ++i)
+        if (!net->gw[i] || !net->gb[i]) return BM_EINVAL;
+    if (!net->dz[0] || !net->dz[1]) return BM_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    int cur = 0;  // dz of layer i lives in dz[cur]
+    for (int i = L - 1; i >= 0; --i) {
+        const int K = net->dims[i], N = net->dims[i + 1];
+        const uint16_t* dz = (const uint16_t*)net->dz[cur];
+        // gW_i [N][K] = dz^T [N][B] h_i [B][K]
+        GemmArgs gw{N, K, B, dz, N, 1, (const uint16_t*)net->h[i], K, 1, BM_GEMM_STORE, nullptr, nullptr, 0,
+                    net->gw[i], K, nullptr, 0, 0.f};
+        st = launch_gemm(gw, s);
+        if (st != BM_OK) return st;
+        hipLaunchKernelGGL(k_colsum_bf16, dim3((N + 255) / 256), dim3(256), 0, s, dz, B, N, net->gb[i], 0.f);
+        BM_CHECK_HIP(hipGetLastError());
+        if (i > 0) {
+            // dz_{i-1} [B][K] = (dz [B][N] W_i [N][K]) * silu'(z_{i-1})
+            GemmArgs dx{B, K, N, dz, N, 0, (const uint16_t*)net->w16[i], K, 1, BM_GEMM_SILU_GRAD, nullptr,
+                        net->z[i - 1], K, nullptr, 0, (uint16_t*)net->dz[1 - cur], K, 0.f};
+            st = launch_gemm(dx, s);
+            if (st != BM_OK) return st;
+            cur = 1 - cur;
+        }
+    }
+    return BM_OK;
+}
+
+extern "C" int bm_adam_step(const bm_mlp* net, float lr, float beta1, float beta2, float eps, int step,
+                            void* stream) {
+    int st = check_mlp(net, 0);
+    if (st != BM_OK) return st;
+    if (step < 1) return BM_EINVAL;
+    // bias corrections in double: 1 - beta^t cancels badly in float for beta near 1
+    const float c1 = (float)(1.0 - std::pow((double)beta1, step));
+    const float c2 = (float)(1.0 - std::pow((double)beta2, step));
+    hipStream_t s = (hipStream_t)stream;
+    for (int i = 0; i < net->n_layers; ++i) {
+        if (!net->w32[i] || !net->gw[i] || !net->mw[i] || !net->vw[i] || !net->gb[i] || !net->mb[i] || !net->vb[i])
+            return BM_EINVAL;
+        const int64_t nw = (int64_t)net->dims[i + 1] * net->dims[i];
+        const int64_t nb = net->dims[i + 1];
+        hipLaunchKernelGGL(k_adam, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, s, net->w32[i],
+                           (uint16_t*)net->w16[i], net->gw[i], net->mw[i], net->vw[i], nw, lr, beta1, beta2, eps, c1,
+                           c2);
+        hipLaunchKernelGGL(k_adam, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, net->b32[i],
+                           (uint16_t*)nullptr, net->gb[i], net->mb[i], net->vb[i], nb, lr, beta1, beta2, eps, c1, c2);
+        BM_CHECK_HIP(hipGetLastError());
+    }
+    return BM_OK;
+}
+
+extern "C" int bm_mlp_sync_bf16(const bm_mlp* net, void* stream) {
+    int st = check_mlp(net, 0);
+    if (st != BM_OK) return st;
+    for (int i = 0; i < net->n_layers; ++i) {
+        if (!net->w32[i]) return BM_EINVAL;
+        const int64_t nw = (int64_t)net->dims[i + 1] * net->dims[i];
+        hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+                           net->w32[i], (uint16_t*)net->w16[i], nw);
+        BM_CHECK_HIP(hipGetLastError());
+    }
+    return BM_OK;
+}
+
+extern "C" int bm_surrogate_chi2(const float* out, int B, int N, const double* mean, const double* scale,
+                                 const double* data, const double* err, double* chi2, void* stream) {
+    if (!out || !mean || !scale || !data || !err || !chi2) return BM_EINVAL;
+    if (B < 0 || N < 1) return BM_ESHAPE;
+    if (B == 0) return BM_OK;
+    hipLaunchKernelGGL(k_surrogate_chi2, dim3(B), dim3(256), 0, (hipStream_t)stream, out, B, N, mean, scale, data,
+                       err, chi2);
+    BM_CHECK_HIP(hipGetLastError());
+    return BM_OK;
+}

@@ -14,7 +14,7 @@ import ctypes as C
 import numpy as np
 import torch
 
-from . import (BmDemcz, Forward, _check, _ptr, _stream, lib)
+from . import (BartmiError, BmDemcz, BmModel, Forward, _check, _ptr, _stream, lib)
 
 
 class DEMCz:
@@ -69,6 +69,18 @@ class DEMCz:
     def da_accept(self, chi2, flags, chi2_surr, active, stream=None):
         self._r("bm_da_accept", _ptr(chi2), _ptr(flags), _ptr(chi2_surr), _ptr(active), stream=stream)
 
+    def load_state(self, x: torch.Tensor, archive: torch.Tensor, generation: int = 0):
+        """Chain states and archive from elsewhere (e.g. a burn-in run); the log posteriors
+        must be set again (set_lp) before the next generation."""
+        m = archive.shape[0]
+        if tuple(x.shape) != tuple(self.x.shape) or archive.shape[1] != self.d:
+            raise BartmiError("state shapes do not match the sampler")
+        if not 2 <= m <= self.z_cap:
+            raise BartmiError("archive must hold 2..z_cap rows")
+        self.x.copy_(x)
+        self.z[:m].copy_(archive)
+        self.counters.copy_(torch.tensor([generation, m], dtype=torch.int64))
+
     @property
     def generation(self) -> int:
         return int(self.counters[0])
@@ -78,16 +90,71 @@ class DEMCz:
         return int(self.counters[1])
 
 
+class PerSampleForward:
+    """The plain per-sample form of the forward model: one bm_forward_batch call per
+    chain (B = 1), as BART runs one forward-model worker per chain, spread round-robin
+    over ``workers`` streams with a workspace each. Same outputs as Forward(model, C,
+    binned=True, chi2=True), written in place per sample."""
+
+    def __init__(self, model, n_chains: int, workers: int = 1, device="cuda"):
+        self.model, self.B, self.W = model, n_chains, workers
+        self._structs = (BmModel * 1)(model.struct)
+        self.n_nu, self.n_bins = model.n_nu, model.n_bins
+        self.depth = torch.empty(n_chains * self.n_nu, dtype=torch.float64, device=device)
+        self.binned = torch.empty(n_chains * self.n_bins, dtype=torch.float64, device=device)
+        self.chi2 = torch.empty(n_chains, dtype=torch.float64, device=device)
+        self.flags = torch.empty(n_chains, dtype=torch.int32, device=device)
+        ws = int(lib().bm_workspace_size(self._structs, 1, None, 1))
+        if ws == 0:
+            raise BartmiError("bm_workspace_size rejected the model")
+        self.ws_bytes = ws
+        self.workspaces = [torch.zeros(ws, dtype=torch.uint8, device=device) for _ in range(workers)]
+        self.streams = [torch.cuda.Stream() for _ in range(workers - 1)]
+
+    def __call__(self, params: torch.Tensor, stream=None):
+        if params.shape[0] != self.B or params.dtype != torch.float64 or not params.is_contiguous():
+            raise BartmiError("params must be a contiguous float64 [B][P] device tensor")
+        main = stream if stream is not None else torch.cuda.current_stream()
+        streams = [main] + self.streams
+        for s_ in self.streams:
+            s_.wait_stream(main)
+        P = params.shape[1]
+        fn = lib().bm_forward_batch
+        p0, d0, b0 = _ptr(params).value, _ptr(self.depth).value, _ptr(self.binned).value
+        c0, f0 = _ptr(self.chi2).value, _ptr(self.flags).value
+        wsp = [_ptr(w).value for w in self.workspaces]
+        for c in range(self.B):
+            w = c % self.W
+            st = fn(self._structs, 1, None, C.c_void_p(p0 + 8 * P * c), P, 1, None,
+                    C.c_void_p(d0 + 8 * self.n_nu * c),
+                    C.c_void_p(b0 + 8 * self.n_bins * c) if self.n_bins else None,
+                    C.c_void_p(c0 + 8 * c), C.c_void_p(f0 + 4 * c), C.c_void_p(wsp[w]),
+                    C.c_size_t(self.ws_bytes), C.c_void_p(streams[w].cuda_stream))
+            if st != 0:
+                _check(st, "bm_forward_batch")
+        for s_ in self.streams:
+            main.wait_stream(s_)
+        return self
+
+
 class Retrieval:
     """A DE-MCz retrieval of one model's observation (model.data / model.err set).
 
     ``surrogate`` (optional) maps a [C][d] parameter tensor to a [C] surrogate chi^2 on
-    the same stream; it enables two-stage delayed acceptance."""
+    the same stream; it enables two-stage delayed acceptance. ``per_sample_workers`` > 0
+    selects the plain per-sample form (PerSampleForward) instead of one batched call per
+    generation."""
 
     def __init__(self, model, n_chains: int, lo, hi, seed: int, thin: int = 10,
-                 hist_cap: int = 0, surrogate=None, eps_scale: float = 1e-6, z_cap=None):
+                 hist_cap: int = 0, surrogate=None, eps_scale: float = 1e-6, z_cap=None,
+                 per_sample_workers: int = 0):
         self.model = model
-        self.fwd = Forward(model, n_chains, binned=True, chi2=True)
+        if per_sample_workers:
+            if surrogate is not None:
+                raise BartmiError("the per-sample form has no surrogate stage")
+            self.fwd = PerSampleForward(model, n_chains, per_sample_workers)
+        else:
+            self.fwd = Forward(model, n_chains, binned=True, chi2=True)
         self.s = DEMCz(n_chains, lo, hi, seed, thin=thin, hist_cap=hist_cap, z_cap=z_cap,
                        eps_scale=eps_scale, surrogate=surrogate is not None)
         self.surrogate = surrogate
@@ -95,6 +162,20 @@ class Retrieval:
 
     def start(self, z_init: int | None = None):
         self.s.init(z_init)
+        self._set_lp()
+
+    def resume(self, x: torch.Tensor, archive: torch.Tensor):
+        """Continue from given chain states and archive (e.g. after a burn-in)."""
+        self.s.load_state(x, archive)
+        self._set_lp()
+
+    def reset_archive(self):
+        """Replace the archive by the current chain states: drops the wide early states of
+        a burn-in so that the difference vectors shrink to the current spread."""
+        self.s.load_state(self.s.x.clone(), self.s.x.clone(), self.s.generation)
+        self._set_lp()
+
+    def _set_lp(self):
         self.fwd(self.s.x)
         chi2_s = self.surrogate(self.s.x) if self.surrogate is not None else None
         self.s.set_lp(self.fwd.chi2, self.fwd.flags, chi2_s)
@@ -125,3 +206,45 @@ class Retrieval:
                 self.run(n_gen)
         torch.cuda.current_stream().wait_stream(side)
         return g
+
+
+def fisher_covariance(model, theta, lo, hi, rel_step: float = 1e-4) -> np.ndarray:
+    """Gaussian (Laplace) approximation of the posterior covariance at theta from the
+    binned-spectrum Jacobian: (J^T diag(1/err^2) J + diag(12/width^2))^-1, J by central
+    differences from one batched forward call of 2d + 1 spectra. The diagonal term is the
+    variance of the uniform prior and keeps unconstrained directions at prior width."""
+    lo = np.asarray(lo, np.float64)
+    hi = np.asarray(hi, np.float64)
+    theta = np.asarray(theta, np.float64).ravel()
+    d = theta.size
+    width = hi - lo
+    step = rel_step * width
+    pts = np.repeat(theta[None], 2 * d + 1, axis=0)
+    for j in range(d):
+        pts[1 + 2 * j, j] += step[j]
+        pts[2 + 2 * j, j] -= step[j]
+    f = Forward(model, 2 * d + 1, binned=True)
+    f(torch.as_tensor(pts, device=model.sigma.device))
+    nb = model.n_bins
+    y = f.binned.view(2 * d + 1, nb).cpu().numpy()
+    if int((f.flags != 0).sum()):
+        raise BartmiError("the forward model flagged a point of the Jacobian stencil")
+    jac = np.stack([(y[1 + 2 * j] - y[2 + 2 * j]) / (2 * step[j]) for j in range(d)], axis=1)
+    err = model.err.cpu().numpy()
+    jw = jac / err[:, None]
+    prec = jw.T @ jw + np.diag(12.0 / width ** 2)
+    return np.linalg.inv(prec)
+
+
+def gaussian_states(mean, cov, n: int, lo, hi, seed: int, inflate: float = 1.0) -> np.ndarray:
+    """n draws from N(mean, inflate^2 cov), redrawn until inside the prior box."""
+    g = np.random.default_rng(seed)
+    lo = np.asarray(lo, np.float64)
+    hi = np.asarray(hi, np.float64)
+    chol = np.linalg.cholesky(cov) * inflate
+    out = np.empty((0, lo.size))
+    while out.shape[0] < n:
+        x = np.asarray(mean, np.float64)[None] + g.normal(size=(2 * n, lo.size)) @ chol.T
+        x = x[np.all((x >= lo) & (x <= hi), axis=1)]
+        out = np.vstack([out, x])
+    return out[:n]

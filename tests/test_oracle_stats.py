@@ -61,3 +61,24 @@ def test_gelman_rubin():
     assert np.all(np.abs(stats.gelman_rubin(same) - 1.0) < 0.01)
     shifted = same + np.arange(5)[:, None, None]
     assert np.all(stats.gelman_rubin(shifted) > 1.5)
+
+
+def test_product_diagnostics_match_oracle():
+    # the package's vectorised diagnostics against the oracle's per-chain definitions
+    from paper_2104_12522_amd import diagnostics as dg
+    g = np.random.default_rng(21)
+    n, m, d = 400, 5, 3
+    hist = np.empty((n, m, d))
+    x = g.normal(size=(m, d))
+    phi = np.array([0.0, 0.6, 0.95])
+    for t in range(n):
+        x = phi * x + np.sqrt(1 - phi ** 2) * g.normal(size=(m, d))
+        hist[t] = x
+    chains = hist.transpose(1, 0, 2)           # oracle layout [chain][step][param]
+    for c in range(m):
+        for p in range(d):
+            assert dg.speis_per_chain(hist)[c, p] == pytest.approx(
+                stats.speis_chain(chains[c, :, p]), rel=1e-10)
+    assert dg.speis(hist) == pytest.approx(stats.speis(chains), rel=1e-10)
+    assert dg.ess(hist) == pytest.approx(stats.ess(chains), rel=1e-10)
+    np.testing.assert_allclose(dg.gelman_rubin(hist), stats.gelman_rubin(chains), rtol=1e-12)
