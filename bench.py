@@ -1,27 +1,33 @@
-"""Benchmark of the transmission forward model on one MI355X.
+"""Benchmark of the transmission forward model and the retrieval built on it, one MI355X.
 
-Workload (the "full single forward model" configuration): 4 absorbers with opacity
-tables on 20 temperatures (300-3000 K) x 100 log-spaced layers (1e-8--100 bar) x 30000
-wavenumbers (0.5 cm^-1 from 1000 cm^-1) in float32, a 20 x 30000 H2-H2 CIA table, the
-five-parameter T(p) profile, one spectrum per call. A step is one bm_forward_batch call
-with B = 1: atmosphere, extinction, chord optical depth, transit depth (steps a1-a5),
-and 30-point channel binning with chi^2 against a synthetic observation (a6). Every
-step uses a different prior draw, so consecutive calls read different table rows.
+Headline (``forward``): the full single forward model, one spectrum per call, back to
+back on one stream. 4 absorbers with opacity tables on 20 temperatures (300-3000 K) x
+100 log-spaced layers (1e-8--100 bar) x 30000 wavenumbers (0.5 cm^-1 from 1000 cm^-1) in
+float32, built by the library's line-by-line opacity build (1e5-1e6 synthetic lines per
+absorber), a 20 x 30000 H2-H2 CIA table, the five-parameter T(p) profile. A step is one
+bm_forward_batch call with B = 1: atmosphere, extinction, chord optical depth, transit
+depth (a1-a5), 30-point channels and chi^2 against a synthetic observation (a6); every
+step uses a different prior draw. ``roofline`` is for the fused kernel, timed per launch
+with HIP events on its stream (bm_timing_start/stop).
 
-BART runs one forward-model worker per MCMC chain, all sharing one copy of the opacity
-table (Sec. 3; Sec. 4 items 8-9). The benchmark does the same: ``--workers`` concurrent
-callers, each on its own HIP stream with its own workspace and outputs, each issuing
-one-spectrum calls back to back (step i goes to worker i mod W). ``value`` is the
-aggregate spectra/s over the timed steps; a single-stream figure is reported beside it.
-
-Inputs are resident in HBM before timing starts. Tables come from the library's own
-line-by-line opacity build (``--table opacity``, default) or from the seeded random
-generator (``--table random``). One JSON line goes to stdout.
+Further sections, each reported in its own object of the same JSON line:
+  batched   256 DE-MCz chains per generation in one graph-captured launch sequence, and a
+            mixed batch of three instances (60/100/150 layers, 8000/30000/50000
+            wavenumbers) fused in one launch; launch configurations autotuned.
+  mcmc      the learned surrogate (MLP 10 -> 4 x 512 -> 1000, BF16) trained on forward-model
+            spectra, as stage 1 of delayed acceptance in 256-chain DE-MCz, against the
+            plain per-sample forward model: effective samples/s and posterior agreement.
+  opacity   the line-by-line opacity-table build, 1e7 lines onto 1e5 wavenumbers x 20 T x
+            100 p (opt-in: --sections ...,opacity).
+Inputs are resident in HBM before any timed region. One JSON line goes to stdout;
+progress goes to stderr.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -33,12 +39,14 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+# ----------------------------------------------------------------------------- inputs
 def build_tables(setup, how: str, seed: int):
     import torch
     import workloads as wl
@@ -54,8 +62,490 @@ def build_tables(setup, how: str, seed: int):
         bm.opacity_table_build(lines, setup.temps, setup.p_bar, float(setup.nu[0]),
                                float(setup.nu[1] - setup.nu[0]), N, out=out[i])
         torch.cuda.synchronize()
-        log(f"opacity table species {i}: {n_lines} lines in {time.time() - t0:.2f} s")
+        log(f"opacity table {setup.name} species {i}: {n_lines} lines in {time.time() - t0:.2f} s")
     return out
+
+
+def make_model(setup, sigma, seed: int, truth=None):
+    """Model of one setup with a synthetic observation: the forward model at `truth` (a
+    prior draw when None) binned to 30-point channels plus 60 ppm Gaussian noise."""
+    import torch
+    import workloads as wl
+    import paper_2104_12522_amd as bm
+    cia = torch.as_tensor(wl.cia_table(setup.cia_temps, setup.nu), device="cuda")
+    nb = setup.nu.size // setup.bin_width
+    model = bm.Model(sigma, setup.temps, setup.p_bar, setup.mass_amu, setup.tp_mode,
+                     setup.planet, cia=cia, cia_temps=setup.cia_temps,
+                     bin_width=setup.bin_width, data=np.zeros(nb), err=np.full(nb, 60e-6))
+    prior = wl.line2013_prior(setup.n_species)
+    if truth is None:
+        truth = prior.draw(1, seed=seed + 2)[0]
+    f = bm.Forward(model, 1, binned=True)
+    f(torch.as_tensor(np.asarray(truth, np.float64)[None], device="cuda"))
+    noise = wl.rng(seed + 3).normal(0.0, 60e-6, nb)
+    model.set_observation(f.binned.cpu().numpy() + noise, np.full(nb, 60e-6))
+    return model, cia
+
+
+def spectrum_bytes(S, L, N, NTC, nb):
+    """Algorithmic HBM bytes of one spectrum: the two bracketing temperature rows of every
+    species table on every layer (float32), the CIA table once (double), the spectrum and
+    the channel means out (double)."""
+    return 4 * (2 * S * L * N) + 8 * NTC * N + 8 * N + 8 * nb
+
+
+def spectrum_flops(S, L, N):
+    """Algorithmic FP32 operations of one spectrum: the temperature interpolation and
+    density weighting (4 per species, layer and wavenumber), the chord optical depths
+    (2 per nonzero chord weight), 1 - exp(-tau) and the impact-parameter sum (~4 per
+    chord and wavenumber)."""
+    return N * (4 * S * L + L * (L + 1) + 4 * L)
+
+
+def traffic_from_profile(kernel_source: str):
+    """HBM bytes per launch of the fused kernel from the committed counter summary, if the
+    kernel source has not changed since the counters were taken (else None)."""
+    path = os.path.join(ROOT, "profiles", "forward_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    with open(kernel_source, "rb") as f:
+        digest = hashlib.sha256(f.read()).hexdigest()
+    if rec.get("kernel_sha256") != digest:
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+# ----------------------------------------------------------------------------- sections
+def section_forward(args, setup, model, prior):
+    """Headline: one spectrum per call on one stream."""
+    import torch
+    import paper_2104_12522_amd as bm
+    S, L, N = setup.n_species, setup.p_bar.size, setup.nu.size
+    NTC, nb = len(setup.cia_temps), N // setup.bin_width
+    n_draw = args.warmup + args.steps
+    params = torch.as_tensor(prior.draw(n_draw, seed=args.seed + 1), device="cuda").contiguous()
+    rows = [params[i:i + 1] for i in range(n_draw)]
+    f = bm.Forward(model, 1, binned=True, chi2=True)
+    for i in range(args.warmup):
+        f(rows[i])
+    torch.cuda.synchronize()
+    log(f"forward: warmup {args.warmup} done, timing {args.steps} one-spectrum calls")
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        f(rows[args.warmup + i])
+    end.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = start.elapsed_time(end) / args.steps
+    # the fused kernel alone: the same calls again, each kernel launch between two events
+    with bm.KernelTiming(args.steps) as kt:
+        for i in range(args.steps):
+            f(rows[args.warmup + i])
+        torch.cuda.synchronize()
+    log(f"forward: {ms * 1e3:.2f} us per spectrum (events), {wall / args.steps * 1e6:.2f} us (host "
+        f"clock); fused kernel {kt.mean_ms * 1e3:.2f} us over {kt.launches} launches")
+    bytes_spec = spectrum_bytes(S, L, N, NTC, nb)
+    achieved = bytes_spec / (kt.mean_ms * 1e-3) / 1e9
+    traffic = traffic_from_profile(os.path.join(ROOT, "paper_2104_12522_amd", "csrc", "fwd_kernel.h"))
+    out = {
+        "ms_per_step": ms,
+        "value": 1000.0 / ms,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_forward (fused extinction, chord optical depth, depth, channels)",
+                     "bytes_per_launch": bytes_spec, "kernel_us": kt.mean_ms * 1e3,
+                     "launches_timed": kt.launches,
+                     "call_us": ms * 1e3,
+                     "call_frac": bytes_spec / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "last_flags": int(f.flags[0]),
+    }
+    if args.workers > 1:
+        out["multi_worker"] = multi_worker(args, model, rows)
+    return out
+
+
+def multi_worker(args, model, rows):
+    """BART's layout: one forward-model worker per chain, here W concurrent streams each
+    issuing one-spectrum calls (step i on worker i mod W)."""
+    import torch
+    import paper_2104_12522_amd as bm
+    W = args.workers
+    streams = [torch.cuda.current_stream()] + [torch.cuda.Stream() for _ in range(W - 1)]
+    fwds = [bm.Forward(model, 1, binned=True, chi2=True) for _ in range(W)]
+    for i in range(args.warmup):
+        fwds[i % W](rows[i], stream=streams[i % W])
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    main = streams[0]
+    start.record(main)
+    for s_ in streams[1:]:
+        s_.wait_event(start)
+    for i in range(args.steps):
+        fwds[i % W](rows[args.warmup + i], stream=streams[i % W])
+    for s_ in streams[1:]:
+        ev = torch.cuda.Event()
+        ev.record(s_)
+        main.wait_event(ev)
+    end.record(main)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end) / args.steps
+    log(f"forward, {W} workers: {ms * 1e3:.2f} us per spectrum")
+    return {"workers": W, "value": 1000.0 / ms, "ms_per_step": ms}
+
+
+def graph_time(fn, n_inner: int, n_replay: int):
+    """Capture fn() n_inner times in a HIP graph on a side stream, replay it n_replay
+    times; returns ms per fn() from events around the replays."""
+    import torch
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g, stream=side):
+            for _ in range(n_inner):
+                fn()
+    torch.cuda.current_stream().wait_stream(side)
+    g.replay()
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(n_replay):
+        g.replay()
+    end.record()
+    torch.cuda.synchronize()
+    return start.elapsed_time(end) / (n_inner * n_replay)
+
+
+def section_batched(args, setup, model, prior):
+    """256 chains per DE-MCz generation, graph-captured; mixed-instance batch."""
+    import torch
+    import workloads as wl
+    import paper_2104_12522_amd as bm
+    from paper_2104_12522_amd.mcmc import Retrieval
+    S, L, N = setup.n_species, setup.p_bar.size, setup.nu.size
+    NTC, nb = len(setup.cia_temps), N // setup.bin_width
+    C = args.chains
+    cfg_names = bm.forward_configs()
+    r = Retrieval(model, C, prior.lo, prior.hi, seed=args.seed + 20, thin=10,
+                  z_cap=10 * prior.lo.size + C * (args.batched_gens // 10 + 20))
+    r.start()
+    chosen, times = r.fwd.tune(r.s.x.contiguous(), reps=3)
+    log(f"batched: autotuned {C}-chain forward -> config {chosen} ({cfg_names[chosen]}); "
+        f"ms per call {[round(t, 3) for t in times]}")
+    r.start()
+    # forward only: one B = C call per graph node, replayed
+    x = r.s.x.contiguous()
+    ms_fwd = graph_time(lambda: r.fwd(x), 10, max(1, args.batched_gens // 10))
+    with bm.KernelTiming(20) as kt:
+        for _ in range(20):
+            r.fwd(x)
+        torch.cuda.synchronize()
+    bytes_gen = C * spectrum_bytes(S, L, N, NTC, nb)
+    flops_gen = C * spectrum_flops(S, L, N)
+    # whole generations (propose, forward, accept) captured in one graph
+    r.start()
+    ms_gen = graph_time(r.generation, 10, max(1, args.batched_gens // 10))
+    log(f"batched: {ms_fwd:.3f} ms per {C}-spectrum forward call, {ms_gen:.3f} ms per generation, "
+        f"fused kernel {kt.mean_ms:.3f} ms")
+    out = {
+        "chains": C,
+        "autotune": {"chosen": chosen, "configs": cfg_names, "ms_per_call": times},
+        "forward_ms_per_call": ms_fwd,
+        "spectra_per_s": C / (ms_fwd * 1e-3),
+        "generation_ms": ms_gen,
+        "generation_spectra_per_s": C / (ms_gen * 1e-3),
+        "kernel_ms": kt.mean_ms,
+        "hbm_equiv": {"achieved": bytes_gen / (kt.mean_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                      "unit": "GB/s", "note": "algorithmic bytes as if every spectrum streamed "
+                                              "its table rows from HBM; chains of a tile share "
+                                              "rows through L2"},
+        "fp32": {"achieved": flops_gen / (kt.mean_ms * 1e-3) / 1e12, "peak": FP32_PEAK_TFLOPS,
+                 "unit": "TFLOP/s"},
+    }
+    if args.mixed:
+        out["mixed"] = section_mixed(args, prior)
+    return out
+
+
+def section_mixed(args, prior):
+    import torch
+    import workloads as wl
+    import paper_2104_12522_amd as bm
+    setups = wl.config3_mixed()
+    models = []
+    for k, s in enumerate(setups):
+        sig = build_tables(s, args.table, args.seed + 100 * (k + 1))
+        m, _ = make_model(s, sig, args.seed + 100 * (k + 1))
+        models.append(m)
+    C = args.chains
+    inst = [min(k * len(setups) // C, len(setups) - 1) for k in range(C)]   # contiguous thirds
+    params = torch.as_tensor(prior.draw(C, seed=args.seed + 30), device="cuda").contiguous()
+    f = bm.Forward(models, C, instance=inst, binned=True, chi2=True)
+    chosen, times = f.tune(params, reps=3)
+    ms = graph_time(lambda: f(params), 5, 10)
+    with bm.KernelTiming(10) as kt:
+        for _ in range(10):
+            f(params)
+        torch.cuda.synchronize()
+    bytes_call = sum(spectrum_bytes(s.n_species, s.p_bar.size, s.nu.size, len(s.cia_temps),
+                                    s.nu.size // s.bin_width) for s in (setups[i] for i in inst))
+    log(f"mixed batch: {ms:.3f} ms per call of {C} spectra over {len(setups)} instances "
+        f"(config {chosen}); fused kernel {kt.mean_ms:.3f} ms")
+    return {"instances": [{"n_layers": int(s.p_bar.size), "n_nu": int(s.nu.size),
+                           "dnu": float(s.nu[1] - s.nu[0]), "samples": int(inst.count(k))}
+                          for k, s in enumerate(setups)],
+            "launches_per_call": 1, "ms_per_call": ms, "spectra_per_s": C / (ms * 1e-3),
+            "kernel_ms": kt.mean_ms,
+            "hbm_equiv_gbs": bytes_call / (kt.mean_ms * 1e-3) / 1e9,
+            "autotune": {"chosen": chosen, "ms_per_call": times}}
+
+
+def section_mcmc(args, setup, prior):
+    """Learned surrogate + delayed acceptance against the plain per-sample forward model."""
+    import torch
+    import paper_2104_12522_amd as bm
+    from paper_2104_12522_amd import diagnostics as dg
+    from paper_2104_12522_amd.mcmc import (Retrieval, fisher_covariance, gaussian_states)
+    from paper_2104_12522_amd.surrogate import (MLP, Surrogate, Trainer, standardisation,
+                                                training_set)
+    sigma = args._sigma
+    truth = np.array([-1.5, -0.6, 0.2, 0.3, 0.9, -3.5, -4.0, -5.0, -6.0, 1.15])
+    model, _ = make_model(setup, sigma, args.seed + 50, truth=truth)
+    C, G, BURN = args.chains, args.mcmc_gens, args.mcmc_burn
+    nb = model.n_bins
+    d = prior.lo.size
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), device="cuda")  # noqa: E731
+    lo_p, hi_p = dev(prior.lo), dev(prior.hi)
+
+    def run_graph(r, n_gen, chunk=50):
+        g_ = r.capture(chunk)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(n_gen // chunk):
+            g_.replay()
+            if i % 40 == 39:
+                torch.cuda.synchronize()
+                log(f"mcmc: {(i + 1) * chunk} / {n_gen} generations")
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    def train(net, lo, hi, X, Y, mean, scale, epochs, lr0, seed):
+        tr = Trainer(net, lo, hi, X, Y, mean, scale, batch=512, seed=seed)
+        for e in range(epochs):
+            tr.epoch(1e-6 + 0.5 * (lr0 - 1e-6) * (1 + math.cos(math.pi * e / epochs)))
+
+    def spectra(xs):
+        n = xs.shape[0]
+        Y = torch.empty(n, nb, dtype=torch.float64, device="cuda")
+        fw = None
+        for s0 in range(0, n, 4096):
+            m = min(4096, n - s0)
+            if fw is None or fw.B != m:
+                fw = bm.Forward(model, m, binned=True)
+            fw(xs[s0:s0 + m].contiguous())
+            Y[s0:s0 + m] = fw.binned.view(m, nb)
+        return Y
+
+    def rms_ppm(sur, xs, ys):
+        pred = sur.mean + sur.scale * sur.predict(xs).double()
+        return float(torch.sqrt(((pred - ys) ** 2).mean())) * 1e6
+
+    # 1. surrogate on prior draws (2e5 spectra from the forward model)
+    t0 = time.perf_counter()
+    X, Y = training_set(model, prior, args.train_spectra + 5000, seed=args.seed + 60)
+    Xte, Yte = X[-5000:].contiguous(), Y[-5000:].contiguous()
+    X, Y = X[:-5000].contiguous(), Y[:-5000].contiguous()
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    mean, scale = standardisation(Y)
+    dims = [d, 512, 512, 512, 512, nb]
+    net = MLP(dims, max_batch=5000, seed=1)
+    t0 = time.perf_counter()
+    train(net, lo_p, hi_p, X, Y, mean, scale, args.epochs, 1e-3, 2)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    sur_p = Surrogate(net, lo_p, hi_p, mean, scale, model.data, model.err, n_chains=5000)
+    rms_prior = rms_ppm(sur_p, Xte, Yte)
+    log(f"mcmc: prior surrogate: {X.shape[0]} spectra in {t_data:.1f} s, {args.epochs} epochs in "
+        f"{t_train:.1f} s ({net.step} Adam steps), held-out rms {rms_prior:.2f} ppm")
+    del X, Y
+
+    # 2. burn-in with the exact sampler from the Laplace approximation at the truth
+    cov = fisher_covariance(model, truth, prior.lo, prior.hi)
+    x_init = dev(gaussian_states(truth, cov, C, prior.lo, prior.hi, seed=args.seed + 61))
+    z_init = dev(gaussian_states(truth, cov, 10 * C, prior.lo, prior.hi, seed=args.seed + 62))
+    rb = Retrieval(model, C, prior.lo, prior.hi, seed=args.seed + 63, thin=10, hist_cap=BURN,
+                   z_cap=10 * C + C * (BURN // 10 + 2))
+    rb.resume(x_init, z_init)
+    t_burn = run_graph(rb, BURN)
+    hb = rb.s.history[BURN // 2:BURN].cpu().numpy().reshape(-1, d)
+    mu_b, cov_b = hb.mean(0), np.cov(hb.T)
+    sd_b = np.sqrt(np.diag(cov_b))
+    x0 = rb.s.x.clone()
+    m = rb.s.archive_size
+    z0 = rb.s.z[max(0, m - 10 * C):m].clone()
+    log(f"mcmc: burn-in {BURN} generations in {t_burn:.1f} s")
+    post_np = hb[np.random.default_rng(args.seed + 64).choice(hb.shape[0], 2048, replace=False)]
+    post_x = dev(post_np)
+    post_y = spectra(post_x)
+    rms_prior_post = rms_ppm(sur_p, post_x, post_y)
+
+    # 3. local surrogate: inputs on a +-5 sd box around the burn-in states, outputs
+    #    standardised on spectra drawn around them (BF16 inputs resolve ~1/256 of the box)
+    t0 = time.perf_counter()
+    lo_l = np.maximum(mu_b - 5 * sd_b, prior.lo)
+    hi_l = np.minimum(mu_b + 5 * sd_b, prior.hi)
+    Xl = dev(gaussian_states(mu_b, cov_b, args.local_spectra, lo_l, hi_l, seed=args.seed + 65,
+                             inflate=2.0))
+    Yl = spectra(Xl)
+    mean_l, scale_l = standardisation(Yl)
+    net_l = MLP(dims, max_batch=5000, seed=3)
+    train(net_l, dev(lo_l), dev(hi_l), Xl, Yl, mean_l, scale_l, args.epochs, 1e-3, 4)
+    torch.cuda.synchronize()
+    t_local = time.perf_counter() - t0
+    sur = Surrogate(net_l, dev(lo_l), dev(hi_l), mean_l, scale_l, model.data, model.err,
+                    n_chains=5000)
+    rms_local = rms_ppm(sur, post_x, post_y)
+    fw = bm.Forward(model, C, binned=True, chi2=True)
+    fw(post_x[:C].contiguous())
+    dchi2 = (sur(post_x[:C].contiguous()) - fw.chi2).cpu().numpy()
+    log(f"mcmc: local surrogate in {t_local:.1f} s; rms near the posterior: prior-trained "
+        f"{rms_prior_post:.2f} ppm, local {rms_local:.2f} ppm")
+    del Xl, Yl
+
+    # 4. production runs from the same burned-in state and random stream
+    def production(surrogate=None, per_sample=0, n_gen=G):
+        r = Retrieval(model, C, prior.lo, prior.hi, seed=args.seed + 70, thin=10, hist_cap=n_gen,
+                      surrogate=surrogate, per_sample_workers=per_sample,
+                      z_cap=z0.shape[0] + C * (n_gen // 10 + 1))
+        r.resume(x0, z0)
+        torch.cuda.synchronize()
+        if per_sample:
+            t0_ = time.perf_counter()
+            r.run(n_gen)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0_
+        else:
+            wall = run_graph(r, n_gen)
+        h = r.s.history[:n_gen]
+        acc = r.s.n_accept.sum(0).cpu().numpy() / (C * n_gen)
+        return r, h, wall, acc
+
+    def stats(h, wall, acc, n_gen, **extra):
+        hn = h.cpu().numpy()
+        sp = dg.speis_per_chain(hn)
+        ess = hn.shape[0] * hn.shape[1] / sp.max()
+        mu, sd = dg.marginal_summary(hn)
+        out = {"generations": n_gen, "wall_s": wall, "ms_per_generation": wall / n_gen * 1e3,
+               "acceptance": float(acc[1]), "speis_max": float(sp.max()),
+               "speis_median": float(np.median(sp)), "ess": float(ess),
+               "ess_per_s": float(ess / wall),
+               "gelman_rubin_max": float(dg.gelman_rubin(hn).max())}
+        out.update(extra)
+        return out, mu, sd
+
+    log(f"mcmc: plain batched production, {G} generations")
+    _, h_b, w_b, acc_b = production()
+    plain_b, mu_b2, sd_b2 = stats(h_b, w_b, acc_b, G)
+    log(f"mcmc: delayed-acceptance production, {G} generations")
+    _, h_d, w_d, acc_d = production(surrogate=sur)
+    da, mu_d, sd_d = stats(h_d, w_d, acc_d, G, stage1_pass_rate=float(acc_d[0]))
+    log(f"mcmc: plain per-sample, {args.per_sample_gens} generations timed")
+    _, h_p, w_p, _ = production(per_sample=1, n_gen=args.per_sample_gens)
+    identical = bool(torch.equal(h_p, h_b[:args.per_sample_gens]))
+    ms_ps = w_p / args.per_sample_gens * 1e3
+    # the per-sample form computes the same chains (checked above on the timed slice), so
+    # its ESS over G generations is the batched plain run's
+    ps_wall = ms_ps * 1e-3 * G
+    plain_ps = {"ms_per_generation": ms_ps, "timed_generations": args.per_sample_gens,
+                "chains_identical_to_batched": identical, "ess": plain_b["ess"],
+                "ess_per_s": plain_b["ess"] / ps_wall}
+    diff = (mu_d - mu_b2) / sd_b2
+    ratio = da["ess_per_s"] / plain_ps["ess_per_s"]
+    # end to end: surrogate data and training charged to the delayed-acceptance run
+    e2e = (da["ess"] / (w_d + t_local)) / (plain_b["ess"] / ps_wall)
+    log(f"mcmc: ESS/s per-sample {plain_ps['ess_per_s']:.2f}, batched {plain_b['ess_per_s']:.2f}, "
+        f"delayed acceptance {da['ess_per_s']:.2f} -> {ratio:.1f}x; max |mean diff| "
+        f"{np.abs(diff).max():.3f} sd")
+    return {
+        "chains": C, "burn_in": BURN, "truth": truth.tolist(),
+        "surrogate": {"dims": dims, "dtype": "bf16 weights/activations, fp32 accumulate",
+                      "train_spectra": args.train_spectra, "epochs": args.epochs,
+                      "data_s": t_data, "train_s": t_train, "adam_steps": net.step,
+                      "rms_ppm_prior_heldout": rms_prior,
+                      "rms_ppm_near_posterior": rms_prior_post,
+                      "local": {"train_spectra": args.local_spectra, "s": t_local,
+                                "rms_ppm_near_posterior": rms_local,
+                                "chi2_error_mean": float(dchi2.mean()),
+                                "chi2_error_sd": float(dchi2.std())}},
+        "plain_per_sample": plain_ps,
+        "plain_batched": plain_b,
+        "delayed_acceptance": da,
+        "ess_per_s_ratio_vs_per_sample": ratio,
+        "ess_per_s_ratio_vs_batched": da["ess_per_s"] / plain_b["ess_per_s"],
+        "ess_per_s_ratio_end_to_end": e2e,
+        "marginal_mean_diff_sd": diff.tolist(),
+        "max_abs_mean_diff_sd": float(np.abs(diff).max()),
+        "marginal_mean": {"plain": mu_b2.tolist(), "delayed_acceptance": mu_d.tolist()},
+        "marginal_sd": {"plain": sd_b2.tolist(), "delayed_acceptance": sd_d.tolist()},
+    }
+
+
+def section_opacity(args):
+    """Line-by-line opacity build: 1e7 lines, 1e5 nu x 20 T x 100 p, float32, 25 HWHM."""
+    import torch
+    import workloads as wl
+    import paper_2104_12522_amd as bm
+    nu, temps, p_bar = wl.config4_grid()
+    n_lines = args.opacity_lines
+    t0 = time.time()
+    lines = wl.config4_lines(n_lines)
+    log(f"opacity: {n_lines} lines generated in {time.time() - t0:.1f} s")
+    out = torch.empty(len(temps), len(p_bar), nu.size, dtype=torch.float32, device="cuda")
+    dnu = float(nu[1] - nu[0])
+    bm.opacity_table_build(lines.subset(slice(0, 1000)), temps, p_bar, float(nu[0]), dnu, nu.size,
+                           out=out)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record()
+    bm.opacity_table_build(lines, temps, p_bar, float(nu[0]), dnu, nu.size, out=out)
+    end.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end)
+    log(f"opacity: build in {ms / 1e3:.2f} s")
+    return {"lines": n_lines, "n_nu": int(nu.size), "n_temp": int(len(temps)),
+            "n_p": int(len(p_bar)), "dtype": "f32 out, f64 accumulation", "cutoff_hwhm": 25.0,
+            "seconds": ms / 1e3, "output_gb": out.numel() * 4 / 1e9,
+            "lines_x_cells_per_s": n_lines * len(temps) * len(p_bar) / (ms * 1e-3)}
+
+
+def section_copy(args):
+    """A plain device copy of known size (1 GiB read + 1 GiB written), the reference that
+    scales the HBM byte counters of a profiling run."""
+    import torch
+    n = 1 << 28
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    y.copy_(x)
+    start.record()
+    for _ in range(3):
+        y.copy_(x)
+    end.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end) / 3
+    log(f"copy: {4 * n / 2**20:.0f} MiB in {ms:.3f} ms")
+    return {"bytes_read": 4 * n, "bytes_written": 4 * n, "ms": ms,
+            "gbs": 8 * n / (ms * 1e-3) / 1e9}
 
 
 def cpu_baseline(setup, sigma_np, cia_np, params, budget_s: float):
@@ -80,114 +570,78 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--table", choices=("opacity", "random"), default="opacity")
+    ap.add_argument("--sections", default="forward,batched,mcmc",
+                    help="comma list of forward, batched, mcmc, opacity, copy")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--seed", type=int, default=2104_12522 + 2)
-    ap.add_argument("--workers", type=int, default=4)
+    ap.add_argument("--workers", type=int, default=1,
+                    help="extra multi-stream figure with W concurrent one-spectrum callers")
+    ap.add_argument("--chains", type=int, default=256)
+    ap.add_argument("--batched-gens", type=int, default=200)
+    ap.add_argument("--no-mixed", dest="mixed", action="store_false")
+    ap.add_argument("--mcmc-gens", type=int, default=12000)
+    ap.add_argument("--mcmc-burn", type=int, default=1000)
+    ap.add_argument("--per-sample-gens", type=int, default=200)
+    ap.add_argument("--train-spectra", type=int, default=200000)
+    ap.add_argument("--local-spectra", type=int, default=100000)
+    ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--opacity-lines", type=int, default=10_000_000)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU; multi-GPU runs are not "
                                    "part of this build (the forward model shards by chain or "
-                                   "by wavenumber range, see DESIGN.md)", "n_gpus": args.gpus}))
+                                   "by wavenumber range)", "n_gpus": args.gpus}))
         sys.exit(2)
+    sections = [s.strip() for s in args.sections.split(",") if s.strip()]
 
     import torch
     import workloads as wl
-    import paper_2104_12522_amd as bm
 
     setup = wl.config2()
     S, L, N = setup.n_species, setup.p_bar.size, setup.nu.size
-    NT, NTC = len(setup.temps), len(setup.cia_temps)
+    NT = len(setup.temps)
+    prior = wl.line2013_prior(S)
     log(f"building tables ({args.table})")
     sigma = build_tables(setup, args.table, args.seed)
-    cia = torch.as_tensor(wl.cia_table(setup.cia_temps, setup.nu), device="cuda")
-    prior = wl.line2013_prior(S)
-    n_draw = args.warmup + args.steps
-    params_np = prior.draw(n_draw, seed=args.seed + 1)
-    # synthetic observation: the forward model at a fixed truth plus 60 ppm noise
-    truth = prior.draw(1, seed=args.seed + 2)
-    nb = N // setup.bin_width
-    model = bm.Model(sigma, setup.temps, setup.p_bar, setup.mass_amu, setup.tp_mode, setup.planet,
-                     cia=cia, cia_temps=setup.cia_temps, bin_width=setup.bin_width,
-                     data=np.zeros(nb), err=np.full(nb, 60e-6))
-    f_truth = bm.Forward(model, 1, binned=True)
-    f_truth(torch.as_tensor(truth, device="cuda"))
-    noise = wl.rng(args.seed + 3).normal(0.0, 60e-6, nb)
-    model.set_observation(f_truth.binned.cpu().numpy() + noise, np.full(nb, 60e-6))
+    args._sigma = sigma
+    model, cia = make_model(setup, sigma, args.seed)
 
-    params = torch.as_tensor(params_np, device="cuda").contiguous()
-    rows = [params[i:i + 1] for i in range(n_draw)]
-
-    def timed(n_workers):
-        streams = [torch.cuda.current_stream()] + [torch.cuda.Stream() for _ in range(n_workers - 1)]
-        fwds = [bm.Forward(model, 1, binned=True, chi2=True) for _ in range(n_workers)]
-        for i in range(args.warmup):
-            fwds[i % n_workers](rows[i], stream=streams[i % n_workers])
-        torch.cuda.synchronize()
-        start = torch.cuda.Event(enable_timing=True)
-        end = torch.cuda.Event(enable_timing=True)
-        main = streams[0]
-        start.record(main)
-        for s_ in streams[1:]:
-            s_.wait_event(start)
-        t0 = time.perf_counter()
-        for i in range(args.steps):
-            w = i % n_workers
-            fwds[w](rows[args.warmup + i], stream=streams[w])
-        for s_ in streams[1:]:
-            ev = torch.cuda.Event()
-            ev.record(s_)
-            main.wait_event(ev)
-        end.record(main)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        return start.elapsed_time(end) / args.steps, wall / args.steps * 1e3, int(fwds[0].flags[0])
-
-    log(f"warmup {args.warmup}, timing {args.steps} steps on {args.workers} workers")
-    ms, ms_wall, flags = timed(args.workers)
-    log(f"{ms * 1e3:.2f} us per spectrum (events), {ms_wall * 1e3:.2f} us (host clock)")
-    ms1 = None
-    if args.workers != 1:
-        ms1, _, _ = timed(1)
-        log(f"single stream: {ms1 * 1e3:.2f} us per spectrum")
-
-    # algorithmic HBM bytes of one spectrum: the two bracketing temperature rows of every
-    # species table on every layer, the CIA table at most once, the spectrum and bins out
-    bytes_spec = 4 * (2 * S * L * N) + 8 * NTC * N + 8 * N + 8 * nb
-    achieved = bytes_spec / (ms * 1e-3) / 1e9
-    out = {
-        "metric": "forward spectra/s (100 lyr x 30k nu)",
-        "value": 1000.0 / ms,
-        "unit": "spectra/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": "transmission forward model, 4 absorbers, 20 T x 100 layers x "
-                               "30000 nu float32 tables, H2-H2 CIA, Line-2013 T(p), 1 spectrum "
-                               "per call, 30-point bins + chi^2",
-                   "table": args.table, "batch_per_call": 1, "workers": args.workers,
-                   "n_layers": L, "n_nu": N, "n_species": S, "n_temp": NT},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "bytes_per_launch": bytes_spec,
-                     "timing": "HIP events around the timed loop / steps: aggregate over the "
-                               "workers, atmosphere and chi^2 kernels and launch gaps included"},
-        "single_stream": None if ms1 is None else {"value": 1000.0 / ms1, "ms_per_step": ms1},
-        "last_flags": flags,
-    }
-    if not args.no_cpu:
+    out = {"metric": "forward spectra/s (100 lyr x 30k nu)", "value": None, "unit": "spectra/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": None,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": "transmission forward model, 4 absorbers, 20 T x 100 layers x "
+                                  "30000 nu float32 tables, H2-H2 CIA, Line-2013 T(p), 1 spectrum "
+                                  "per call on one stream, 30-point bins + chi^2",
+                      "table": args.table, "batch_per_call": 1, "n_layers": L, "n_nu": N,
+                      "n_species": S, "n_temp": NT}}
+    if "forward" in sections:
+        fw = section_forward(args, setup, model, prior)
+        out["value"] = fw.pop("value")
+        out["ms_per_step"] = fw.pop("ms_per_step")
+        out["roofline"] = fw.pop("roofline")
+        out.update(fw)
+    if not args.no_cpu and "forward" in sections:
         log("timing the CPU oracle")
+        params_np = prior.draw(200, seed=args.seed + 1)
         sig_np = sigma.cpu().numpy().astype(np.float64)
         cia_np = cia.cpu().numpy().astype(np.float64)
         setup_cpu = wl.config2()
         setup_cpu.bin_width = 0
         out["cpu_baseline"] = cpu_baseline(setup_cpu, sig_np, cia_np, params_np, args.cpu_seconds)
+        del sig_np
+    if "batched" in sections:
+        out["batched"] = section_batched(args, setup, model, prior)
+    if "mcmc" in sections:
+        out["mcmc"] = section_mcmc(args, setup, prior)
+    if "copy" in sections:
+        out["copy"] = section_copy(args)
+    if "opacity" in sections:
+        del model, sigma
+        args._sigma = None
+        torch.cuda.empty_cache()
+        out["opacity"] = section_opacity(args)
     print(json.dumps(out), flush=True)
 
 

@@ -188,6 +188,42 @@ int bm_forward_batch(const bm_model* models, int n_models, const int32_t* instan
                      double* depth, double* binned, double* chi2, int32_t* flags,
                      void* workspace, size_t workspace_bytes, void* stream);
 
+/* ---- launch configurations and the autotuner --------------------------------------------
+ * The fused kernel of bm_forward_batch has several launch configurations (waves per
+ * workgroup; non-temporal or cached table loads). bm_forward_tune runs every
+ * configuration on this exact batch (same arguments as bm_forward_batch without
+ * `active`; it overwrites the outputs): one warm-up call, then `reps` calls timed with
+ * HIP events, and remembers the fastest for the batch signature (dtype, species count,
+ * CIA, and each run of samples: layers, wavenumbers, temperatures, bin width, count).
+ * Later bm_forward_batch calls with that signature use it; others use configuration 0.
+ * It waits for its events (host-synchronous) and refuses a stream under graph capture
+ * (BM_EINVAL): tune first, then capture. `chosen` (host, may be NULL) receives the chosen
+ * index, times_ms (host [n_times], may be NULL) the mean time per call of each
+ * configuration (-1 where it was not run: FP64 has configuration 0 only). */
+int bm_forward_config_count(void);
+const char* bm_forward_config_name(int config);   /* static string; NULL if out of range */
+int bm_forward_tune(const bm_model* models, int n_models, const int32_t* instance,
+                    const double* params, int param_stride, int B, double* depth,
+                    double* binned, double* chi2, int32_t* flags, void* workspace,
+                    size_t workspace_bytes, void* stream, int reps, int* chosen,
+                    float* times_ms, int n_times);
+/* Pin configuration `config` for the signature of this batch (as if the autotuner had
+ * chosen it); config -1 forgets the signature's entry. FP64 batches always run
+ * configuration 0. */
+int bm_forward_set_config(const bm_model* models, int n_models, const int32_t* instance, int B,
+                          int config);
+
+/* ---- kernel timing (measurement) ----------------------------------------------------------
+ * Between bm_timing_start(capacity) and bm_timing_stop, the first `capacity` launches of
+ * the fused forward kernel issued by bm_forward_batch outside graph capture each carry a
+ * pair of HIP timing events that the dispatch records at the kernel's start and end
+ * (hipExtLaunchKernel). bm_timing_stop waits for them and returns the summed kernel time
+ * (ms) and the number of launches timed. One
+ * session per process at a time (BM_EINVAL otherwise); the library creates and destroys
+ * the events. */
+int bm_timing_start(int capacity);
+int bm_timing_stop(double* total_ms, int64_t* launches);
+
 /* ---- DE-MCz sampler with delayed acceptance ----------------------------------------------
  * Sec. 3 and Sec. 5: MC3's differential-evolution samplers (DEMC, ter Braak 2006; the
  * archive-based DEMCzs, ter Braak & Vrugt 2008), here in archive form for a whole

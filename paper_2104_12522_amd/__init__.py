@@ -267,6 +267,27 @@ class Forward:
                "bm_forward_batch")
         return self
 
+    def tune(self, params: torch.Tensor, reps: int = 5, stream=None):
+        """Autotune the fused kernel's launch configuration for this batch (bm_forward_tune);
+        returns (chosen index, mean ms per call of every configuration). Overwrites the
+        outputs; call before capturing the batch in a graph."""
+        if params.shape[0] != self.B or params.dtype != torch.float64 or not params.is_contiguous():
+            raise BartmiError("params must be a contiguous float64 [B][P] device tensor")
+        n = lib().bm_forward_config_count()
+        chosen = C.c_int(-1)
+        times = (C.c_float * n)()
+        _check(lib().bm_forward_tune(self._structs, len(self.models), self._inst, _ptr(params),
+                                     params.shape[1], self.B, _ptr(self.depth), _ptr(self.binned),
+                                     _ptr(self.chi2), _ptr(self.flags), _ptr(self.workspace),
+                                     C.c_size_t(self.workspace.numel()), _stream(stream), reps,
+                                     C.byref(chosen), times, n), "bm_forward_tune")
+        return chosen.value, [float(t) for t in times]
+
+    def set_config(self, config: int):
+        """Pin a launch configuration for this batch (-1 returns to the default)."""
+        _check(lib().bm_forward_set_config(self._structs, len(self.models), self._inst, self.B,
+                                           config), "bm_forward_set_config")
+
     def spectrum(self, b: int) -> torch.Tensor:
         return self.depth[self.depth_off[b]:self.depth_off[b + 1]]
 
@@ -281,6 +302,37 @@ def forward_batch(models, params: torch.Tensor, instance=None, binned=False, chi
         params = params[None]
     f = Forward(models, params.shape[0], instance, binned=binned, chi2=chi2, device=params.device)
     return f(params, stream)
+
+
+def forward_configs() -> list[str]:
+    """Names of the fused kernel's launch configurations, by index."""
+    return [lib().bm_forward_config_name(i).decode() for i in range(lib().bm_forward_config_count())]
+
+
+class KernelTiming:
+    """Context manager around bm_timing_start/stop: the fused kernel's launches inside the
+    block are timed with HIP events on their streams. After the block, ``total_ms`` and
+    ``launches`` hold the summed kernel time and the number of launches timed."""
+
+    def __init__(self, capacity: int):
+        self.capacity = capacity
+        self.total_ms = 0.0
+        self.launches = 0
+
+    def __enter__(self):
+        _check(lib().bm_timing_start(self.capacity), "bm_timing_start")
+        return self
+
+    def __exit__(self, *exc):
+        tot = C.c_double(0.0)
+        n = C.c_int64(0)
+        _check(lib().bm_timing_stop(C.byref(tot), C.byref(n)), "bm_timing_stop")
+        self.total_ms, self.launches = tot.value, n.value
+        return False
+
+    @property
+    def mean_ms(self) -> float:
+        return self.total_ms / self.launches if self.launches else float("nan")
 
 
 # ------------------------------------------------------------------------------- opacity

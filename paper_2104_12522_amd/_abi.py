@@ -69,6 +69,13 @@ PROTOTYPES = {
     "bm_workspace_size": (C.c_size_t, [_PM, _I, C.POINTER(C.c_int32), _I]),
     "bm_forward_batch": (_I, [_PM, _I, C.POINTER(C.c_int32), _VP, _I, _I, _VP, _VP, _VP, _VP, _VP,
                               _VP, C.c_size_t, _VP]),
+    "bm_forward_config_count": (_I, []),
+    "bm_forward_config_name": (C.c_char_p, [_I]),
+    "bm_forward_tune": (_I, [_PM, _I, C.POINTER(C.c_int32), _VP, _I, _I, _VP, _VP, _VP, _VP, _VP,
+                             C.c_size_t, _VP, _I, C.POINTER(C.c_int), C.POINTER(C.c_float), _I]),
+    "bm_forward_set_config": (_I, [_PM, _I, C.POINTER(C.c_int32), _I, _I]),
+    "bm_timing_start": (_I, [_I]),
+    "bm_timing_stop": (_I, [C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "bm_demcz_init": (_I, [C.POINTER(BmDemcz), _I, _VP]),
     "bm_demcz_set_lp": (_I, [C.POINTER(BmDemcz), _VP, _VP, _VP, _VP]),
     "bm_demcz_propose": (_I, [C.POINTER(BmDemcz), _VP]),

@@ -1,6 +1,8 @@
 // Shared declarations of the forward-model kernels (internal).
 #pragma once
 
+#include <vector>
+
 #include "bm_internal.h"
 
 namespace bm {
@@ -164,6 +166,29 @@ __host__ __device__ inline size_t record_bytes_t(int S, int L, int tiles) {
 // host helpers (forward.hip)
 int validate_model(const bm_model& m, bool need_tables);
 ModelDev to_device_view(const bm_model& m);
+// raise a kernel's dynamic-LDS ceiling (once per kernel, device and size)
+int ensure_dynamic_lds(const void* fn, size_t bytes);
+
+// A batch split into launch plans of at most kMaxSegments same-model runs each.
+struct HostPlan {
+    std::vector<LaunchPlan> plans;
+    std::vector<int> first_sample;   // first sample of each plan
+    std::vector<int> n_samples;      // samples of each plan
+    size_t ws_bytes = 0;
+    int max_L = 0;
+    int n_species = 0;
+    bool cia = false;
+    int max_ntc = 0;          // largest CIA temperature grid (LDS staging rows)
+    int total_samples = 0;
+    size_t max_entries = 0;   // chord-weight entries of the largest record
+};
+
+// launch of the fused kernel for one plan with kW waves per workgroup and non-temporal
+// (kNT) or cached table loads (fwd_kernel.h); ev0/ev1 (or null) are timing events that
+// the dispatch itself records at the kernel's start and end
+template <typename T, int kW, bool kNT>
+int launch_k_forward(const HostPlan& hp, const LaunchPlan& lp, size_t lds, char* ws, const int32_t* act,
+                     double* depth, double* binned, double* c2, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1);
 
 template <typename T>
 __global__ void k_atm_prep(LaunchPlan plan, const double* __restrict__ params, int stride,

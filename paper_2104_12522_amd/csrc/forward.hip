@@ -1,334 +1,27 @@
-// Steps a3-a6 of the forward model on the GPU and the C-ABI entry points that expose
-// them: temperature interpolation of the opacity tables and extinction (Sec. 3,
-// Sec. 6.1.1), chord optical depth through spherical layers and the transit-depth
-// integral over impact parameter (Sec. 6.1), channel binning and chi^2 (Sec. 3).
-//
-// Hot kernel: k_forward. One workgroup (8 waves) owns one tile of up to 64 consecutive
-// wavenumbers (one per lane; a whole number of channels when binning) of one sample:
-//   phase 1  extinction. Wave w owns a contiguous run of layers; their record fields
-//            (T bracket, weights, densities) sit one layer per lane and are broadcast
-//            with v_readlane, so the two bracketing temperature rows of every species
-//            table are streamed for four layers at a time (coalesced along
-//            wavenumber, non-temporal) with no memory wait for addresses. CIA rows of
-//            the tile are staged in LDS once. e[l][nu] is left in LDS.
-//   phase 2  chord optical depth on the matrix cores (FP32): v_mfma_f32_16x16x4f32 over
-//            16-row blocks of the triangular chord-weight matrix (A, staged in LDS) and
-//            4-layer slices of e (B); items (row block, 16-column group) are dealt to
-//            waves in snake order. Each finished optical depth becomes 1 - exp(-tau) and
-//            is accumulated in double with its impact-parameter weight; partial sums are
-//            combined in a fixed order. FP64 uses the vector ALU with 8-row blocks.
-//   phase 3  the tile bins its own channels and writes its chi^2 partial; a small
-//            kernel sums the partials per sample in a fixed tree.
-// Workgroups are ordered XCD-aware and tile-major (see Segment) so that, in a batch,
-// all samples of one tile read the same table rows from the same L2.
-#include "bm_forward.h"
+// Host side of the forward model and the C-ABI entry points (steps a3-a6): the launch
+// plans of the fused kernel (fwd_kernel.h), the per-sample chi^2 reduction, the
+// standalone step kernels, the autotuner and the kernel-timing hook.
+#include "fwd_kernel.h"
 
+#include <map>
+#include <mutex>
+#include <string>
 #include <vector>
 
 namespace bm {
 
-template <typename T, bool kNonTemporal>
-__device__ __forceinline__ T ld_table(const T* p) {
-    if constexpr (kNonTemporal)
-        return __builtin_nontemporal_load(p);
-    else
-        return *p;
-}
-
-typedef float floatx4 __attribute__((ext_vector_type(4)));
-
-// LDS layout of one forward workgroup (bytes from the start of dynamic shared memory):
-//   es    extinction tile [rows][64] (FP32: L rounded up to 4 plus 16 zero rows, the
-//         furthest a padded k-step reaches)
-//   cw    impact-parameter weights [L] (double)
-//   u     CIA rows of the tile [NTc][64] (double) during phase 1; afterwards the
-//         per-row-block partial sums [blocks][64] and the tile's depths [64]
-template <typename T>
-struct FwdLds {
-    size_t es, cw, ciat, part, bins, total;
-    int es_rows;
-    __host__ __device__ FwdLds(int L, int kWaves, int ntc) {
-        es_rows = (sizeof(T) == 4) ? ((L + 3) & ~3) + kMfmaM : L;
-        es = 0;
-        size_t o = align_up(sizeof(T) * (size_t)es_rows * kTileNu, 16);
-        cw = o;
-        o = align_up(o + sizeof(double) * (size_t)L, 16);
-        ciat = o;
-        part = o;
-        const int nparts = (sizeof(T) == 4) ? mfma_row_blocks(L) : kWaves;
-        bins = part + sizeof(double) * (size_t)nparts * kTileNu;
-        size_t u1 = sizeof(double) * (size_t)ntc * kTileNu;
-        size_t u2 = bins + sizeof(double) * kTileNu - o;
-        o += (u1 > u2 ? u1 : u2);
-        const size_t chi2_part = sizeof(double) * (size_t)kWaves * kWave;
-        total = o > chi2_part ? o : chi2_part;
-    }
-};
-
-// extinction tile element (l, column c): FP32 rows swap their 16-column halves on odd
-// layers so that the matrix-core B reads (4 layers x 16 columns) are bank-conflict free
-template <typename T>
-__device__ __forceinline__ int es_index(int l, int c) {
-    if constexpr (sizeof(T) == 4) return l * kTileNu + (c ^ ((l & 1) << 4));
-    return l * kTileNu + c;
-}
-
-// broadcast lane `i` (uniform) of a per-lane value to the whole wave (v_readlane)
-__device__ __forceinline__ int lane_get(int v, int i) { return __builtin_amdgcn_readlane(v, i); }
-__device__ __forceinline__ float lane_get(float v, int i) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), i));
-}
-__device__ __forceinline__ double lane_get(double v, int i) {
-    const long long u = __builtin_bit_cast(long long, v);
-    const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffLL), i);
-    const int hi = __builtin_amdgcn_readlane((int)(u >> 32), i);
-    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
-}
-
-template <typename T, int kWaves, int kS, bool kCia, bool kNonTemporal>
-__global__ void __launch_bounds__(kWaves * kWave)
-    k_forward(LaunchPlan plan, char* __restrict__ ws, const int32_t* __restrict__ active,
-              double* __restrict__ depth, double* __restrict__ binned, double* __restrict__ chi2) {
-    extern __shared__ __align__(16) char smem[];
-    const int si = plan.segment_of_wg(blockIdx.x);
-    const Segment& sg = plan.seg[si];
-    const ModelDev& m = plan.model[sg.model];
-    // XCD-aware order: workgroup g runs on XCD g % 8; each XCD sweeps its own contiguous
-    // tile range and runs all samples of a tile back to back (shared table rows in L2)
-    const int g = blockIdx.x - sg.tile_begin;
-    const int kx = g / kXcds;
-    const int tile = (g % kXcds) * sg.tiles_per_xcd + kx / sg.count;
-    const int s_in = kx % sg.count;
-    if (tile >= sg.tiles) return;  // padding workgroup of the XCD split
-    const int b = sg.first + s_in;
-    if (active && !active[b]) return;  // sample not requested in this call
-    const int L = m.L, Nnu = m.Nnu;
-    const RecordView<T> rec(ws + sg.ws_off + (size_t)s_in * sg.rec_bytes, kS, L);
-    const FwdLds<T> lay(L, kWaves, plan.max_ntc);
-
-    const int lane = threadIdx.x & (kWave - 1);
-    // the wave index is uniform across a wave; readfirstlane lets the compiler keep the
-    // layer loops and every per-layer record load on the scalar unit
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    const int nu = tile * sg.tile_w + lane;
-    const bool valid = lane < sg.tile_w && nu < Nnu;
-    const int nu_c = valid ? nu : min(tile * sg.tile_w, Nnu - 1);
-
-    T* es = reinterpret_cast<T*>(smem + lay.es);
-    double* part = reinterpret_cast<double*>(smem + lay.part);
-    double* dsh = reinterpret_cast<double*>(smem + lay.bins);
-    double* dout = depth + sg.depth_off + (size_t)s_in * Nnu;
-    const int flags = rec.hdr->flags;
-    double dval = __builtin_nan("");  // this lane's depth (wave 0)
-
-    if (!(flags & BM_FLAG_RADIUS)) {
-        // impact-parameter weights to LDS (read per optical depth in phase 2)
-        double* cw_s = reinterpret_cast<double*>(smem + lay.cw);
-        for (int i = threadIdx.x; i < L; i += kWaves * kWave) cw_s[i] = rec.cw[i];
-        // this tile's columns of every CIA temperature row (read by many layers); the
-        // loads are all issued before the first store
-        double* cia_s = reinterpret_cast<double*>(smem + lay.ciat);
-        if constexpr (kCia) {
-            constexpr int kMaxPer = BM_MAX_TEMPS * kTileNu / (kWaves * kWave);
-            const int n = m.NTc * kTileNu;
-            double cv[kMaxPer];
-#pragma unroll
-            for (int q = 0; q < kMaxPer; ++q) {
-                const int i = min((int)threadIdx.x + q * kWaves * kWave, n - 1);
-                const int col = min(tile * sg.tile_w + (i % kTileNu), Nnu - 1);
-                cv[q] = m.cia[(size_t)(i / kTileNu) * Nnu + col];
-            }
-#pragma unroll
-            for (int q = 0; q < kMaxPer; ++q) {
-                const int i = threadIdx.x + q * kWaves * kWave;
-                if (i < n) cia_s[i] = cv[q];
-            }
-        }
-        __syncthreads();
-
-        // ---- phase 1: extinction into LDS --------------------------------------------
-        // wave w owns layers [w*per, (w+1)*per). Their record fields are loaded once, one
-        // layer per lane, and broadcast with v_readlane, so the table loads of a group of
-        // four layers are issued back to back without waiting on memory for addresses.
-        const T* __restrict__ sig = static_cast<const T*>(m.sigma);
-        const size_t t_stride = (size_t)L * Nnu;
-        const size_t s_stride = (size_t)m.NT * t_stride;
-        const int per = (L + kWaves - 1) / kWaves;
-        const int lb = wave * per;
-        const int le = min(L, lb + per);
-        const int mine = min(lb + lane, L - 1);
-        const int r_k = rec.kidx[mine];
-        const T r_w = rec.w[mine];
-        T r_a[kS];
-#pragma unroll
-        for (int i = 0; i < kS; ++i) r_a[i] = rec.afac[i * L + mine];
-        int r_kc = 0;
-        double r_wc = 0.0, r_b = 0.0;
-        if constexpr (kCia) {
-            r_kc = rec.kcidx[mine];
-            r_wc = rec.wc[mine];
-            r_b = rec.bfac[mine];
-        }
-        for (int l0 = lb; l0 < le; l0 += 4) {
-            T s0[4][kS], s1[4][kS];
-            double c0[4], c1[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int uu = min(l0 + u, le - 1) - lb;
-                const T* p = sig + (size_t)lane_get(r_k, uu) * t_stride + (size_t)(lb + uu) * Nnu + nu_c;
-#pragma unroll
-                for (int i = 0; i < kS; ++i) {
-                    s0[u][i] = ld_table<T, kNonTemporal>(p + i * s_stride);
-                    s1[u][i] = ld_table<T, kNonTemporal>(p + i * s_stride + t_stride);
-                }
-                if constexpr (kCia) {
-                    const double* c = cia_s + lane_get(r_kc, uu) * kTileNu + lane;
-                    c0[u] = c[0];
-                    c1[u] = c[kTileNu];
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int l = l0 + u;
-                if (l < le) {
-                    const int uu = l - lb;
-                    const T w = lane_get(r_w, uu);
-                    T e = T(0);
-#pragma unroll
-                    for (int i = 0; i < kS; ++i)
-                        e = fma(lane_get(r_a[i], uu), fma(w, s1[u][i] - s0[u][i], s0[u][i]), e);
-                    if constexpr (kCia)
-                        e += (T)(lane_get(r_b, uu) * fma(lane_get(r_wc, uu), c1[u] - c0[u], c0[u]));
-                    es[es_index<T>(l, lane)] = e;
-                }
-            }
-        }
-        if constexpr (sizeof(T) == 4) {
-            // zero rows past the last layer (read, against zero weights, by padded k-steps)
-            for (int i = threadIdx.x; i < (lay.es_rows - L) * kTileNu; i += kWaves * kWave) es[L * kTileNu + i] = T(0);
-        }
-        __syncthreads();
-
-        // ---- phase 2: chord optical depth, 1 - exp(-tau), impact-parameter sum -------
-        if constexpr (sizeof(T) == 4) {
-            // items (row block J, 16-column group) in decreasing cost, dealt in snake order
-            const int nJ = mfma_row_blocks(L);
-            const int n_items = nJ * 4;
-            for (int it = 0; it < n_items; ++it) {
-                const int round = it / kWaves, pos = it - round * kWaves;
-                const int owner = (round & 1) ? (kWaves - 1 - pos) : pos;
-                if (owner != wave) continue;
-                const int J = it >> 2, col = it & 3;
-                const int K = mfma_ksteps(L, J);  // a multiple of kMfmaChunk
-                // A fragments stream from L2 (coalesced, one chunk ahead), B from LDS. (Staging
-                // them in LDS measured slower: it holds registers through phase 1.)
-                const float* ag = rec.wb + (size_t)mfma_kstep_offset(L, J) * kWave + lane;
-                const int brow = kMfmaM * J + (lane >> 4);
-                const int bcol = col * 16 + (lane & 15);
-                floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-                floatx4 acc2 = {0.f, 0.f, 0.f, 0.f};
-                float an[kMfmaChunk];
-#pragma unroll
-                for (int u = 0; u < kMfmaChunk; ++u) an[u] = ag[u * kWave];
-                for (int ks = 0; ks < K; ks += kMfmaChunk) {
-                    float ac[kMfmaChunk], bv[kMfmaChunk];
-#pragma unroll
-                    for (int u = 0; u < kMfmaChunk; ++u) {
-                        ac[u] = an[u];
-                        an[u] = ag[min(ks + kMfmaChunk + u, K - 1) * kWave];
-                        bv[u] = es[es_index<T>(brow + kMfmaK * (ks + u), bcol)];
-                    }
-#pragma unroll
-                    for (int u = 0; u < kMfmaChunk; u += 2) {
-                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ac[u], bv[u], acc, 0, 0, 0);
-                        acc2 = __builtin_amdgcn_mfma_f32_16x16x4f32(ac[u + 1], bv[u + 1], acc2, 0, 0, 0);
-                    }
-                }
-                acc += acc2;
-                // this lane holds rows 16J + 4(lane/16) + r of column bcol
-                double pp = 0.0;
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int j = kMfmaM * J + 4 * (lane >> 4) + r;
-                    if (j <= L - 2) pp += cw_s[j] * (double)(-expm1f(-acc[r]));
-                }
-                pp += __shfl_xor(pp, 16);
-                pp += __shfl_xor(pp, 32);
-                if (lane < 16) part[J * kTileNu + bcol] = pp;
-            }
-            __syncthreads();
-            if (wave == 0) {
-                double s = rec.hdr->base;
-                for (int J = 0; J < nJ; ++J) s += part[J * kTileNu + lane];
-                dval = s / rec.hdr->rs2;
-            }
-        } else {
-            // FP64: vector ALU, 8-row register blocks, chord weights as uniform loads
-            double acc = 0.0;
-            const int nbu = (L - 1 + kRows - 1) / kRows;
-            for (int blk = 0; blk < nbu; ++blk) {
-                const int round = blk / kWaves, pos = blk - round * kWaves;
-                const int owner = (round & 1) ? (kWaves - 1 - pos) : pos;
-                if (owner != wave) continue;
-                const int j0 = blk * kRows;
-                T t[kRows];
-#pragma unroll
-                for (int r = 0; r < kRows; ++r) t[r] = T(0);
-                const T* __restrict__ wcol = rec.wb + (size_t)blk * L * kRows;
-                for (int l = j0; l < L; ++l) {
-                    const T e = es[es_index<T>(l, lane)];
-#pragma unroll
-                    for (int r = 0; r < kRows; ++r) t[r] = fma(wcol[l * kRows + r], e, t[r]);
-                }
-#pragma unroll
-                for (int r = 0; r < kRows; ++r) {
-                    const int j = j0 + r;
-                    if (j <= L - 2) acc += cw_s[j] * (double)(-dev_expm1(-t[r]));
-                }
-            }
-            part[wave * kTileNu + lane] = acc;
-            __syncthreads();
-            if (wave == 0) {
-                double s = rec.hdr->base;
-                for (int w2 = 0; w2 < kWaves; ++w2) s += part[w2 * kTileNu + lane];
-                dval = s / rec.hdr->rs2;
-            }
-        }
-    }
-    if (wave == 0) {
-        if (valid) dout[nu] = dval;
-        dsh[lane] = dval;
-    }
-
-    // ---- phase 3: channels of this tile; chi^2 partial; last tile sums the partials ----
-    if (binned == nullptr || !sg.fused_bins) return;
-    __syncthreads();
-    const int bw = m.bin_width;
-    const int nbt = sg.tile_w / bw;   // whole channels per tile
-    const int nbins = Nnu / bw;
-    const bool want_chi2 = (chi2 != nullptr) && m.data && m.err;
-    double* bout = binned + sg.bin_off + (size_t)s_in * nbins;
-    if (wave == 0) {
-        double term = 0.0;
-        const int cg = tile * nbt + lane;
-        if (lane < nbt && cg < nbins) {
-            double acc = 0.0;
-            for (int q = 0; q < bw; ++q) acc += dsh[lane * bw + q];
-            const double mean = acc / bw;
-            bout[cg] = mean;
-            if (want_chi2) {
-                const double d = (mean - m.data[cg]) / m.err[cg];
-                term = d * d;
-            }
-        }
-        if (want_chi2) {
-            // fixed-order butterfly over the wave
-            for (int o = 32; o > 0; o >>= 1) term += __shfl_xor(term, o);
-            if (lane == 0) rec.chi2part[tile] = term;
-        }
-    }
-}
-
+// the fused kernel's launchers are instantiated in fwd_f32_nt.hip, fwd_f32_t.hip and
+// fwd_f64.hip (compiled in parallel)
+#define BM_FWD_EXTERN(T, W, NT)                                                                            \
+    extern template int launch_k_forward<T, W, NT>(const HostPlan&, const LaunchPlan&, size_t, char*,       \
+                                                    const int32_t*, double*, double*, double*, hipStream_t, \
+                                                    hipEvent_t, hipEvent_t);
+BM_FWD_EXTERN(float, 8, true)
+BM_FWD_EXTERN(float, 4, true)
+BM_FWD_EXTERN(float, 8, false)
+BM_FWD_EXTERN(float, 4, false)
+BM_FWD_EXTERN(double, 8, true)
+#undef BM_FWD_EXTERN
 // chi^2 of each sample: the tiles' partials summed in a fixed tree (one workgroup per
 // sample, after the forward kernel: the kernel boundary orders the partial writes)
 template <typename T>
@@ -491,19 +184,6 @@ static size_t record_bytes(const bm_model& m, int tiles) {
                              : record_bytes_t<double>(m.n_species, m.n_layers, tiles);
 }
 
-// Split a batch into launch plans of at most kMaxSegments same-model runs.
-struct HostPlan {
-    std::vector<LaunchPlan> plans;
-    std::vector<int> first_sample;   // first sample of each plan
-    std::vector<int> n_samples;      // samples of each plan
-    size_t ws_bytes = 0;
-    int max_L = 0;
-    int n_species = 0;
-    bool cia = false;
-    int max_ntc = 0;          // largest CIA temperature grid (LDS staging rows)
-    int total_samples = 0;
-    size_t max_entries = 0;   // chord-weight entries of the largest record
-};
 
 // slices of the record preparation per sample: enough workgroups to spread the chord
 // weights of a single spectrum over the chip, fewer when the batch fills it anyway
@@ -582,11 +262,26 @@ static int build_plans(const bm_model* models, int n_models, const int32_t* inst
     return BM_OK;
 }
 
-constexpr int kFwdWaves = 8;
+// Launch configurations of the fused forward kernel that the autotuner chooses from:
+// waves per workgroup (phase-1 layers per wave, phase-2 items per wave, workgroups per
+// CU) and whether table rows are loaded non-temporally (streamed once: best for one
+// spectrum) or through the caches (rows shared by the samples of a tile in a batch).
+struct FwdConfig {
+    int waves;
+    bool nontemporal;
+    const char* name;
+};
+constexpr FwdConfig kFwdConfigs[] = {
+    {8, true, "8 waves/workgroup, non-temporal table loads"},
+    {8, false, "8 waves/workgroup, cached table loads"},
+    {4, true, "4 waves/workgroup, non-temporal table loads"},
+    {4, false, "4 waves/workgroup, cached table loads"},
+};
+constexpr int kNumFwdConfigs = sizeof(kFwdConfigs) / sizeof(kFwdConfigs[0]);
 
 template <typename T>
-static size_t forward_lds_bytes(int max_L, int max_ntc) {
-    return FwdLds<T>(max_L, kFwdWaves, max_ntc).total;
+static size_t forward_lds_bytes(int max_L, int waves, int max_ntc) {
+    return FwdLds<T>(max_L, waves, max_ntc).total;
 }
 
 // Dynamic LDS above 64 KB must be enabled per kernel; the device limit is queried once.
@@ -605,26 +300,51 @@ static size_t device_lds_limit() {
 
 // Raise a kernel's dynamic-LDS ceiling once per device (hipFuncSetAttribute is host work
 // that the per-call path should not repeat).
-static int ensure_dynamic_lds(const void* fn, size_t bytes) {
+int ensure_dynamic_lds(const void* fn, size_t bytes) {
     if (bytes <= 48 * 1024) return BM_OK;
     struct Entry { const void* fn; int dev; size_t bytes; };
-    static Entry cache[64];
+    static Entry cache[256];
     static int n_cache = 0;
+    static std::mutex mu;
     int dev = 0;
     BM_CHECK_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(mu);
     for (int i = 0; i < n_cache; ++i)
         if (cache[i].fn == fn && cache[i].dev == dev && cache[i].bytes >= bytes) return BM_OK;
     BM_CHECK_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
-    if (n_cache < 64) cache[n_cache++] = Entry{fn, dev, bytes};
+    if (n_cache < 256) cache[n_cache++] = Entry{fn, dev, bytes};
     return BM_OK;
 }
 
+// ---- kernel timing (measurement hook) -------------------------------------------------
+// While a session is open, every launch of the fused kernel outside graph capture carries
+// a pair of timing events that its dispatch records at the kernel's start and end.
+struct TimingSession {
+    std::vector<hipEvent_t> ev;
+    int cap = 0, used = 0;
+};
+static std::mutex g_timing_mu;
+static TimingSession* g_timing = nullptr;
+
+static void timing_slot(hipStream_t st, hipEvent_t* e0, hipEvent_t* e1) {
+    *e0 = *e1 = nullptr;
+    std::lock_guard<std::mutex> lock(g_timing_mu);
+    if (!g_timing || g_timing->used >= g_timing->cap) return;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
+    const int i = g_timing->used++;
+    *e0 = g_timing->ev[2 * i];
+    *e1 = g_timing->ev[2 * i + 1];
+}
+
 template <typename T>
-static int launch_forward(const HostPlan& hp, const double* params, int stride, const int32_t* active,
+static int launch_forward(const HostPlan& hp, int cfg, const double* params, int stride, const int32_t* active,
                           double* depth, double* binned, double* chi2, int32_t* flags, char* ws, hipStream_t st) {
-    const size_t lds = forward_lds_bytes<T>(hp.max_L, hp.max_ntc);
+    // FP64 (the parity mode) has the default configuration only
+    if (sizeof(T) == 8 || cfg < 0 || cfg >= kNumFwdConfigs) cfg = 0;
+    const FwdConfig& fc = kFwdConfigs[cfg];
+    const size_t lds = forward_lds_bytes<T>(hp.max_L, fc.waves, hp.max_ntc);
     if (lds > device_lds_limit()) return BM_ESHAPE;
-    int st_code = BM_OK;
     for (size_t p = 0; p < hp.plans.size(); ++p) {
         const LaunchPlan& lp = hp.plans[p];
         const int b0 = hp.first_sample[p];
@@ -636,27 +356,20 @@ static int launch_forward(const HostPlan& hp, const double* params, int stride, 
                            params + (size_t)b0 * stride, stride, act, ws, flags + b0);
         BM_CHECK_HIP(hipGetLastError());
         double* c2 = chi2 ? chi2 + b0 : nullptr;
-        const dim3 grid(lp.total_wgs), block(kFwdWaves * kWave);
-        switch (hp.n_species) {
-#define BM_FWD_LAUNCH(NS, CIA)                                                                         \
-    st_code = ensure_dynamic_lds((const void*)k_forward<T, kFwdWaves, NS, CIA, true>, lds);             \
-    if (st_code != BM_OK) return st_code;                                                              \
-    hipLaunchKernelGGL((k_forward<T, kFwdWaves, NS, CIA, true>), grid, block, lds, st, lp, ws, act, depth, binned, c2);
-#define BM_FWD_CASE(NS)                  \
-    case NS:                             \
-        if (hp.cia) {                    \
-            BM_FWD_LAUNCH(NS, true)      \
-        } else {                         \
-            BM_FWD_LAUNCH(NS, false)     \
-        }                                \
-        break;
-            BM_FWD_CASE(1) BM_FWD_CASE(2) BM_FWD_CASE(3) BM_FWD_CASE(4)
-            BM_FWD_CASE(5) BM_FWD_CASE(6) BM_FWD_CASE(7) BM_FWD_CASE(8)
-#undef BM_FWD_CASE
-#undef BM_FWD_LAUNCH
-            default: return BM_ESHAPE;
+        hipEvent_t e0, e1;
+        timing_slot(st, &e0, &e1);
+        int code;
+        if constexpr (sizeof(T) == 8) {
+            code = launch_k_forward<T, 8, true>(hp, lp, lds, ws, act, depth, binned, c2, st, e0, e1);
+        } else {
+            switch (cfg) {
+                case 1: code = launch_k_forward<T, 8, false>(hp, lp, lds, ws, act, depth, binned, c2, st, e0, e1); break;
+                case 2: code = launch_k_forward<T, 4, true>(hp, lp, lds, ws, act, depth, binned, c2, st, e0, e1); break;
+                case 3: code = launch_k_forward<T, 4, false>(hp, lp, lds, ws, act, depth, binned, c2, st, e0, e1); break;
+                default: code = launch_k_forward<T, 8, true>(hp, lp, lds, ws, act, depth, binned, c2, st, e0, e1); break;
+            }
         }
-        BM_CHECK_HIP(hipGetLastError());
+        if (code != BM_OK) return code;
         if (c2 && binned) {
             bool any_fused = false;
             for (int si = 0; si < lp.n_seg; ++si) any_fused |= lp.seg[si].fused_bins != 0;
@@ -678,6 +391,57 @@ static int launch_forward(const HostPlan& hp, const double* params, int stride, 
             }
         }
     }
+    return BM_OK;
+}
+
+// ---- tuned configurations --------------------------------------------------------------
+// Keyed by the batch signature: dtype, species count, CIA, and every run of samples
+// (instance shape and count) in order.
+static std::string batch_signature(const bm_model* models, const HostPlan& hp) {
+    std::string s = std::to_string(models[0].dtype) + ":" + std::to_string(hp.n_species) + ":" +
+                    std::to_string((int)hp.cia);
+    for (const LaunchPlan& lp : hp.plans)
+        for (int i = 0; i < lp.n_seg; ++i) {
+            const Segment& sg = lp.seg[i];
+            const ModelDev& m = lp.model[sg.model];
+            s += "|" + std::to_string(m.L) + "x" + std::to_string(m.Nnu) + "x" + std::to_string(m.NT) + "x" +
+                 std::to_string(m.NTc) + "b" + std::to_string(m.bin_width) + "n" + std::to_string(sg.count);
+        }
+    return s;
+}
+
+static std::mutex g_tune_mu;
+static std::map<std::string, int>* g_tuned = nullptr;
+
+static int tuned_config(const bm_model* models, const HostPlan& hp) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    if (!g_tuned || g_tuned->empty()) return 0;
+    auto it = g_tuned->find(batch_signature(models, hp));
+    return it == g_tuned->end() ? 0 : it->second;
+}
+
+static int run_forward(const bm_model* models, const HostPlan& hp, int cfg, const double* params, int stride,
+                       const int32_t* active, double* depth, double* binned, double* chi2, int32_t* flags,
+                       void* ws, hipStream_t s) {
+    if (models[0].dtype == BM_F32)
+        return launch_forward<float>(hp, cfg, params, stride, active, depth, binned, chi2, flags, (char*)ws, s);
+    return launch_forward<double>(hp, cfg, params, stride, active, depth, binned, chi2, flags, (char*)ws, s);
+}
+
+// argument checks shared by bm_forward_batch and bm_forward_tune
+static int check_forward_args(const bm_model* models, int n_models, const int32_t* instance, const double* params,
+                              int param_stride, int B, double* depth, double* binned, double* chi2,
+                              int32_t* flags, void* workspace, size_t workspace_bytes, HostPlan& hp) {
+    if (!models || !params || !depth || !flags || !workspace) return BM_EINVAL;
+    int st = build_plans(models, n_models, instance, B, hp);
+    if (st != BM_OK) return st;
+    for (int i = 0; i < n_models; ++i) {
+        if (param_stride < bm_n_params(&models[i])) return BM_ESHAPE;
+        if (binned && models[i].bin_width <= 0) return BM_EINVAL;
+        if (chi2 && (!models[i].data || !models[i].err)) return BM_EINVAL;
+    }
+    if (chi2 && !binned) return BM_EINVAL;
+    if (workspace_bytes < hp.ws_bytes) return BM_ENOSPACE;
     return BM_OK;
 }
 
@@ -781,20 +545,138 @@ extern "C" int bm_forward_batch(const bm_model* models, int n_models, const int3
                                 const double* params, int param_stride, int B, const int32_t* active,
                                 double* depth, double* binned, double* chi2, int32_t* flags, void* workspace,
                                 size_t workspace_bytes, void* stream) {
-    if (!models || !params || !depth || !flags || !workspace) return BM_EINVAL;
+    HostPlan hp;
+    int st = check_forward_args(models, n_models, instance, params, param_stride, B, depth, binned, chi2, flags,
+                                workspace, workspace_bytes, hp);
+    if (st != BM_OK) return st;
+    if (B == 0) return BM_OK;
+    const int cfg = tuned_config(models, hp);
+    return run_forward(models, hp, cfg, params, param_stride, active, depth, binned, chi2, flags, workspace,
+                       (hipStream_t)stream);
+}
+
+extern "C" int bm_forward_config_count(void) { return kNumFwdConfigs; }
+
+extern "C" const char* bm_forward_config_name(int config) {
+    if (config < 0 || config >= kNumFwdConfigs) return nullptr;
+    return kFwdConfigs[config].name;
+}
+
+extern "C" int bm_forward_tune(const bm_model* models, int n_models, const int32_t* instance, const double* params,
+                               int param_stride, int B, double* depth, double* binned, double* chi2, int32_t* flags,
+                               void* workspace, size_t workspace_bytes, void* stream, int reps, int* chosen,
+                               float* times_ms, int n_times) {
+    HostPlan hp;
+    int st = check_forward_args(models, n_models, instance, params, param_stride, B, depth, binned, chi2, flags,
+                                workspace, workspace_bytes, hp);
+    if (st != BM_OK) return st;
+    if (reps < 1 || B < 1) return BM_EINVAL;
+    const hipStream_t s = (hipStream_t)stream;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    BM_CHECK_HIP(hipStreamIsCapturing(s, &cs));
+    if (cs != hipStreamCaptureStatusNone) return BM_EINVAL;
+    const int n_cfg = models[0].dtype == BM_F32 ? kNumFwdConfigs : 1;
+    hipEvent_t e0, e1;
+    BM_CHECK_HIP(hipEventCreate(&e0));
+    BM_CHECK_HIP(hipEventCreate(&e1));
+    int best = 0;
+    float best_ms = 0.f;
+    int code = BM_OK;
+    for (int c = 0; c < kNumFwdConfigs && code == BM_OK; ++c) {
+        float ms = -1.f;
+        if (c < n_cfg) {
+            code = run_forward(models, hp, c, params, param_stride, nullptr, depth, binned, chi2, flags, workspace, s);
+            if (code == BM_ESHAPE) {  // this configuration does not fit the batch (LDS)
+                code = BM_OK;
+            } else if (code == BM_OK) {
+                if (hipEventRecord(e0, s) != hipSuccess) code = BM_EHIP;
+                for (int r = 0; r < reps && code == BM_OK; ++r)
+                    code = run_forward(models, hp, c, params, param_stride, nullptr, depth, binned, chi2, flags,
+                                       workspace, s);
+                if (code == BM_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                                      hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                    code = BM_EHIP;
+                if (code == BM_OK) {
+                    ms /= reps;
+                    if (best_ms == 0.f || ms < best_ms) {
+                        best_ms = ms;
+                        best = c;
+                    }
+                }
+            }
+        }
+        if (times_ms && c < n_times) times_ms[c] = ms;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (code != BM_OK) return code;
+    if (best_ms == 0.f) return BM_ESHAPE;
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        if (!g_tuned) g_tuned = new std::map<std::string, int>();
+        (*g_tuned)[batch_signature(models, hp)] = best;
+    }
+    if (chosen) *chosen = best;
+    return BM_OK;
+}
+
+extern "C" int bm_forward_set_config(const bm_model* models, int n_models, const int32_t* instance, int B,
+                                     int config) {
+    if (config < -1 || config >= kNumFwdConfigs) return BM_EINVAL;
     HostPlan hp;
     int st = build_plans(models, n_models, instance, B, hp);
     if (st != BM_OK) return st;
-    if (B == 0) return BM_OK;
-    for (int i = 0; i < n_models; ++i) {
-        if (param_stride < bm_n_params(&models[i])) return BM_ESHAPE;
-        if (binned && models[i].bin_width <= 0) return BM_EINVAL;
-        if (chi2 && (!models[i].data || !models[i].err)) return BM_EINVAL;
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    if (!g_tuned) g_tuned = new std::map<std::string, int>();
+    if (config < 0)
+        g_tuned->erase(batch_signature(models, hp));
+    else
+        (*g_tuned)[batch_signature(models, hp)] = config;
+    return BM_OK;
+}
+
+extern "C" int bm_timing_start(int capacity) {
+    if (capacity < 1 || capacity > (1 << 20)) return BM_EINVAL;
+    std::lock_guard<std::mutex> lock(g_timing_mu);
+    if (g_timing) return BM_EINVAL;
+    TimingSession* t = new TimingSession();
+    t->ev.resize(2 * (size_t)capacity, nullptr);
+    for (auto& e : t->ev) {
+        if (hipEventCreate(&e) != hipSuccess) {
+            for (auto& f : t->ev)
+                if (f) hipEventDestroy(f);
+            delete t;
+            return BM_EHIP;
+        }
     }
-    if (chi2 && !binned) return BM_EINVAL;
-    if (workspace_bytes < hp.ws_bytes) return BM_ENOSPACE;
-    const hipStream_t s = (hipStream_t)stream;
-    if (models[0].dtype == BM_F32)
-        return launch_forward<float>(hp, params, param_stride, active, depth, binned, chi2, flags, (char*)workspace, s);
-    return launch_forward<double>(hp, params, param_stride, active, depth, binned, chi2, flags, (char*)workspace, s);
+    t->cap = capacity;
+    g_timing = t;
+    return BM_OK;
+}
+
+extern "C" int bm_timing_stop(double* total_ms, int64_t* launches) {
+    TimingSession* t;
+    {
+        std::lock_guard<std::mutex> lock(g_timing_mu);
+        t = g_timing;
+        g_timing = nullptr;
+    }
+    if (!t) return BM_EINVAL;
+    double tot = 0.0;
+    int code = BM_OK;
+    for (int i = 0; i < t->used; ++i) {
+        float ms = 0.f;
+        if (hipEventSynchronize(t->ev[2 * i + 1]) != hipSuccess ||
+            hipEventElapsedTime(&ms, t->ev[2 * i], t->ev[2 * i + 1]) != hipSuccess) {
+            code = BM_EHIP;
+            break;
+        }
+        tot += ms;
+    }
+    const int used = t->used;
+    for (auto& e : t->ev) hipEventDestroy(e);
+    delete t;
+    if (total_ms) *total_ms = tot;
+    if (launches) *launches = used;
+    return code;
 }

@@ -1,0 +1,363 @@
+// Steps a3-a6 of the forward model on the GPU and the C-ABI entry points that expose
+// them: temperature interpolation of the opacity tables and extinction (Sec. 3,
+// Sec. 6.1.1), chord optical depth through spherical layers and the transit-depth
+// integral over impact parameter (Sec. 6.1), channel binning and chi^2 (Sec. 3).
+//
+// Hot kernel: k_forward. One workgroup (8 waves) owns one tile of up to 64 consecutive
+// wavenumbers (one per lane; a whole number of channels when binning) of one sample:
+//   phase 1  extinction. Wave w owns a contiguous run of layers; their record fields
+//            (T bracket, weights, densities) sit one layer per lane and are broadcast
+//            with v_readlane, so the two bracketing temperature rows of every species
+//            table are streamed for four layers at a time (coalesced along
+//            wavenumber, non-temporal) with no memory wait for addresses. CIA rows of
+//            the tile are staged in LDS once. e[l][nu] is left in LDS.
+//   phase 2  chord optical depth on the matrix cores (FP32): v_mfma_f32_16x16x4f32 over
+//            16-row blocks of the triangular chord-weight matrix (A, staged in LDS) and
+//            4-layer slices of e (B); items (row block, 16-column group) are dealt to
+//            waves in snake order. Each finished optical depth becomes 1 - exp(-tau) and
+//            is accumulated in double with its impact-parameter weight; partial sums are
+//            combined in a fixed order. FP64 uses the vector ALU with 8-row blocks.
+//   phase 3  the tile bins its own channels and writes its chi^2 partial; a small
+//            kernel sums the partials per sample in a fixed tree.
+// Workgroups are ordered XCD-aware and tile-major (see Segment) so that, in a batch,
+// all samples of one tile read the same table rows from the same L2.
+#pragma once
+#include <hip/hip_ext.h>
+
+#include "bm_forward.h"
+
+namespace bm {
+
+template <typename T, bool kNonTemporal>
+__device__ __forceinline__ T ld_table(const T* p) {
+    if constexpr (kNonTemporal)
+        return __builtin_nontemporal_load(p);
+    else
+        return *p;
+}
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// LDS layout of one forward workgroup (bytes from the start of dynamic shared memory):
+//   es    extinction tile [rows][64] (FP32: L rounded up to 4 plus 16 zero rows, the
+//         furthest a padded k-step reaches)
+//   cw    impact-parameter weights [L] (double)
+//   u     CIA rows of the tile [NTc][64] (double) during phase 1; afterwards the
+//         per-row-block partial sums [blocks][64] and the tile's depths [64]
+template <typename T>
+struct FwdLds {
+    size_t es, cw, ciat, part, bins, total;
+    int es_rows;
+    __host__ __device__ FwdLds(int L, int kWaves, int ntc) {
+        es_rows = (sizeof(T) == 4) ? ((L + 3) & ~3) + kMfmaM : L;
+        es = 0;
+        size_t o = align_up(sizeof(T) * (size_t)es_rows * kTileNu, 16);
+        cw = o;
+        o = align_up(o + sizeof(double) * (size_t)L, 16);
+        ciat = o;
+        part = o;
+        const int nparts = (sizeof(T) == 4) ? mfma_row_blocks(L) : kWaves;
+        bins = part + sizeof(double) * (size_t)nparts * kTileNu;
+        size_t u1 = sizeof(double) * (size_t)ntc * kTileNu;
+        size_t u2 = bins + sizeof(double) * kTileNu - o;
+        o += (u1 > u2 ? u1 : u2);
+        const size_t chi2_part = sizeof(double) * (size_t)kWaves * kWave;
+        total = o > chi2_part ? o : chi2_part;
+    }
+};
+
+// extinction tile element (l, column c): FP32 rows swap their 16-column halves on odd
+// layers so that the matrix-core B reads (4 layers x 16 columns) are bank-conflict free
+template <typename T>
+__device__ __forceinline__ int es_index(int l, int c) {
+    if constexpr (sizeof(T) == 4) return l * kTileNu + (c ^ ((l & 1) << 4));
+    return l * kTileNu + c;
+}
+
+// broadcast lane `i` (uniform) of a per-lane value to the whole wave (v_readlane)
+__device__ __forceinline__ int lane_get(int v, int i) { return __builtin_amdgcn_readlane(v, i); }
+__device__ __forceinline__ float lane_get(float v, int i) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), i));
+}
+__device__ __forceinline__ double lane_get(double v, int i) {
+    const long long u = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffLL), i);
+    const int hi = __builtin_amdgcn_readlane((int)(u >> 32), i);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <typename T, int kWaves, int kS, bool kCia, bool kNonTemporal>
+__global__ void __launch_bounds__(kWaves * kWave)
+    k_forward(LaunchPlan plan, char* __restrict__ ws, const int32_t* __restrict__ active,
+              double* __restrict__ depth, double* __restrict__ binned, double* __restrict__ chi2) {
+    extern __shared__ __align__(16) char smem[];
+    const int si = plan.segment_of_wg(blockIdx.x);
+    const Segment& sg = plan.seg[si];
+    const ModelDev& m = plan.model[sg.model];
+    // XCD-aware order: workgroup g runs on XCD g % 8; each XCD sweeps its own contiguous
+    // tile range and runs all samples of a tile back to back (shared table rows in L2)
+    const int g = blockIdx.x - sg.tile_begin;
+    const int kx = g / kXcds;
+    const int tile = (g % kXcds) * sg.tiles_per_xcd + kx / sg.count;
+    const int s_in = kx % sg.count;
+    if (tile >= sg.tiles) return;  // padding workgroup of the XCD split
+    const int b = sg.first + s_in;
+    if (active && !active[b]) return;  // sample not requested in this call
+    const int L = m.L, Nnu = m.Nnu;
+    const RecordView<T> rec(ws + sg.ws_off + (size_t)s_in * sg.rec_bytes, kS, L);
+    const FwdLds<T> lay(L, kWaves, plan.max_ntc);
+
+    const int lane = threadIdx.x & (kWave - 1);
+    // the wave index is uniform across a wave; readfirstlane lets the compiler keep the
+    // layer loops and every per-layer record load on the scalar unit
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int nu = tile * sg.tile_w + lane;
+    const bool valid = lane < sg.tile_w && nu < Nnu;
+    const int nu_c = valid ? nu : min(tile * sg.tile_w, Nnu - 1);
+
+    T* es = reinterpret_cast<T*>(smem + lay.es);
+    double* part = reinterpret_cast<double*>(smem + lay.part);
+    double* dsh = reinterpret_cast<double*>(smem + lay.bins);
+    double* dout = depth + sg.depth_off + (size_t)s_in * Nnu;
+    const int flags = rec.hdr->flags;
+    double dval = __builtin_nan("");  // this lane's depth (wave 0)
+
+    if (!(flags & BM_FLAG_RADIUS)) {
+        // impact-parameter weights to LDS (read per optical depth in phase 2)
+        double* cw_s = reinterpret_cast<double*>(smem + lay.cw);
+        for (int i = threadIdx.x; i < L; i += kWaves * kWave) cw_s[i] = rec.cw[i];
+        // this tile's columns of every CIA temperature row (read by many layers); the
+        // loads are all issued before the first store
+        double* cia_s = reinterpret_cast<double*>(smem + lay.ciat);
+        if constexpr (kCia) {
+            constexpr int kMaxPer = BM_MAX_TEMPS * kTileNu / (kWaves * kWave);
+            const int n = m.NTc * kTileNu;
+            double cv[kMaxPer];
+#pragma unroll
+            for (int q = 0; q < kMaxPer; ++q) {
+                const int i = min((int)threadIdx.x + q * kWaves * kWave, n - 1);
+                const int col = min(tile * sg.tile_w + (i % kTileNu), Nnu - 1);
+                cv[q] = m.cia[(size_t)(i / kTileNu) * Nnu + col];
+            }
+#pragma unroll
+            for (int q = 0; q < kMaxPer; ++q) {
+                const int i = threadIdx.x + q * kWaves * kWave;
+                if (i < n) cia_s[i] = cv[q];
+            }
+        }
+        __syncthreads();
+
+        // ---- phase 1: extinction into LDS --------------------------------------------
+        // wave w owns layers [w*per, (w+1)*per). Their record fields are loaded once, one
+        // layer per lane, and broadcast with v_readlane, so the table loads of a group of
+        // four layers are issued back to back without waiting on memory for addresses.
+        const T* __restrict__ sig = static_cast<const T*>(m.sigma);
+        const size_t t_stride = (size_t)L * Nnu;
+        const size_t s_stride = (size_t)m.NT * t_stride;
+        const int per = (L + kWaves - 1) / kWaves;
+        const int lb = wave * per;
+        const int le = min(L, lb + per);
+        const int mine = min(lb + lane, L - 1);
+        const int r_k = rec.kidx[mine];
+        const T r_w = rec.w[mine];
+        T r_a[kS];
+#pragma unroll
+        for (int i = 0; i < kS; ++i) r_a[i] = rec.afac[i * L + mine];
+        int r_kc = 0;
+        double r_wc = 0.0, r_b = 0.0;
+        if constexpr (kCia) {
+            r_kc = rec.kcidx[mine];
+            r_wc = rec.wc[mine];
+            r_b = rec.bfac[mine];
+        }
+        for (int l0 = lb; l0 < le; l0 += 4) {
+            T s0[4][kS], s1[4][kS];
+            double c0[4], c1[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int uu = min(l0 + u, le - 1) - lb;
+                const T* p = sig + (size_t)lane_get(r_k, uu) * t_stride + (size_t)(lb + uu) * Nnu + nu_c;
+#pragma unroll
+                for (int i = 0; i < kS; ++i) {
+                    s0[u][i] = ld_table<T, kNonTemporal>(p + i * s_stride);
+                    s1[u][i] = ld_table<T, kNonTemporal>(p + i * s_stride + t_stride);
+                }
+                if constexpr (kCia) {
+                    const double* c = cia_s + lane_get(r_kc, uu) * kTileNu + lane;
+                    c0[u] = c[0];
+                    c1[u] = c[kTileNu];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int l = l0 + u;
+                if (l < le) {
+                    const int uu = l - lb;
+                    const T w = lane_get(r_w, uu);
+                    T e = T(0);
+#pragma unroll
+                    for (int i = 0; i < kS; ++i)
+                        e = fma(lane_get(r_a[i], uu), fma(w, s1[u][i] - s0[u][i], s0[u][i]), e);
+                    if constexpr (kCia)
+                        e += (T)(lane_get(r_b, uu) * fma(lane_get(r_wc, uu), c1[u] - c0[u], c0[u]));
+                    es[es_index<T>(l, lane)] = e;
+                }
+            }
+        }
+        if constexpr (sizeof(T) == 4) {
+            // zero rows past the last layer (read, against zero weights, by padded k-steps)
+            for (int i = threadIdx.x; i < (lay.es_rows - L) * kTileNu; i += kWaves * kWave) es[L * kTileNu + i] = T(0);
+        }
+        __syncthreads();
+
+        // ---- phase 2: chord optical depth, 1 - exp(-tau), impact-parameter sum -------
+        if constexpr (sizeof(T) == 4) {
+            // items (row block J, 16-column group) in decreasing cost, dealt in snake order
+            const int nJ = mfma_row_blocks(L);
+            const int n_items = nJ * 4;
+            for (int it = 0; it < n_items; ++it) {
+                const int round = it / kWaves, pos = it - round * kWaves;
+                const int owner = (round & 1) ? (kWaves - 1 - pos) : pos;
+                if (owner != wave) continue;
+                const int J = it >> 2, col = it & 3;
+                const int K = mfma_ksteps(L, J);  // a multiple of kMfmaChunk
+                // A fragments stream from L2 (coalesced, one chunk ahead), B from LDS. (Staging
+                // them in LDS measured slower: it holds registers through phase 1.)
+                const float* ag = rec.wb + (size_t)mfma_kstep_offset(L, J) * kWave + lane;
+                const int brow = kMfmaM * J + (lane >> 4);
+                const int bcol = col * 16 + (lane & 15);
+                floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+                floatx4 acc2 = {0.f, 0.f, 0.f, 0.f};
+                float an[kMfmaChunk];
+#pragma unroll
+                for (int u = 0; u < kMfmaChunk; ++u) an[u] = ag[u * kWave];
+                for (int ks = 0; ks < K; ks += kMfmaChunk) {
+                    float ac[kMfmaChunk], bv[kMfmaChunk];
+#pragma unroll
+                    for (int u = 0; u < kMfmaChunk; ++u) {
+                        ac[u] = an[u];
+                        an[u] = ag[min(ks + kMfmaChunk + u, K - 1) * kWave];
+                        bv[u] = es[es_index<T>(brow + kMfmaK * (ks + u), bcol)];
+                    }
+#pragma unroll
+                    for (int u = 0; u < kMfmaChunk; u += 2) {
+                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ac[u], bv[u], acc, 0, 0, 0);
+                        acc2 = __builtin_amdgcn_mfma_f32_16x16x4f32(ac[u + 1], bv[u + 1], acc2, 0, 0, 0);
+                    }
+                }
+                acc += acc2;
+                // this lane holds rows 16J + 4(lane/16) + r of column bcol
+                double pp = 0.0;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int j = kMfmaM * J + 4 * (lane >> 4) + r;
+                    if (j <= L - 2) pp += cw_s[j] * (double)(-expm1f(-acc[r]));
+                }
+                pp += __shfl_xor(pp, 16);
+                pp += __shfl_xor(pp, 32);
+                if (lane < 16) part[J * kTileNu + bcol] = pp;
+            }
+            __syncthreads();
+            if (wave == 0) {
+                double s = rec.hdr->base;
+                for (int J = 0; J < nJ; ++J) s += part[J * kTileNu + lane];
+                dval = s / rec.hdr->rs2;
+            }
+        } else {
+            // FP64: vector ALU, 8-row register blocks, chord weights as uniform loads
+            double acc = 0.0;
+            const int nbu = (L - 1 + kRows - 1) / kRows;
+            for (int blk = 0; blk < nbu; ++blk) {
+                const int round = blk / kWaves, pos = blk - round * kWaves;
+                const int owner = (round & 1) ? (kWaves - 1 - pos) : pos;
+                if (owner != wave) continue;
+                const int j0 = blk * kRows;
+                T t[kRows];
+#pragma unroll
+                for (int r = 0; r < kRows; ++r) t[r] = T(0);
+                const T* __restrict__ wcol = rec.wb + (size_t)blk * L * kRows;
+                for (int l = j0; l < L; ++l) {
+                    const T e = es[es_index<T>(l, lane)];
+#pragma unroll
+                    for (int r = 0; r < kRows; ++r) t[r] = fma(wcol[l * kRows + r], e, t[r]);
+                }
+#pragma unroll
+                for (int r = 0; r < kRows; ++r) {
+                    const int j = j0 + r;
+                    if (j <= L - 2) acc += cw_s[j] * (double)(-dev_expm1(-t[r]));
+                }
+            }
+            part[wave * kTileNu + lane] = acc;
+            __syncthreads();
+            if (wave == 0) {
+                double s = rec.hdr->base;
+                for (int w2 = 0; w2 < kWaves; ++w2) s += part[w2 * kTileNu + lane];
+                dval = s / rec.hdr->rs2;
+            }
+        }
+    }
+    if (wave == 0) {
+        if (valid) dout[nu] = dval;
+        dsh[lane] = dval;
+    }
+
+    // ---- phase 3: channels of this tile; chi^2 partial; last tile sums the partials ----
+    if (binned == nullptr || !sg.fused_bins) return;
+    __syncthreads();
+    const int bw = m.bin_width;
+    const int nbt = sg.tile_w / bw;   // whole channels per tile
+    const int nbins = Nnu / bw;
+    const bool want_chi2 = (chi2 != nullptr) && m.data && m.err;
+    double* bout = binned + sg.bin_off + (size_t)s_in * nbins;
+    if (wave == 0) {
+        double term = 0.0;
+        const int cg = tile * nbt + lane;
+        if (lane < nbt && cg < nbins) {
+            double acc = 0.0;
+            for (int q = 0; q < bw; ++q) acc += dsh[lane * bw + q];
+            const double mean = acc / bw;
+            bout[cg] = mean;
+            if (want_chi2) {
+                const double d = (mean - m.data[cg]) / m.err[cg];
+                term = d * d;
+            }
+        }
+        if (want_chi2) {
+            // fixed-order butterfly over the wave
+            for (int o = 32; o > 0; o >>= 1) term += __shfl_xor(term, o);
+            if (lane == 0) rec.chi2part[tile] = term;
+        }
+    }
+}
+
+template <typename T, int kW, bool kNT>
+int launch_k_forward(const HostPlan& hp, const LaunchPlan& lp, size_t lds, char* ws, const int32_t* act,
+                            double* depth, double* binned, double* c2, hipStream_t st, hipEvent_t ev0,
+                            hipEvent_t ev1) {
+    const dim3 grid(lp.total_wgs), block(kW * kWave);
+    int code = BM_OK;
+    switch (hp.n_species) {
+#define BM_FWD_LAUNCH(NS, CIA)                                                                     \
+    code = ensure_dynamic_lds((const void*)k_forward<T, kW, NS, CIA, kNT>, lds);                   \
+    if (code != BM_OK) return code;                                                                \
+    hipExtLaunchKernelGGL((k_forward<T, kW, NS, CIA, kNT>), grid, block, lds, st, ev0, ev1, 0, lp, ws, act, depth, \
+                          binned, c2);
+#define BM_FWD_CASE(NS)              \
+    case NS:                         \
+        if (hp.cia) {                \
+            BM_FWD_LAUNCH(NS, true)  \
+        } else {                     \
+            BM_FWD_LAUNCH(NS, false) \
+        }                            \
+        break;
+        BM_FWD_CASE(1) BM_FWD_CASE(2) BM_FWD_CASE(3) BM_FWD_CASE(4)
+        BM_FWD_CASE(5) BM_FWD_CASE(6) BM_FWD_CASE(7) BM_FWD_CASE(8)
+#undef BM_FWD_CASE
+#undef BM_FWD_LAUNCH
+        default: return BM_ESHAPE;
+    }
+    BM_CHECK_HIP(hipGetLastError());
+    return BM_OK;
+}
+
+}  // namespace bm

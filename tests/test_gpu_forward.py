@@ -248,3 +248,45 @@ def test_fused_channel_widths(bw):
     err = np.full(nb, 1e-4)
     params = wl.line2013_prior(4).draw(2, seed=19 + bw)
     _check_fused(s, sigma, cia, params, rtol=1e-4, data=data, err=err)
+
+
+def test_launch_configurations_are_bit_identical_and_tunable():
+    # every launch configuration computes each optical depth and partial sum in the same
+    # order, so the outputs agree bit for bit; the first matches the oracle elsewhere
+    s, sigma, cia = small_config2(n_nu=900, n_layers=70, seed=31)
+    nb = s.nu.size // s.bin_width
+    data, err = np.full(nb, 0.02), np.full(nb, 6e-5)
+    model = gpu_model(s, sigma, cia, data=data, err=err)
+    B = 6
+    params = torch.as_tensor(prior_for(s).draw(B, seed=32), device="cuda")
+    f = bm.Forward(model, B, binned=True, chi2=True)
+    ref = None
+    for c in range(len(bm.forward_configs())):
+        f.set_config(c)
+        f(params)
+        out = (f.depth.clone(), f.binned.clone(), f.chi2.clone(), f.flags.clone())
+        if ref is None:
+            ref = out
+        else:
+            for a, b in zip(ref, out):
+                assert torch.equal(a, b), c
+    chosen, times = f.tune(params, reps=2)
+    assert 0 <= chosen < len(times) and times[chosen] > 0
+    assert times[chosen] == min(t for t in times if t > 0)
+    f(params)
+    assert torch.equal(f.depth, ref[0]) and torch.equal(f.chi2, ref[2])
+    f.set_config(-1)
+
+
+def test_kernel_timing_counts_launches():
+    s, sigma, cia = small_config2(n_nu=600, n_layers=60, seed=33)
+    model = gpu_model(s, sigma, cia)
+    f = bm.Forward(model, 2)
+    params = torch.as_tensor(prior_for(s).draw(2, seed=34), device="cuda")
+    with bm.KernelTiming(3) as t:
+        for _ in range(5):
+            f(params)
+    assert t.launches == 3 and t.total_ms > 0
+    with bm.KernelTiming(10) as t2:
+        f(params)
+    assert t2.launches == 1
