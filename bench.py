@@ -128,6 +128,10 @@ def section_forward(args, setup, model, prior):
     params = torch.as_tensor(prior.draw(n_draw, seed=args.seed + 1), device="cuda").contiguous()
     rows = [params[i:i + 1] for i in range(n_draw)]
     f = bm.Forward(model, 1, binned=True, chi2=True)
+    chosen, times = f.tune(rows[0], reps=50)
+    cfg_names = bm.forward_configs()
+    log(f"forward: autotuned one-spectrum call -> config {chosen} ({cfg_names[chosen]}); us per call "
+        f"{[round(t * 1e3, 1) for t in times]}")
     for i in range(args.warmup):
         f(rows[i])
     torch.cuda.synchronize()
@@ -163,6 +167,7 @@ def section_forward(args, setup, model, prior):
                      "call_us": ms * 1e3,
                      "call_frac": bytes_spec / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "last_flags": int(f.flags[0]),
+        "autotune": {"chosen": chosen, "configs": cfg_names, "ms_per_call": times},
     }
     if args.workers > 1:
         out["multi_worker"] = multi_worker(args, model, rows)

@@ -17,6 +17,7 @@ struct AtmShared {
     double ndens[BM_MAX_LAYERS];
     double lnp[BM_MAX_LAYERS];
     double scan[BM_MAX_LAYERS];
+    double wave_tot[kAtmThreads / kWave];
     double x[BM_MAX_SPECIES];
     double theta[5 + BM_MAX_SPECIES + 1];
     Line2013Consts tp;
@@ -35,8 +36,13 @@ __device__ void atm_compute(const ModelDev& m, const double* __restrict__ theta_
     if (tid < np) sh.theta[tid] = theta_g[tid];
     if (tid < m.NT && m.temp) sh.tgrid[tid] = m.temp[tid];
     if (tid < m.NTc && m.temp_cia) sh.tgrid_cia[tid] = m.temp_cia[tid];
+    // with L <= 128 the Line-2013 profile's two xi() terms of layer l are evaluated by
+    // threads l and l + 128 (a dependent chain half as long)
+    const bool split = (m.tp_mode == BM_TP_LINE2013) && (2 * L <= kAtmThreads);
+    const int lay = split ? (tid & (kAtmThreads / 2 - 1)) : tid;
+    const bool upper = split && tid >= kAtmThreads / 2;
     double p = 0.0;
-    if (tid < L) p = m.p_bar[tid];
+    if (lay < L && (split || tid < L)) p = m.p_bar[lay];
     __syncthreads();
     const double* theta = sh.theta;
     // per-sample constants, each on its own thread
@@ -62,7 +68,19 @@ __device__ void atm_compute(const ModelDev& m, const double* __restrict__ theta_
         sh.flags = flags;
     }
     // temperature, number density and ln p per layer
-    if (tid < L) {
+    if (split) {
+        const double tau = line2013_tau(p, sh.tp);
+        double xi = 0.0;
+        if (lay < L) xi = line2013_xi(upper ? sh.tp.g2 : sh.tp.g1, tau);
+        if (upper && lay < L) sh.scan[lay] = xi;  // scratch until the radius scan
+        if (!upper && lay < L) sh.lnp[lay] = log(p);
+        __syncthreads();
+        if (tid < L) {
+            const double t = line2013_temperature_xi(tau, xi, sh.scan[tid], sh.tp);
+            sh.temp[tid] = t;
+            sh.ndens[tid] = p * kBar / (kBoltz * t);
+        }
+    } else if (tid < L) {
         const double t = (m.tp_mode == BM_TP_ISOTHERMAL) ? theta[0] : line2013_temperature_c(p, sh.tp);
         sh.temp[tid] = t;
         sh.ndens[tid] = p * kBar / (kBoltz * t);
@@ -72,16 +90,22 @@ __device__ void atm_compute(const ModelDev& m, const double* __restrict__ theta_
     if (tid < L && !(isfinite(sh.temp[tid]) && sh.temp[tid] > 0.0)) atomicOr(&sh.flags, BM_FLAG_NONFINITE);
     // hydrostatic radii: 1/r_l = 1/R_ref + k_B/(GM mu m_u) (I_l - I_ref), with I the
     // exact integral of the piecewise-linear (in ln p) temperature from layer 0:
-    // segment integrals, then an inclusive Hillis-Steele scan over layers
-    if (tid < L) sh.scan[tid] = (tid > 0) ? (sh.lnp[tid] - sh.lnp[tid - 1]) * 0.5 * (sh.temp[tid - 1] + sh.temp[tid]) : 0.0;
-    __syncthreads();
-    for (int off = 1; off < L; off <<= 1) {
-        double v = 0.0;
-        if (tid < L && tid >= off) v = sh.scan[tid - off];
+    // segment integrals, an inclusive scan within each wave (shuffles), then each wave
+    // adds the totals of the waves before it
+    {
+        double v = (tid > 0 && tid < L) ? (sh.lnp[tid] - sh.lnp[tid - 1]) * 0.5 * (sh.temp[tid - 1] + sh.temp[tid]) : 0.0;
+        const int lane = tid & (kWave - 1), w = tid / kWave;
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) {
+            const double u = __shfl_up(v, off, kWave);
+            if (lane >= off) v += u;
+        }
+        if (lane == kWave - 1) sh.wave_tot[w] = v;
         __syncthreads();
-        if (tid < L && tid >= off) sh.scan[tid] += v;
-        __syncthreads();
+        for (int q = 0; q < w; ++q) v += sh.wave_tot[q];
+        if (tid < L) sh.scan[tid] = v;
     }
+    __syncthreads();
     // the layer m with ln p_m >= ln p_ref > ln p_{m+1} (pressures decrease with l; m is
     // clamped to [0, L-2], i.e. linear extrapolation outside the grid)
     const double lnref = log(m.pl.p_ref_bar);

@@ -5,7 +5,7 @@
 #include <stdint.h>
 #include <math.h>
 
-#include "../../include/bartmi.h"
+#include "bartmi.h"
 
 namespace bm {
 
@@ -105,11 +105,18 @@ __host__ __device__ inline double line2013_xi(double gamma, double tau) {
 
 // T^4 = 3/4 T_int^4 (2/3 + tau) + 3/4 T_irr^4 [(1 - alpha) xi(gamma_1) + alpha xi(gamma_2)],
 // tau = kappa p / g
-__host__ __device__ inline double line2013_temperature_c(double p_bar, const Line2013Consts& c) {
-    const double tau = c.kappa_over_g * (p_bar * kBar);
-    const double t4 = 0.75 * c.tint4 * (2.0 / 3.0 + tau) + 0.75 * c.tirr4 * (1.0 - c.alpha) * line2013_xi(c.g1, tau) +
-                      0.75 * c.tirr4 * c.alpha * line2013_xi(c.g2, tau);
+__host__ __device__ inline double line2013_tau(double p_bar, const Line2013Consts& c) {
+    return c.kappa_over_g * (p_bar * kBar);
+}
+__host__ __device__ inline double line2013_temperature_xi(double tau, double xi1, double xi2,
+                                                          const Line2013Consts& c) {
+    const double t4 = 0.75 * c.tint4 * (2.0 / 3.0 + tau) + 0.75 * c.tirr4 * (1.0 - c.alpha) * xi1 +
+                      0.75 * c.tirr4 * c.alpha * xi2;
     return sqrt(sqrt(t4));
+}
+__host__ __device__ inline double line2013_temperature_c(double p_bar, const Line2013Consts& c) {
+    const double tau = line2013_tau(p_bar, c);
+    return line2013_temperature_xi(tau, line2013_xi(c.g1, tau), line2013_xi(c.g2, tau), c);
 }
 
 __host__ __device__ inline double line2013_temperature(double p_bar, const double* tp, const bm_planet& pl) {

@@ -12,15 +12,15 @@ namespace bm {
 
 // the fused kernel's launchers are instantiated in fwd_f32_nt.hip, fwd_f32_t.hip and
 // fwd_f64.hip (compiled in parallel)
-#define BM_FWD_EXTERN(T, W, NT)                                                                            \
-    extern template int launch_k_forward<T, W, NT>(const HostPlan&, const LaunchPlan&, size_t, char*,       \
-                                                    const int32_t*, double*, double*, double*, hipStream_t, \
-                                                    hipEvent_t, hipEvent_t);
-BM_FWD_EXTERN(float, 8, true)
-BM_FWD_EXTERN(float, 4, true)
-BM_FWD_EXTERN(float, 8, false)
-BM_FWD_EXTERN(float, 4, false)
-BM_FWD_EXTERN(double, 8, true)
+#define BM_FWD_EXTERN(T, W, NT, SA)                                                                    \
+    extern template int launch_k_forward<T, W, NT, SA>(const HostPlan&, const LaunchPlan&, size_t, char*,  \
+                                                        const int32_t*, double*, double*, double*,        \
+                                                        hipStream_t, hipEvent_t, hipEvent_t);
+BM_FWD_EXTERN(float, 8, true, true)
+BM_FWD_EXTERN(float, 8, true, false)
+BM_FWD_EXTERN(float, 8, false, true)
+BM_FWD_EXTERN(float, 8, false, false)
+BM_FWD_EXTERN(double, 8, true, false)
 #undef BM_FWD_EXTERN
 // chi^2 of each sample: the tiles' partials summed in a fixed tree (one workgroup per
 // sample, after the forward kernel: the kernel boundary orders the partial writes)
@@ -263,25 +263,33 @@ static int build_plans(const bm_model* models, int n_models, const int32_t* inst
 }
 
 // Launch configurations of the fused forward kernel that the autotuner chooses from:
-// waves per workgroup (phase-1 layers per wave, phase-2 items per wave, workgroups per
-// CU) and whether table rows are loaded non-temporally (streamed once: best for one
-// spectrum) or through the caches (rows shared by the samples of a tile in a batch).
+// table rows loaded non-temporally (streamed once: one spectrum) or through the caches
+// (rows shared by the samples of a tile in a batch), and the FP32 chord weights copied
+// into LDS during phase 1 (short phase 2, more LDS per workgroup) or streamed from L2 in
+// phase 2 (more workgroups per CU).
 struct FwdConfig {
     int waves;
     bool nontemporal;
+    bool stage_a;
     const char* name;
 };
 constexpr FwdConfig kFwdConfigs[] = {
-    {8, true, "8 waves/workgroup, non-temporal table loads"},
-    {8, false, "8 waves/workgroup, cached table loads"},
-    {4, true, "4 waves/workgroup, non-temporal table loads"},
-    {4, false, "4 waves/workgroup, cached table loads"},
+    {8, true, true, "non-temporal table loads, chord weights staged in LDS"},
+    {8, false, true, "cached table loads, chord weights staged in LDS"},
+    {8, true, false, "non-temporal table loads, chord weights streamed from L2"},
+    {8, false, false, "cached table loads, chord weights streamed from L2"},
 };
 constexpr int kNumFwdConfigs = sizeof(kFwdConfigs) / sizeof(kFwdConfigs[0]);
+// the same table-load mode with the chord weights streamed (when staging does not fit LDS)
+constexpr int kStreamedOf[kNumFwdConfigs] = {2, 3, 2, 3};
 
+// dynamic LDS of a launch; the staged configurations add their static staging arrays
 template <typename T>
 static size_t forward_lds_bytes(int max_L, int waves, int max_ntc) {
     return FwdLds<T>(max_L, waves, max_ntc).total;
+}
+static size_t static_lds_bytes(bool stage_a) {
+    return stage_a ? sizeof(float) * (kStageMaxFloats + 4 * kWave) : 0;
 }
 
 // Dynamic LDS above 64 KB must be enabled per kernel; the device limit is queried once.
@@ -341,10 +349,13 @@ template <typename T>
 static int launch_forward(const HostPlan& hp, int cfg, const double* params, int stride, const int32_t* active,
                           double* depth, double* binned, double* chi2, int32_t* flags, char* ws, hipStream_t st) {
     // FP64 (the parity mode) has the default configuration only
-    if (sizeof(T) == 8 || cfg < 0 || cfg >= kNumFwdConfigs) cfg = 0;
-    const FwdConfig& fc = kFwdConfigs[cfg];
-    const size_t lds = forward_lds_bytes<T>(hp.max_L, fc.waves, hp.max_ntc);
-    if (lds > device_lds_limit()) return BM_ESHAPE;
+    if (cfg < 0 || cfg >= kNumFwdConfigs) cfg = 0;
+    if (sizeof(T) == 8) cfg = kStreamedOf[0];
+    const size_t lds = forward_lds_bytes<T>(hp.max_L, kFwdConfigs[cfg].waves, hp.max_ntc);
+    if (kFwdConfigs[cfg].stage_a &&
+        (hp.max_L > kStageMaxLayers || lds + static_lds_bytes(true) > device_lds_limit()))
+        cfg = kStreamedOf[cfg];
+    if (lds + static_lds_bytes(kFwdConfigs[cfg].stage_a) > device_lds_limit()) return BM_ESHAPE;
     for (size_t p = 0; p < hp.plans.size(); ++p) {
         const LaunchPlan& lp = hp.plans[p];
         const int b0 = hp.first_sample[p];
@@ -360,13 +371,13 @@ static int launch_forward(const HostPlan& hp, int cfg, const double* params, int
         timing_slot(st, &e0, &e1);
         int code;
         if constexpr (sizeof(T) == 8) {
-            code = launch_k_forward<T, 8, true>(hp, lp, lds, ws, act, depth, binned, c2, st, e0, e1);
+            code = launch_k_forward<T, 8, true, false>(hp, lp, lds, ws, act, depth, binned, c2, st, e0, e1);
         } else {
             switch (cfg) {
-                case 1: code = launch_k_forward<T, 8, false>(hp, lp, lds, ws, act, depth, binned, c2, st, e0, e1); break;
-                case 2: code = launch_k_forward<T, 4, true>(hp, lp, lds, ws, act, depth, binned, c2, st, e0, e1); break;
-                case 3: code = launch_k_forward<T, 4, false>(hp, lp, lds, ws, act, depth, binned, c2, st, e0, e1); break;
-                default: code = launch_k_forward<T, 8, true>(hp, lp, lds, ws, act, depth, binned, c2, st, e0, e1); break;
+                case 1: code = launch_k_forward<T, 8, false, true>(hp, lp, lds, ws, act, depth, binned, c2, st, e0, e1); break;
+                case 2: code = launch_k_forward<T, 8, true, false>(hp, lp, lds, ws, act, depth, binned, c2, st, e0, e1); break;
+                case 3: code = launch_k_forward<T, 8, false, false>(hp, lp, lds, ws, act, depth, binned, c2, st, e0, e1); break;
+                default: code = launch_k_forward<T, 8, true, true>(hp, lp, lds, ws, act, depth, binned, c2, st, e0, e1); break;
             }
         }
         if (code != BM_OK) return code;

@@ -44,6 +44,14 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 //   cw    impact-parameter weights [L] (double)
 //   u     CIA rows of the tile [NTc][64] (double) during phase 1; afterwards the
 //         per-row-block partial sums [blocks][64] and the tile's depths [64]
+// staged configurations keep the sample's FP32 chord-weight fragments in a static LDS
+// array, copied from the record straight into LDS while phase 1 streams the tables; it
+// holds the fragments of up to kStageMaxLayers layers (36 KB)
+constexpr int kStageMaxLayers = 128;
+constexpr int kStageMaxFloats = 144 * kWave;  // mfma_total_ksteps(128) k-steps of 64 lanes
+constexpr int kStageChunks = kStageMaxFloats / (4 * kWave);  // 16-byte-per-lane copies
+constexpr int kStageChunksPerWave = (kStageChunks + 7) / 8;  // 8 waves per workgroup
+
 template <typename T>
 struct FwdLds {
     size_t es, cw, ciat, part, bins, total;
@@ -86,11 +94,18 @@ __device__ __forceinline__ double lane_get(double v, int i) {
     return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
 }
 
-template <typename T, int kWaves, int kS, bool kCia, bool kNonTemporal>
+typedef __attribute__((address_space(3))) void* lds_void_ptr;
+
+template <typename T, int kWaves, int kS, bool kCia, bool kNonTemporal, bool kStageA>
 __global__ void __launch_bounds__(kWaves * kWave)
     k_forward(LaunchPlan plan, char* __restrict__ ws, const int32_t* __restrict__ active,
               double* __restrict__ depth, double* __restrict__ binned, double* __restrict__ chi2) {
     extern __shared__ __align__(16) char smem[];
+    // staged chord-weight fragments: a separate LDS object, so that the compiler can tell
+    // phase 1's LDS traffic from the in-flight copies and does not wait for them there
+    __shared__ __align__(16) float wa_s[kStageA ? kStageMaxFloats : 1];
+    __shared__ __align__(16) float wa_dummy[kStageA ? 4 * kWave : 1];
+    static_assert(!kStageA || (kWaves == 8 && sizeof(T) == 4), "staging is laid out for 8 FP32 waves");
     const int si = plan.segment_of_wg(blockIdx.x);
     const Segment& sg = plan.seg[si];
     const ModelDev& m = plan.model[sg.model];
@@ -123,6 +138,22 @@ __global__ void __launch_bounds__(kWaves * kWave)
     double dval = __builtin_nan("");  // this lane's depth (wave 0)
 
     if (!(flags & BM_FLAG_RADIUS)) {
+        if constexpr (kStageA && sizeof(T) == 4) {
+            // chord-weight fragments record -> LDS without passing through registers
+            // (global_load_lds: lane i of a wave writes 16 bytes at dst + 16 i). Every wave
+            // issues the same fixed number of copies, so the compiler's memory-counter waits
+            // stay exact; copies past the sample's fragments reread chunk 0 into a dummy
+            // LDS row. They overlap the prologue's loads and are complete at its barrier.
+            const int n_chunks = mfma_total_ksteps(L) * kWave / (4 * kWave);  // <= kStageChunks
+#pragma unroll
+            for (int i = 0; i < kStageChunksPerWave; ++i) {
+                const int q = wave + kWaves * i;
+                const bool real = q < n_chunks;
+                const float* src = rec.wb + (real ? q : 0) * 4 * kWave + 4 * lane;
+                float* dst = real ? wa_s + q * 4 * kWave : wa_dummy;
+                __builtin_amdgcn_global_load_lds((const void*)src, (lds_void_ptr)dst, 16, 0, 0);
+            }
+        }
         // impact-parameter weights to LDS (read per optical depth in phase 2)
         double* cw_s = reinterpret_cast<double*>(smem + lay.cw);
         for (int i = threadIdx.x; i < L; i += kWaves * kWave) cw_s[i] = rec.cw[i];
@@ -208,6 +239,7 @@ __global__ void __launch_bounds__(kWaves * kWave)
             // zero rows past the last layer (read, against zero weights, by padded k-steps)
             for (int i = threadIdx.x; i < (lay.es_rows - L) * kTileNu; i += kWaves * kWave) es[L * kTileNu + i] = T(0);
         }
+        if constexpr (kStageA) __builtin_amdgcn_s_waitcnt(0);  // this wave's LDS copies are done
         __syncthreads();
 
         // ---- phase 2: chord optical depth, 1 - exp(-tau), impact-parameter sum -------
@@ -221,28 +253,45 @@ __global__ void __launch_bounds__(kWaves * kWave)
                 if (owner != wave) continue;
                 const int J = it >> 2, col = it & 3;
                 const int K = mfma_ksteps(L, J);  // a multiple of kMfmaChunk
-                // A fragments stream from L2 (coalesced, one chunk ahead), B from LDS. (Staging
-                // them in LDS measured slower: it holds registers through phase 1.)
-                const float* ag = rec.wb + (size_t)mfma_kstep_offset(L, J) * kWave + lane;
                 const int brow = kMfmaM * J + (lane >> 4);
                 const int bcol = col * 16 + (lane & 15);
                 floatx4 acc = {0.f, 0.f, 0.f, 0.f};
                 floatx4 acc2 = {0.f, 0.f, 0.f, 0.f};
-                float an[kMfmaChunk];
+                if constexpr (kStageA) {
+                    // A fragments and B from LDS
+                    const float* wa = wa_s + (size_t)mfma_kstep_offset(L, J) * kWave + lane;
+                    for (int ks = 0; ks < K; ks += kMfmaChunk) {
+                        float ac[kMfmaChunk], bv[kMfmaChunk];
 #pragma unroll
-                for (int u = 0; u < kMfmaChunk; ++u) an[u] = ag[u * kWave];
-                for (int ks = 0; ks < K; ks += kMfmaChunk) {
-                    float ac[kMfmaChunk], bv[kMfmaChunk];
+                        for (int u = 0; u < kMfmaChunk; ++u) {
+                            ac[u] = wa[(ks + u) * kWave];
+                            bv[u] = es[es_index<T>(brow + kMfmaK * (ks + u), bcol)];
+                        }
 #pragma unroll
-                    for (int u = 0; u < kMfmaChunk; ++u) {
-                        ac[u] = an[u];
-                        an[u] = ag[min(ks + kMfmaChunk + u, K - 1) * kWave];
-                        bv[u] = es[es_index<T>(brow + kMfmaK * (ks + u), bcol)];
+                        for (int u = 0; u < kMfmaChunk; u += 2) {
+                            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ac[u], bv[u], acc, 0, 0, 0);
+                            acc2 = __builtin_amdgcn_mfma_f32_16x16x4f32(ac[u + 1], bv[u + 1], acc2, 0, 0, 0);
+                        }
                     }
+                } else {
+                    // A fragments stream from L2 (coalesced, one chunk ahead), B from LDS
+                    const float* ag = rec.wb + (size_t)mfma_kstep_offset(L, J) * kWave + lane;
+                    float an[kMfmaChunk];
 #pragma unroll
-                    for (int u = 0; u < kMfmaChunk; u += 2) {
-                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ac[u], bv[u], acc, 0, 0, 0);
-                        acc2 = __builtin_amdgcn_mfma_f32_16x16x4f32(ac[u + 1], bv[u + 1], acc2, 0, 0, 0);
+                    for (int u = 0; u < kMfmaChunk; ++u) an[u] = ag[u * kWave];
+                    for (int ks = 0; ks < K; ks += kMfmaChunk) {
+                        float ac[kMfmaChunk], bv[kMfmaChunk];
+#pragma unroll
+                        for (int u = 0; u < kMfmaChunk; ++u) {
+                            ac[u] = an[u];
+                            an[u] = ag[min(ks + kMfmaChunk + u, K - 1) * kWave];
+                            bv[u] = es[es_index<T>(brow + kMfmaK * (ks + u), bcol)];
+                        }
+#pragma unroll
+                        for (int u = 0; u < kMfmaChunk; u += 2) {
+                            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ac[u], bv[u], acc, 0, 0, 0);
+                            acc2 = __builtin_amdgcn_mfma_f32_16x16x4f32(ac[u + 1], bv[u + 1], acc2, 0, 0, 0);
+                        }
                     }
                 }
                 acc += acc2;
@@ -330,7 +379,7 @@ __global__ void __launch_bounds__(kWaves * kWave)
     }
 }
 
-template <typename T, int kW, bool kNT>
+template <typename T, int kW, bool kNT, bool kSA>
 int launch_k_forward(const HostPlan& hp, const LaunchPlan& lp, size_t lds, char* ws, const int32_t* act,
                             double* depth, double* binned, double* c2, hipStream_t st, hipEvent_t ev0,
                             hipEvent_t ev1) {
@@ -338,10 +387,10 @@ int launch_k_forward(const HostPlan& hp, const LaunchPlan& lp, size_t lds, char*
     int code = BM_OK;
     switch (hp.n_species) {
 #define BM_FWD_LAUNCH(NS, CIA)                                                                     \
-    code = ensure_dynamic_lds((const void*)k_forward<T, kW, NS, CIA, kNT>, lds);                   \
+    code = ensure_dynamic_lds((const void*)k_forward<T, kW, NS, CIA, kNT, kSA>, lds);              \
     if (code != BM_OK) return code;                                                                \
-    hipExtLaunchKernelGGL((k_forward<T, kW, NS, CIA, kNT>), grid, block, lds, st, ev0, ev1, 0, lp, ws, act, depth, \
-                          binned, c2);
+    hipExtLaunchKernelGGL((k_forward<T, kW, NS, CIA, kNT, kSA>), grid, block, lds, st, ev0, ev1, 0, lp, ws, act,   \
+                          depth, binned, c2);
 #define BM_FWD_CASE(NS)              \
     case NS:                         \
         if (hp.cia) {                \
