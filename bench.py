@@ -102,19 +102,21 @@ def spectrum_flops(S, L, N):
     return N * (4 * S * L + L * (L + 1) + 4 * L)
 
 
-def traffic_from_profile(kernel_source: str):
-    """HBM bytes per launch of the fused kernel from the committed counter summary, if the
-    kernel source has not changed since the counters were taken (else None)."""
+def traffic_from_profile(workload: str, config: int):
+    """HBM bytes per launch of the fused kernel (counter runs summarised in
+    profiles/forward_traffic.json) for a workload and launch configuration, or None when
+    the kernel source has changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "forward_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    with open(kernel_source, "rb") as f:
+    with open(os.path.join(ROOT, rec["kernel_source"]), "rb") as f:
         digest = hashlib.sha256(f.read()).hexdigest()
     if rec.get("kernel_sha256") != digest:
         return None
-    return rec.get("hbm_bytes_per_launch")
+    entry = rec["workloads"].get(workload, {}).get("configs", {}).get(str(config))
+    return None if entry is None else entry["hbm_bytes_per_launch"]
 
 
 # ----------------------------------------------------------------------------- sections
@@ -155,7 +157,7 @@ def section_forward(args, setup, model, prior):
         f"clock); fused kernel {kt.mean_ms * 1e3:.2f} us over {kt.launches} launches")
     bytes_spec = spectrum_bytes(S, L, N, NTC, nb)
     achieved = bytes_spec / (kt.mean_ms * 1e-3) / 1e9
-    traffic = traffic_from_profile(os.path.join(ROOT, "paper_2104_12522_amd", "csrc", "fwd_kernel.h"))
+    traffic = traffic_from_profile("config2_b1", chosen)
     out = {
         "ms_per_step": ms,
         "value": 1000.0 / ms,
@@ -273,6 +275,7 @@ def section_batched(args, setup, model, prior):
                                               "rows through L2"},
         "fp32": {"achieved": flops_gen / (kt.mean_ms * 1e-3) / 1e12, "peak": FP32_PEAK_TFLOPS,
                  "unit": "TFLOP/s"},
+        "traffic": traffic_from_profile("config2_b256", chosen),
     }
     if args.mixed:
         out["mixed"] = section_mixed(args, prior)
@@ -381,6 +384,12 @@ def section_mcmc(args, setup, prior):
     log(f"mcmc: prior surrogate: {X.shape[0]} spectra in {t_data:.1f} s, {args.epochs} epochs in "
         f"{t_train:.1f} s ({net.step} Adam steps), held-out rms {rms_prior:.2f} ppm")
     del X, Y
+
+    # launch configuration of the C-chain forward call, tuned once for every run below
+    tune_fwd = bm.Forward(model, C, binned=True, chi2=True)
+    chosen, _ = tune_fwd.tune(dev(prior.draw(C, seed=args.seed + 66)), reps=3)
+    log(f"mcmc: {C}-chain forward call tuned -> config {chosen}")
+    del tune_fwd
 
     # 2. burn-in with the exact sampler from the Laplace approximation at the truth
     cov = fisher_covariance(model, truth, prior.lo, prior.hi)
@@ -526,10 +535,34 @@ def section_opacity(args):
     torch.cuda.synchronize()
     ms = start.elapsed_time(end)
     log(f"opacity: build in {ms / 1e3:.2f} s")
+    evals = window_evaluations(lines, nu, temps, p_bar, sample=20000, seed=args.seed + 80)
     return {"lines": n_lines, "n_nu": int(nu.size), "n_temp": int(len(temps)),
             "n_p": int(len(p_bar)), "dtype": "f32 out, f64 accumulation", "cutoff_hwhm": 25.0,
             "seconds": ms / 1e3, "output_gb": out.numel() * 4 / 1e9,
-            "lines_x_cells_per_s": n_lines * len(temps) * len(p_bar) / (ms * 1e-3)}
+            "profile_evaluations": evals, "evaluations_per_s": evals / (ms * 1e-3),
+            "evaluations_note": "window points summed over lines and cells, counted on the host "
+                                "from a 20000-line sample scaled to all lines"}
+
+
+def window_evaluations(lines, nu, temps, p_bar, sample: int, seed: int) -> float:
+    """Profile evaluations of a build: grid points inside each line's 25-HWHM window,
+    summed over (T, p) cells, on a random sample of lines scaled to the full list."""
+    k_b, amu, c_light = 1.380649e-16, 1.66053906660e-24, 2.99792458e10
+    g = np.random.default_rng(seed)
+    n_all = lines.nu0.size
+    idx = g.choice(n_all, min(sample, n_all), replace=False)
+    nu0, g296, mass = lines.nu0[idx], lines.gamma296[idx], lines.mass_amu[idx]
+    dnu, n = nu[1] - nu[0], nu.size
+    total = 0.0
+    for t in temps:
+        sig = nu0 / c_light * np.sqrt(k_b * t / (mass * amu))
+        for p in p_bar:
+            gam = g296 * (p / 1.01325) * np.sqrt(296.0 / t)
+            hw = 25.0 * (0.5346 * gam + np.sqrt(0.2166 * gam * gam + 2.0 * np.log(2.0) * sig * sig))
+            lo = np.clip(np.ceil((nu0 - hw - nu[0]) / dnu), 0, n - 1)
+            hi = np.clip(np.floor((nu0 + hw - nu[0]) / dnu), -1, n - 1)
+            total += float(np.maximum(hi - lo + 1, 0).sum())
+    return total * n_all / idx.size
 
 
 def section_copy(args):

@@ -195,7 +195,9 @@ int bm_forward_batch(const bm_model* models, int n_models, const int32_t* instan
  * `active`; it overwrites the outputs): one warm-up call, then `reps` calls timed with
  * HIP events, and remembers the fastest for the batch signature (dtype, species count,
  * CIA, and each run of samples: layers, wavenumbers, temperatures, bin width, count).
- * Later bm_forward_batch calls with that signature use it; others use configuration 0.
+ * Later bm_forward_batch calls with that signature use it; untuned batches use cached table
+ * loads with chord weights staged in LDS up to 512 workgroups (a few spectra), streamed
+ * from L2 above that.
  * It waits for its events (host-synchronous) and refuses a stream under graph capture
  * (BM_EINVAL): tune first, then capture. `chosen` (host, may be NULL) receives the chosen
  * index, times_ms (host [n_times], may be NULL) the mean time per call of each

@@ -424,11 +424,20 @@ static std::string batch_signature(const bm_model* models, const HostPlan& hp) {
 static std::mutex g_tune_mu;
 static std::map<std::string, int>* g_tuned = nullptr;
 
+// Untuned batches: cached table loads; chord weights staged in LDS while the launch has
+// at most two workgroups per CU (one or a few spectra), streamed from L2 beyond that (LDS
+// would then cap the workgroups per CU). Measured on MI355X for the config-2 shapes.
+static int default_config(const HostPlan& hp) {
+    size_t wgs = 0;
+    for (const LaunchPlan& lp : hp.plans) wgs += (size_t)lp.total_wgs;
+    return wgs <= 2 * 256 ? 1 : 3;
+}
+
 static int tuned_config(const bm_model* models, const HostPlan& hp) {
     std::lock_guard<std::mutex> lock(g_tune_mu);
-    if (!g_tuned || g_tuned->empty()) return 0;
+    if (!g_tuned || g_tuned->empty()) return default_config(hp);
     auto it = g_tuned->find(batch_signature(models, hp));
-    return it == g_tuned->end() ? 0 : it->second;
+    return it == g_tuned->end() ? default_config(hp) : it->second;
 }
 
 static int run_forward(const bm_model* models, const HostPlan& hp, int cfg, const double* params, int stride,
