@@ -37,8 +37,11 @@ __device__ __forceinline__ float silu_grad(float z) {
 // ---- GEMM: C[M][N] = sum_k A(m, k) B(k, n) -------------------------------------------------
 // A(m, k) = A[m * lda + k] (trans_a = 0) or A[k * lda + m] (trans_a = 1); B(k, n) =
 // B[n * ldb + k] (trans_b = 0: B holds rows of length K, as W[out][in]) or B[k * ldb + n].
-// Tiles 64 x 64 x 32, 4 waves, each wave a 32 x 32 quadrant of 2 x 2 MFMA tiles.
-constexpr int kTM = 64, kTN = 64, kTK = 32, kPad = 8;
+// Block tile BM x BN x 32 with 4 waves in a 2 x 2 layout, each wave (BM/2) x (BN/2) of
+// 16 x 16 MFMA tiles. Operand tiles are double-buffered in LDS: the next tile's global
+// loads are in flight while the matrix cores work on the current one. Each thread moves
+// 8 consecutive elements of an operand row (one 16-byte load when the layout allows it).
+constexpr int kTK = 32, kPad = 8;
 
 struct GemmArgs {
     int M, N, K;
@@ -55,48 +58,114 @@ struct GemmArgs {
     uint16_t* out_bf16;       // [M][ldob]
     int ldob;
     float beta;               // out_f32 = beta * out_f32 + result (accumulating modes)
+    int vec_a, vec_b;         // 16-byte operand loads allowed (alignment and extents)
 };
 
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// 8 elements of one operand for tile rows [r0, r0 + R) x k-slice [k0, k0 + 32): chunk t of
+// the tile. Non-transposed: row r = t / 4, k = 8 (t % 4) .. +7 (contiguous in memory).
+// Transposed: k = t / (R / 8), rows 8 (t % (R / 8)) .. +7 (contiguous in memory).
+template <int R>
+struct TileChunk {
+    u32x4 v;
+    __device__ __forceinline__ void load(const uint16_t* __restrict__ X, int ld, int trans, int vec, int rows,
+                                         int K, int r0, int k0, int t) {
+        v = u32x4{0u, 0u, 0u, 0u};
+        if (t >= R * kTK / 8) return;
+        uint16_t e[8];
+        if (!trans) {
+            const int r = r0 + t / (kTK / 8), k = k0 + 8 * (t % (kTK / 8));
+            if (r >= rows) return;
+            const uint16_t* p = X + (size_t)r * ld + k;
+            if (vec) {
+                if (k < K) v = *reinterpret_cast<const u32x4*>(p);  // K % 8 == 0: all 8 or none
+                return;
+            }
+#pragma unroll
+            for (int i = 0; i < 8; ++i) e[i] = (k + i < K) ? p[i] : (uint16_t)0;
+        } else {
+            const int k = k0 + t / (R / 8), r = r0 + 8 * (t % (R / 8));
+            if (k >= K) return;
+            const uint16_t* p = X + (size_t)k * ld + r;
+            if (vec) {
+                if (r < rows) v = *reinterpret_cast<const u32x4*>(p);  // rows % 8 == 0
+                return;
+            }
+#pragma unroll
+            for (int i = 0; i < 8; ++i) e[i] = (r + i < rows) ? p[i] : (uint16_t)0;
+        }
+        v = u32x4{(uint32_t)e[0] | ((uint32_t)e[1] << 16), (uint32_t)e[2] | ((uint32_t)e[3] << 16),
+                  (uint32_t)e[4] | ((uint32_t)e[5] << 16), (uint32_t)e[6] | ((uint32_t)e[7] << 16)};
+    }
+    // into the LDS tile [R][kTK + kPad] (row-major in k)
+    __device__ __forceinline__ void store(uint16_t (*S)[kTK + kPad], int trans, int t) const {
+        if (t >= R * kTK / 8) return;
+        if (!trans) {
+            *reinterpret_cast<u32x4*>(&S[t / (kTK / 8)][8 * (t % (kTK / 8))]) = v;
+        } else {
+            const int k = t / (R / 8), r = 8 * (t % (R / 8));
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                S[r + 2 * i][k] = (uint16_t)(v[i] & 0xffffu);
+                S[r + 2 * i + 1][k] = (uint16_t)(v[i] >> 16);
+            }
+        }
+    }
+};
+
+template <int BM, int BN>
 __global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
-    __shared__ __align__(16) uint16_t As[kTM][kTK + kPad];
-    __shared__ __align__(16) uint16_t Bs[kTN][kTK + kPad];
-    const int m0 = blockIdx.y * kTM, n0 = blockIdx.x * kTN;
+    constexpr int WM = BM / 2, WN = BN / 2;          // wave tile
+    constexpr int TI = WM / 16, TJ = WN / 16;        // MFMA tiles per wave
+    __shared__ __align__(16) uint16_t As[2][BM][kTK + kPad];
+    __shared__ __align__(16) uint16_t Bs[2][BN][kTK + kPad];
+    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-    f32x4 acc[2][2];
-    for (int i = 0; i < 2; ++i)
-        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < g.K; k0 += kTK) {
-        // stage A and B tiles as [row][k]; out-of-range elements are zero
-        // consecutive threads walk the contiguous index of the stored operand
-        for (int e = tid; e < kTM * kTK; e += 256) {
-            const int r = g.trans_a ? e % kTM : e / kTK, kk = g.trans_a ? e / kTM : e % kTK;
-            const int m = m0 + r, k = k0 + kk;
-            uint16_t v = 0;
-            if (m < g.M && k < g.K) v = g.trans_a ? g.A[(size_t)k * g.lda + m] : g.A[(size_t)m * g.lda + k];
-            As[r][kk] = v;
+    const int wm = (wave >> 1) * WM, wn = (wave & 1) * WN;
+    f32x4 acc[TI][TJ];
+#pragma unroll
+    for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int j = 0; j < TJ; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int nk = (g.K + kTK - 1) / kTK;
+    TileChunk<BM> ca;
+    TileChunk<BN> cb;
+    ca.load(g.A, g.lda, g.trans_a, g.vec_a, g.M, g.K, m0, 0, tid);
+    cb.load(g.B, g.ldb, g.trans_b, g.vec_b, g.N, g.K, n0, 0, tid);
+    ca.store(As[0], g.trans_a, tid);
+    cb.store(Bs[0], g.trans_b, tid);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        const int cur = kt & 1;
+        if (kt + 1 < nk) {
+            ca.load(g.A, g.lda, g.trans_a, g.vec_a, g.M, g.K, m0, (kt + 1) * kTK, tid);
+            cb.load(g.B, g.ldb, g.trans_b, g.vec_b, g.N, g.K, n0, (kt + 1) * kTK, tid);
         }
-        for (int e = tid; e < kTN * kTK; e += 256) {
-            const int r = g.trans_b ? e % kTN : e / kTK, kk = g.trans_b ? e / kTN : e % kTK;
-            const int n = n0 + r, k = k0 + kk;
-            uint16_t v = 0;
-            if (n < g.N && k < g.K) v = g.trans_b ? g.B[(size_t)k * g.ldb + n] : g.B[(size_t)n * g.ldb + k];
-            Bs[r][kk] = v;
-        }
-        __syncthreads();
         // operands: lane holds 8 consecutive k of row (lane % 16); k offset 8 (lane / 16)
         const int kq = 8 * (lane >> 4);
-        bf16x8 a[2], b[2];
-        for (int i = 0; i < 2; ++i) a[i] = *reinterpret_cast<const bf16x8*>(&As[wm + 16 * i + (lane & 15)][kq]);
-        for (int j = 0; j < 2; ++j) b[j] = *reinterpret_cast<const bf16x8*>(&Bs[wn + 16 * j + (lane & 15)][kq]);
-        for (int i = 0; i < 2; ++i)
-            for (int j = 0; j < 2; ++j)
+        bf16x8 a[TI], b[TJ];
+#pragma unroll
+        for (int i = 0; i < TI; ++i) a[i] = *reinterpret_cast<const bf16x8*>(&As[cur][wm + 16 * i + (lane & 15)][kq]);
+#pragma unroll
+        for (int j = 0; j < TJ; ++j) b[j] = *reinterpret_cast<const bf16x8*>(&Bs[cur][wn + 16 * j + (lane & 15)][kq]);
+#pragma unroll
+        for (int i = 0; i < TI; ++i)
+#pragma unroll
+            for (int j = 0; j < TJ; ++j)
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        if (kt + 1 < nk) {
+            ca.store(As[cur ^ 1], g.trans_a, tid);
+            cb.store(Bs[cur ^ 1], g.trans_b, tid);
+        }
         __syncthreads();
     }
     // epilogue: lane holds C[4 (lane / 16) + r][lane % 16] of each 16 x 16 tile
-    for (int i = 0; i < 2; ++i)
-        for (int j = 0; j < 2; ++j)
+#pragma unroll
+    for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int j = 0; j < TJ; ++j)
+#pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int m = m0 + wm + 16 * i + 4 * (lane >> 4) + r;
                 const int n = n0 + wn + 16 * j + (lane & 15);
@@ -123,13 +192,24 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
             }
 }
 
-// column sums of a bf16 matrix [M][N] (bias gradients), fixed order per column
-__global__ void k_colsum_bf16(const uint16_t* __restrict__ x, int M, int N, float* __restrict__ out, float beta) {
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= N) return;
+// column sums of a bf16 matrix [M][N] (bias gradients): 64 columns per workgroup, four
+// row groups per column summed in a fixed order
+__global__ void __launch_bounds__(256) k_colsum_bf16(const uint16_t* __restrict__ x, int M, int N,
+                                                     float* __restrict__ out, float beta) {
+    __shared__ float part[4][64];
+    const int c = threadIdx.x & 63, grp = threadIdx.x >> 6;
+    const int n = blockIdx.x * 64 + c;
     float s = 0.f;
-    for (int m = 0; m < M; ++m) s += bf2f(x[(size_t)m * N + n]);
-    out[n] = (beta != 0.f ? beta * out[n] : 0.f) + s;
+    if (n < N) {
+#pragma unroll 8
+        for (int m = grp; m < M; m += 4) s += bf2f(x[(size_t)m * N + n]);
+    }
+    part[grp][c] = s;
+    __syncthreads();
+    if (grp == 0 && n < N) {
+        const float tot = (part[0][c] + part[1][c]) + (part[2][c] + part[3][c]);
+        out[n] = (beta != 0.f ? beta * out[n] : 0.f) + tot;
+    }
 }
 
 // network input: h0[b][j] = bf16((theta_j - lo_j) / (hi_j - lo_j)), zero padding to dims[0]
@@ -213,11 +293,23 @@ __global__ void k_surrogate_chi2(const float* __restrict__ out, int B, int N, co
     if (threadIdx.x == 0) chi2[b] = part[0];
 }
 
-static int launch_gemm(const GemmArgs& a, hipStream_t st) {
+static bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+static int launch_gemm(GemmArgs a, hipStream_t st) {
     if (a.M < 0 || a.N < 0 || a.K < 0) return BM_ESHAPE;
     if (a.M == 0 || a.N == 0) return BM_OK;
-    dim3 grid((a.N + kTN - 1) / kTN, (a.M + kTM - 1) / kTM);
-    hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(256), 0, st, a);
+    // 16-byte operand loads: rows of 8-element multiples, aligned base
+    a.vec_a = aligned16(a.A) && a.lda % 8 == 0 && (a.trans_a ? a.M % 8 == 0 : a.K % 8 == 0);
+    a.vec_b = aligned16(a.B) && a.ldb % 8 == 0 && (a.trans_b ? a.N % 8 == 0 : a.K % 8 == 0);
+    // 64 x 64 tiles when they fill the chip, 32 x 32 tiles (4x the workgroups) otherwise
+    const long tiles64 = (long)((a.N + 63) / 64) * ((a.M + 63) / 64);
+    if (tiles64 >= 256) {
+        dim3 grid((a.N + 63) / 64, (a.M + 63) / 64);
+        hipLaunchKernelGGL((k_gemm_bf16<64, 64>), grid, dim3(256), 0, st, a);
+    } else {
+        dim3 grid((a.N + 31) / 32, (a.M + 31) / 32);
+        hipLaunchKernelGGL((k_gemm_bf16<32, 32>), grid, dim3(256), 0, st, a);
+    }
     BM_CHECK_HIP(hipGetLastError());
     return BM_OK;
 }
@@ -315,7 +407,7 @@ extern "C" int bm_mlp_backward(const bm_mlp* net, int B, void* stream) {
                     net->gw[i], K, nullptr, 0, 0.f};
         st = launch_gemm(gw, s);
         if (st != BM_OK) return st;
-        hipLaunchKernelGGL(k_colsum_bf16, dim3((N + 255) / 256), dim3(256), 0, s, dz, B, N, net->gb[i], 0.f);
+        hipLaunchKernelGGL(k_colsum_bf16, dim3((N + 63) / 64), dim3(256), 0, s, dz, B, N, net->gb[i], 0.f);
         BM_CHECK_HIP(hipGetLastError());
         if (i > 0) {
             // dz_{i-1} [B][K] = (dz [B][N] W_i [N][K]) * silu'(z_{i-1})
