@@ -186,3 +186,57 @@ def test_masked_forward_leaves_inactive_samples_untouched():
             assert torch.equal(f.depth[sl], full.depth[sl]) and f.chi2[b] == full.chi2[b]
         else:
             assert torch.equal(f.depth[sl], d0[sl]) and f.chi2[b] == c0[b]
+
+
+def test_surrogate_stage_cuts_exact_evaluations():
+    """What the learned surrogate gains: as stage 1 of delayed acceptance it spares most
+    exact forward evaluations while the exact model, as stage 2, keeps the acceptances."""
+    import math
+    from paper_2104_12522_amd.mcmc import fisher_covariance, gaussian_states
+    from paper_2104_12522_amd.surrogate import MLP, Surrogate, Trainer, standardisation
+    model, truth = _retrieval_setup()
+    C, burn, n_gen = 64, 300, 400
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), device="cuda")  # noqa: E731
+    cov = fisher_covariance(model, truth, PRIOR.lo, PRIOR.hi)
+    rb = Retrieval(model, C, PRIOR.lo, PRIOR.hi, seed=21, thin=5, hist_cap=burn,
+                   z_cap=8 * C + C * (burn // 5 + 2))
+    rb.resume(dev(gaussian_states(truth, cov, C, PRIOR.lo, PRIOR.hi, seed=22)),
+              dev(gaussian_states(truth, cov, 8 * C, PRIOR.lo, PRIOR.hi, seed=23)))
+    rb.run(burn)
+    hb = rb.s.history[burn // 2:burn].cpu().numpy().reshape(-1, PRIOR.lo.size)
+    mu, cb = hb.mean(0), np.cov(hb.T)
+    sd = np.sqrt(np.diag(cb))
+    lo, hi = np.maximum(mu - 5 * sd, PRIOR.lo), np.minimum(mu + 5 * sd, PRIOR.hi)
+    X = dev(gaussian_states(mu, cb, 16384, lo, hi, seed=24, inflate=2.0))
+    f = bm.Forward(model, 4096, binned=True)
+    nb = model.n_bins
+    Y = torch.empty(X.shape[0], nb, dtype=torch.float64, device="cuda")
+    for s0 in range(0, X.shape[0], 4096):
+        f(X[s0:s0 + 4096].contiguous())
+        Y[s0:s0 + 4096] = f.binned.view(4096, nb)
+    mean, scale = standardisation(Y)
+    net = MLP([PRIOR.lo.size, 256, 256, 256, nb], max_batch=4096, seed=5)
+    tr = Trainer(net, dev(lo), dev(hi), X, Y, mean, scale, batch=256, seed=6)
+    for e in range(25):
+        tr.epoch(1e-6 + 0.5 * (2e-3 - 1e-6) * (1 + math.cos(math.pi * e / 25)))
+    sur = Surrogate(net, dev(lo), dev(hi), mean, scale, model.data, model.err, n_chains=4096)
+    x0, z0 = rb.s.x.clone(), rb.s.z[:rb.s.archive_size].clone()
+
+    def production(surrogate):
+        r = Retrieval(model, C, PRIOR.lo, PRIOR.hi, seed=31, thin=5, hist_cap=n_gen,
+                      surrogate=surrogate, z_cap=z0.shape[0] + C * (n_gen // 5 + 1))
+        r.resume(x0, z0)
+        r.run(n_gen)
+        torch.cuda.synchronize()
+        return r.s.n_accept.sum(0).cpu().numpy(), r.s.history.cpu().numpy()
+
+    acc_p, h_p = production(None)
+    acc_d, h_d = production(sur)
+    exact_plain = C * n_gen                  # every proposal needs the exact model
+    exact_da = int(acc_d[0])                 # only stage-1 survivors do
+    assert acc_p[1] > 50
+    assert exact_da < 0.5 * exact_plain, (exact_da, exact_plain)
+    assert acc_d[1] > 0.5 * acc_p[1], (acc_d, acc_p)
+    # posterior location agrees between the two runs (short chains: loose bound)
+    hp, hd = h_p[n_gen // 2:].reshape(-1, PRIOR.lo.size), h_d[n_gen // 2:].reshape(-1, PRIOR.lo.size)
+    assert np.all(np.abs(hd.mean(0) - hp.mean(0)) < 1.0 * hp.std(0) + 1e-12)
