@@ -184,10 +184,10 @@ struct HostPlan {
 };
 
 // launch of the fused kernel for one plan with kW waves per workgroup, non-temporal (kNT)
-// or cached table loads, chord weights staged in LDS (kSA) or streamed from L2
-// (fwd_kernel.h); ev0/ev1 (or null) are timing events that the dispatch itself records at
-// the kernel's start and end
-template <typename T, int kW, bool kNT, bool kSA>
+// or cached table loads, and phase-2 mode kMode (chord weights streamed from L2, staged in
+// LDS, or staged with phases 1 and 2 interleaved; fwd_kernel.h); ev0/ev1 (or null) are
+// timing events that the dispatch itself records at the kernel's start and end
+template <typename T, int kW, bool kNT, int kMode>
 int launch_k_forward(const HostPlan& hp, const LaunchPlan& lp, size_t lds, char* ws, const int32_t* act,
                      double* depth, double* binned, double* c2, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1);
 

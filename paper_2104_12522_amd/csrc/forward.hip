@@ -10,17 +10,19 @@
 
 namespace bm {
 
-// the fused kernel's launchers are instantiated in fwd_f32_nt.hip, fwd_f32_t.hip and
-// fwd_f64.hip (compiled in parallel)
-#define BM_FWD_EXTERN(T, W, NT, SA)                                                                    \
-    extern template int launch_k_forward<T, W, NT, SA>(const HostPlan&, const LaunchPlan&, size_t, char*,  \
-                                                        const int32_t*, double*, double*, double*,        \
-                                                        hipStream_t, hipEvent_t, hipEvent_t);
-BM_FWD_EXTERN(float, 8, true, true)
-BM_FWD_EXTERN(float, 8, true, false)
-BM_FWD_EXTERN(float, 8, false, true)
-BM_FWD_EXTERN(float, 8, false, false)
-BM_FWD_EXTERN(double, 8, true, false)
+// the fused kernel's launchers are instantiated in fwd_f32_nt.hip, fwd_f32_t.hip,
+// fwd_f32_pipe.hip and fwd_f64.hip (compiled in parallel)
+#define BM_FWD_EXTERN(T, W, NT, MODE)                                                                  \
+    extern template int launch_k_forward<T, W, NT, MODE>(const HostPlan&, const LaunchPlan&, size_t, char*, \
+                                                          const int32_t*, double*, double*, double*,      \
+                                                          hipStream_t, hipEvent_t, hipEvent_t);
+BM_FWD_EXTERN(float, 8, true, 1)
+BM_FWD_EXTERN(float, 8, true, 0)
+BM_FWD_EXTERN(float, 8, false, 1)
+BM_FWD_EXTERN(float, 8, false, 0)
+BM_FWD_EXTERN(float, 8, true, 2)
+BM_FWD_EXTERN(float, 8, false, 2)
+BM_FWD_EXTERN(double, 8, true, 0)
 #undef BM_FWD_EXTERN
 // chi^2 of each sample: the tiles' partials summed in a fixed tree (one workgroup per
 // sample, after the forward kernel: the kernel boundary orders the partial writes)
@@ -264,32 +266,42 @@ static int build_plans(const bm_model* models, int n_models, const int32_t* inst
 
 // Launch configurations of the fused forward kernel that the autotuner chooses from:
 // table rows loaded non-temporally (streamed once: one spectrum) or through the caches
-// (rows shared by the samples of a tile in a batch), and the FP32 chord weights copied
-// into LDS during phase 1 (short phase 2, more LDS per workgroup) or streamed from L2 in
-// phase 2 (more workgroups per CU).
+// (rows shared by the samples of a tile in a batch); the FP32 chord weights copied into
+// LDS at kernel start (short phase 2, more LDS per workgroup), optionally with phases 1
+// and 2 interleaved by 16-layer stages, or streamed from L2 in phase 2 (more workgroups
+// per CU).
 struct FwdConfig {
     int waves;
     bool nontemporal;
-    bool stage_a;
+    int mode;  // kModeStreamed, kModeStaged, kModePipelined
     const char* name;
 };
 constexpr FwdConfig kFwdConfigs[] = {
-    {8, true, true, "non-temporal table loads, chord weights staged in LDS"},
-    {8, false, true, "cached table loads, chord weights staged in LDS"},
-    {8, true, false, "non-temporal table loads, chord weights streamed from L2"},
-    {8, false, false, "cached table loads, chord weights streamed from L2"},
+    {8, true, kModeStaged, "non-temporal table loads, chord weights staged in LDS"},
+    {8, false, kModeStaged, "cached table loads, chord weights staged in LDS"},
+    {8, true, kModeStreamed, "non-temporal table loads, chord weights streamed from L2"},
+    {8, false, kModeStreamed, "cached table loads, chord weights streamed from L2"},
+    {8, true, kModePipelined, "non-temporal table loads, staged chord weights, pipelined stages"},
+    {8, false, kModePipelined, "cached table loads, staged chord weights, pipelined stages"},
 };
 constexpr int kNumFwdConfigs = sizeof(kFwdConfigs) / sizeof(kFwdConfigs[0]);
-// the same table-load mode with the chord weights streamed (when staging does not fit LDS)
-constexpr int kStreamedOf[kNumFwdConfigs] = {2, 3, 2, 3};
 
-// dynamic LDS of a launch; the staged configurations add their static staging arrays
-template <typename T>
-static size_t forward_lds_bytes(int max_L, int waves, int max_ntc) {
-    return FwdLds<T>(max_L, waves, max_ntc).total;
+// the configuration with the same table loads in another phase-2 mode
+static int config_with_mode(int cfg, int mode) {
+    for (int c = 0; c < kNumFwdConfigs; ++c)
+        if (kFwdConfigs[c].nontemporal == kFwdConfigs[cfg].nontemporal && kFwdConfigs[c].mode == mode) return c;
+    return cfg;
 }
-static size_t static_lds_bytes(bool stage_a) {
-    return stage_a ? sizeof(float) * (kStageMaxFloats + 4 * kWave) : 0;
+
+// dynamic LDS of a launch; the staged modes add their static staging arrays
+template <typename T>
+static size_t forward_lds_bytes(int max_L, int waves, int max_ntc, int mode) {
+    return FwdLds<T>(max_L, waves, max_ntc, mode == kModePipelined).total;
+}
+static size_t static_lds_bytes(int mode) {
+    if (mode == kModeStaged) return sizeof(float) * (kStageMaxFloats + 4 * kWave);
+    if (mode == kModePipelined) return sizeof(float) * (kPipeMaxFloats + 4 * kWave);
+    return 0;
 }
 
 // Dynamic LDS above 64 KB must be enabled per kernel; the device limit is queried once.
@@ -350,12 +362,19 @@ static int launch_forward(const HostPlan& hp, int cfg, const double* params, int
                           double* depth, double* binned, double* chi2, int32_t* flags, char* ws, hipStream_t st) {
     // FP64 (the parity mode) has the default configuration only
     if (cfg < 0 || cfg >= kNumFwdConfigs) cfg = 0;
-    if (sizeof(T) == 8) cfg = kStreamedOf[0];
-    const size_t lds = forward_lds_bytes<T>(hp.max_L, kFwdConfigs[cfg].waves, hp.max_ntc);
-    if (kFwdConfigs[cfg].stage_a &&
-        (hp.max_L > kStageMaxLayers || lds + static_lds_bytes(true) > device_lds_limit()))
-        cfg = kStreamedOf[cfg];
-    if (lds + static_lds_bytes(kFwdConfigs[cfg].stage_a) > device_lds_limit()) return BM_ESHAPE;
+    if (sizeof(T) == 8) cfg = config_with_mode(0, kModeStreamed);
+    // modes that do not fit the batch's layers fall back: pipelined -> staged -> streamed
+    auto fits = [&](int c) {
+        const int md = kFwdConfigs[c].mode;
+        if (md == kModePipelined && hp.max_L > kPipeMaxLayers) return false;
+        if (md == kModeStaged && hp.max_L > kStageMaxLayers) return false;
+        return forward_lds_bytes<T>(hp.max_L, kFwdConfigs[c].waves, hp.max_ntc, md) + static_lds_bytes(md) <=
+               device_lds_limit();
+    };
+    if (!fits(cfg) && kFwdConfigs[cfg].mode == kModePipelined) cfg = config_with_mode(cfg, kModeStaged);
+    if (!fits(cfg)) cfg = config_with_mode(cfg, kModeStreamed);
+    if (!fits(cfg)) return BM_ESHAPE;
+    const size_t lds = forward_lds_bytes<T>(hp.max_L, kFwdConfigs[cfg].waves, hp.max_ntc, kFwdConfigs[cfg].mode);
     for (size_t p = 0; p < hp.plans.size(); ++p) {
         const LaunchPlan& lp = hp.plans[p];
         const int b0 = hp.first_sample[p];
@@ -371,14 +390,18 @@ static int launch_forward(const HostPlan& hp, int cfg, const double* params, int
         timing_slot(st, &e0, &e1);
         int code;
         if constexpr (sizeof(T) == 8) {
-            code = launch_k_forward<T, 8, true, false>(hp, lp, lds, ws, act, depth, binned, c2, st, e0, e1);
+            code = launch_k_forward<T, 8, true, kModeStreamed>(hp, lp, lds, ws, act, depth, binned, c2, st, e0, e1);
         } else {
+#define BM_CFG(NT, MODE) launch_k_forward<T, 8, NT, MODE>(hp, lp, lds, ws, act, depth, binned, c2, st, e0, e1)
             switch (cfg) {
-                case 1: code = launch_k_forward<T, 8, false, true>(hp, lp, lds, ws, act, depth, binned, c2, st, e0, e1); break;
-                case 2: code = launch_k_forward<T, 8, true, false>(hp, lp, lds, ws, act, depth, binned, c2, st, e0, e1); break;
-                case 3: code = launch_k_forward<T, 8, false, false>(hp, lp, lds, ws, act, depth, binned, c2, st, e0, e1); break;
-                default: code = launch_k_forward<T, 8, true, true>(hp, lp, lds, ws, act, depth, binned, c2, st, e0, e1); break;
+                case 1: code = BM_CFG(false, kModeStaged); break;
+                case 2: code = BM_CFG(true, kModeStreamed); break;
+                case 3: code = BM_CFG(false, kModeStreamed); break;
+                case 4: code = BM_CFG(true, kModePipelined); break;
+                case 5: code = BM_CFG(false, kModePipelined); break;
+                default: code = BM_CFG(true, kModeStaged); break;
             }
+#undef BM_CFG
         }
         if (code != BM_OK) return code;
         if (c2 && binned) {

@@ -3,10 +3,10 @@
 #include "fwd_kernel.h"
 
 namespace bm {
-template int launch_k_forward<float, 8, true, true>(const HostPlan&, const LaunchPlan&, size_t, char*,
-                                                     const int32_t*, double*, double*, double*, hipStream_t,
-                                                     hipEvent_t, hipEvent_t);
-template int launch_k_forward<float, 8, true, false>(const HostPlan&, const LaunchPlan&, size_t, char*,
-                                                     const int32_t*, double*, double*, double*, hipStream_t,
-                                                     hipEvent_t, hipEvent_t);
+template int launch_k_forward<float, 8, true, 1>(const HostPlan&, const LaunchPlan&, size_t, char*,
+                                                   const int32_t*, double*, double*, double*, hipStream_t,
+                                                   hipEvent_t, hipEvent_t);
+template int launch_k_forward<float, 8, true, 0>(const HostPlan&, const LaunchPlan&, size_t, char*,
+                                                   const int32_t*, double*, double*, double*, hipStream_t,
+                                                   hipEvent_t, hipEvent_t);
 }  // namespace bm

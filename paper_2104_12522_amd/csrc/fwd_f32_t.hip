@@ -3,10 +3,10 @@
 #include "fwd_kernel.h"
 
 namespace bm {
-template int launch_k_forward<float, 8, false, true>(const HostPlan&, const LaunchPlan&, size_t, char*,
-                                                     const int32_t*, double*, double*, double*, hipStream_t,
-                                                     hipEvent_t, hipEvent_t);
-template int launch_k_forward<float, 8, false, false>(const HostPlan&, const LaunchPlan&, size_t, char*,
-                                                     const int32_t*, double*, double*, double*, hipStream_t,
-                                                     hipEvent_t, hipEvent_t);
+template int launch_k_forward<float, 8, false, 1>(const HostPlan&, const LaunchPlan&, size_t, char*,
+                                                   const int32_t*, double*, double*, double*, hipStream_t,
+                                                   hipEvent_t, hipEvent_t);
+template int launch_k_forward<float, 8, false, 0>(const HostPlan&, const LaunchPlan&, size_t, char*,
+                                                   const int32_t*, double*, double*, double*, hipStream_t,
+                                                   hipEvent_t, hipEvent_t);
 }  // namespace bm

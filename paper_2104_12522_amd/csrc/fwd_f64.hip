@@ -3,7 +3,7 @@
 #include "fwd_kernel.h"
 
 namespace bm {
-template int launch_k_forward<double, 8, true, false>(const HostPlan&, const LaunchPlan&, size_t, char*,
-                                                     const int32_t*, double*, double*, double*, hipStream_t,
-                                                     hipEvent_t, hipEvent_t);
+template int launch_k_forward<double, 8, true, 0>(const HostPlan&, const LaunchPlan&, size_t, char*,
+                                                   const int32_t*, double*, double*, double*, hipStream_t,
+                                                   hipEvent_t, hipEvent_t);
 }  // namespace bm

@@ -40,35 +40,57 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 // LDS layout of one forward workgroup (bytes from the start of dynamic shared memory):
 //   es    extinction tile [rows][64] (FP32: L rounded up to 4 plus 16 zero rows, the
-//         furthest a padded k-step reaches)
+//         furthest a padded k-step reaches; pipelined: L rounded up to 16)
 //   cw    impact-parameter weights [L] (double)
 //   u     CIA rows of the tile [NTc][64] (double) during phase 1; afterwards the
-//         per-row-block partial sums [blocks][64] and the tile's depths [64]
-// staged configurations keep the sample's FP32 chord-weight fragments in a static LDS
-// array, copied from the record straight into LDS while phase 1 streams the tables; it
-// holds the fragments of up to kStageMaxLayers layers (36 KB)
+//         per-row-block partial sums [blocks][64] and the tile's depths [64] (pipelined:
+//         separate regions, since row blocks finish while CIA rows are still read)
+// Staged configurations keep the sample's FP32 chord-weight fragments in a static LDS
+// array, copied from the record straight into LDS at kernel start; it holds the fragments
+// of up to kStageMaxLayers layers (36 KB), or kPipeMaxLayers (28 KB) when pipelined.
 constexpr int kStageMaxLayers = 128;
 constexpr int kStageMaxFloats = 144 * kWave;  // mfma_total_ksteps(128) k-steps of 64 lanes
-constexpr int kStageChunks = kStageMaxFloats / (4 * kWave);  // 16-byte-per-lane copies
-constexpr int kStageChunksPerWave = (kStageChunks + 7) / 8;  // 8 waves per workgroup
+constexpr int kPipeMaxLayers = 112;
+constexpr int kPipeMaxFloats = 112 * kWave;   // mfma_total_ksteps(112)
+
+// launch modes of the fused kernel's FP32 phase 2
+constexpr int kModeStreamed = 0;   // chord weights read from L2 in phase 2
+constexpr int kModeStaged = 1;     // chord weights in LDS, phase 2 after phase 1
+constexpr int kModePipelined = 2;  // chord weights in LDS, phases 1 and 2 interleaved by stage
+
+template <int kMode>
+struct StageSize {
+    static constexpr int floats = kMode == kModeStaged ? kStageMaxFloats : (kMode == kModePipelined ? kPipeMaxFloats : 0);
+    static constexpr int chunks = floats / (4 * kWave);      // 16-byte-per-lane copies
+    static constexpr int chunks_per_wave = (chunks + 7) / 8;  // 8 waves per workgroup
+};
 
 template <typename T>
 struct FwdLds {
     size_t es, cw, ciat, part, bins, total;
     int es_rows;
-    __host__ __device__ FwdLds(int L, int kWaves, int ntc) {
-        es_rows = (sizeof(T) == 4) ? ((L + 3) & ~3) + kMfmaM : L;
+    __host__ __device__ FwdLds(int L, int kWaves, int ntc, bool pipe = false) {
+        if (sizeof(T) == 4)
+            es_rows = pipe ? kMfmaM * ((L + kMfmaM - 1) / kMfmaM) : ((L + 3) & ~3) + kMfmaM;
+        else
+            es_rows = L;
         es = 0;
         size_t o = align_up(sizeof(T) * (size_t)es_rows * kTileNu, 16);
         cw = o;
         o = align_up(o + sizeof(double) * (size_t)L, 16);
         ciat = o;
-        part = o;
         const int nparts = (sizeof(T) == 4) ? mfma_row_blocks(L) : kWaves;
-        bins = part + sizeof(double) * (size_t)nparts * kTileNu;
         size_t u1 = sizeof(double) * (size_t)ntc * kTileNu;
-        size_t u2 = bins + sizeof(double) * kTileNu - o;
-        o += (u1 > u2 ? u1 : u2);
+        if (pipe) {
+            part = align_up(o + u1, 16);
+            bins = part + sizeof(double) * (size_t)nparts * kTileNu;
+            o = bins + sizeof(double) * kTileNu;
+        } else {
+            part = o;
+            bins = part + sizeof(double) * (size_t)nparts * kTileNu;
+            size_t u2 = bins + sizeof(double) * kTileNu - o;
+            o += (u1 > u2 ? u1 : u2);
+        }
         const size_t chi2_part = sizeof(double) * (size_t)kWaves * kWave;
         total = o > chi2_part ? o : chi2_part;
     }
@@ -96,14 +118,16 @@ __device__ __forceinline__ double lane_get(double v, int i) {
 
 typedef __attribute__((address_space(3))) void* lds_void_ptr;
 
-template <typename T, int kWaves, int kS, bool kCia, bool kNonTemporal, bool kStageA>
+template <typename T, int kWaves, int kS, bool kCia, bool kNonTemporal, int kMode>
 __global__ void __launch_bounds__(kWaves * kWave)
     k_forward(LaunchPlan plan, char* __restrict__ ws, const int32_t* __restrict__ active,
               double* __restrict__ depth, double* __restrict__ binned, double* __restrict__ chi2) {
+    constexpr bool kStageA = kMode != kModeStreamed;
+    constexpr bool kPipe = kMode == kModePipelined;
     extern __shared__ __align__(16) char smem[];
     // staged chord-weight fragments: a separate LDS object, so that the compiler can tell
     // phase 1's LDS traffic from the in-flight copies and does not wait for them there
-    __shared__ __align__(16) float wa_s[kStageA ? kStageMaxFloats : 1];
+    __shared__ __align__(16) float wa_s[kStageA ? StageSize<kMode>::floats : 1];
     __shared__ __align__(16) float wa_dummy[kStageA ? 4 * kWave : 1];
     static_assert(!kStageA || (kWaves == 8 && sizeof(T) == 4), "staging is laid out for 8 FP32 waves");
     const int si = plan.segment_of_wg(blockIdx.x);
@@ -120,7 +144,7 @@ __global__ void __launch_bounds__(kWaves * kWave)
     if (active && !active[b]) return;  // sample not requested in this call
     const int L = m.L, Nnu = m.Nnu;
     const RecordView<T> rec(ws + sg.ws_off + (size_t)s_in * sg.rec_bytes, kS, L);
-    const FwdLds<T> lay(L, kWaves, plan.max_ntc);
+    const FwdLds<T> lay(L, kWaves, plan.max_ntc, kPipe);
 
     const int lane = threadIdx.x & (kWave - 1);
     // the wave index is uniform across a wave; readfirstlane lets the compiler keep the
@@ -144,9 +168,9 @@ __global__ void __launch_bounds__(kWaves * kWave)
             // issues the same fixed number of copies, so the compiler's memory-counter waits
             // stay exact; copies past the sample's fragments reread chunk 0 into a dummy
             // LDS row. They overlap the prologue's loads and are complete at its barrier.
-            const int n_chunks = mfma_total_ksteps(L) * kWave / (4 * kWave);  // <= kStageChunks
+            const int n_chunks = mfma_total_ksteps(L) * kWave / (4 * kWave);  // <= StageSize::chunks
 #pragma unroll
-            for (int i = 0; i < kStageChunksPerWave; ++i) {
+            for (int i = 0; i < StageSize<kMode>::chunks_per_wave; ++i) {
                 const int q = wave + kWaves * i;
                 const bool real = q < n_chunks;
                 const float* src = rec.wb + (real ? q : 0) * 4 * kWave + 4 * lane;
@@ -176,8 +200,158 @@ __global__ void __launch_bounds__(kWaves * kWave)
                 if (i < n) cia_s[i] = cv[q];
             }
         }
+        if constexpr (kPipe) {
+            // zero rows past the last layer (read by the top stage against zero weights)
+            for (int i = threadIdx.x; i < (lay.es_rows - L) * kTileNu; i += kWaves * kWave) es[L * kTileNu + i] = T(0);
+            __builtin_amdgcn_s_waitcnt(0);  // the fragment copies: before any table load is issued
+        }
         __syncthreads();
 
+        if constexpr (kPipe) {
+            // ---- phases 1 and 2 interleaved over stages of 16 layers, from the top ----------
+            // Stage s holds layers [lo_s, lo_s + 16), lo_s = Ltop - 16 (s + 1).
+            // Every row block J with 16 J <= lo_s takes one chunk (4 k-steps, the stage's
+            // layers) from it, and is complete after the stage with lo_s = 16 J. Wave w
+            // computes the extinction of layers lo_s + 2w and lo_s + 2w + 1 while the table rows
+            // of the two following stages are in flight, then runs the matrix-core chunks of its
+            // (row block, column group) items; the stages' layers are disjoint, so one barrier
+            // per stage orders the extinction rows before their use.
+            const T* __restrict__ sig = static_cast<const T*>(m.sigma);
+            const size_t t_stride = (size_t)L * Nnu;
+            const size_t s_stride = (size_t)m.NT * t_stride;
+            // a fixed number of stages (layers up to kPipeMaxLayers), so that the stage loop
+            // unrolls into straight-line code and the memory-counter waits stay exact; stages
+            // above the model's top rows (Lk = 16 ceil(L/16)) only reissue valid table loads
+            constexpr int kStages = kPipeMaxLayers / kMfmaM;
+            constexpr int Ltop = kPipeMaxLayers;
+            const int Lk = kMfmaM * ((L + kMfmaM - 1) / kMfmaM);
+            const int nJ = mfma_row_blocks(L);
+            // record fields of this wave's layers, one per lane: lane i <-> stage i / 2,
+            // layer lo + 2 wave + i % 2 (clamped; only lanes below 2S are used)
+            const int my_l = max(0, min(Ltop - kMfmaM * (lane / 2 + 1) + 2 * wave + (lane & 1), L - 1));
+            const int r_k = rec.kidx[my_l];
+            const T r_w = rec.w[my_l];
+            T r_a[kS];
+#pragma unroll
+            for (int i = 0; i < kS; ++i) r_a[i] = rec.afac[i * L + my_l];
+            int r_kc = 0;
+            double r_wc = 0.0, r_b = 0.0;
+            if constexpr (kCia) {
+                r_kc = rec.kcidx[my_l];
+                r_wc = rec.wc[my_l];
+                r_b = rec.bfac[my_l];
+            }
+            // this wave's items: the q-th is item q * 8 + (q odd ? 7 - wave : wave) of the
+            // (J, column group) list, as in the unpipelined snake order
+            int koff[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int it = q * kWaves + ((q & 1) ? (kWaves - 1 - wave) : wave);
+                koff[q] = (it < 4 * nJ) ? mfma_kstep_offset(L, it >> 2) : 0;
+            }
+            floatx4 acc[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[q] = floatx4{0.f, 0.f, 0.f, 0.f};
+            T va0[2][kS], va1[2][kS], vb0[2][kS], vb1[2][kS];
+
+            // table rows of stage s for this wave's two layers (padding layers reread the last
+            // layer's rows, so every wave issues the same loads and the counters stay exact)
+            auto issue = [&](int st, T (&v0)[2][kS], T (&v1)[2][kS]) {
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const int l = min(Ltop - kMfmaM * (st + 1) + 2 * wave + u, L - 1);
+                    const T* p = sig + (size_t)lane_get(r_k, 2 * st + u) * t_stride + (size_t)l * Nnu + nu_c;
+#pragma unroll
+                    for (int i = 0; i < kS; ++i) {
+                        v0[u][i] = ld_table<T, kNonTemporal>(p + i * s_stride);
+                        v1[u][i] = ld_table<T, kNonTemporal>(p + i * s_stride + t_stride);
+                    }
+                }
+            };
+            auto extinction = [&](int st, const T (&v0)[2][kS], const T (&v1)[2][kS]) {
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const int l = Ltop - kMfmaM * (st + 1) + 2 * wave + u;
+                    if (l < L) {
+                        const int i = 2 * st + u;
+                        const T w = lane_get(r_w, i);
+                        T e = T(0);
+#pragma unroll
+                        for (int sp = 0; sp < kS; ++sp)
+                            e = fma(lane_get(r_a[sp], i), fma(w, v1[u][sp] - v0[u][sp], v0[u][sp]), e);
+                        if constexpr (kCia) {
+                            const double* c = cia_s + lane_get(r_kc, i) * kTileNu + lane;
+                            e += (T)(lane_get(r_b, i) * fma(lane_get(r_wc, i), c[kTileNu] - c[0], c[0]));
+                        }
+                        es[es_index<T>(l, lane)] = e;
+                    }
+                }
+            };
+            auto chunks = [&](int st) {
+                const int lo = Ltop - kMfmaM * (st + 1);
+                float a[4][kMfmaChunk], bv[4][kMfmaChunk];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int it = q * kWaves + ((q & 1) ? (kWaves - 1 - wave) : wave);
+                    const int J = it >> 2, col = it & 3;
+                    if (it < 4 * nJ && kMfmaM * J <= lo && lo < Lk) {
+                        const float* wa = wa_s + (size_t)(koff[q] + (lo - kMfmaM * J) / kMfmaK) * kWave + lane;
+#pragma unroll
+                        for (int u = 0; u < kMfmaChunk; ++u) {
+                            a[q][u] = wa[u * kWave];
+                            bv[q][u] = es[es_index<T>(lo + kMfmaK * u + (lane >> 4), col * 16 + (lane & 15))];
+                        }
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < kMfmaChunk; ++u)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int it = q * kWaves + ((q & 1) ? (kWaves - 1 - wave) : wave);
+                        if (it < 4 * nJ && kMfmaM * (it >> 2) <= lo && lo < Lk)
+                            acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[q][u], bv[q][u], acc[q], 0, 0, 0);
+                    }
+                // row blocks completed by this stage: 1 - exp(-tau), impact-parameter weights
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int it = q * kWaves + ((q & 1) ? (kWaves - 1 - wave) : wave);
+                    const int J = it >> 2, col = it & 3;
+                    if (it < 4 * nJ && kMfmaM * J == lo) {
+                        double pp = 0.0;
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const int j = kMfmaM * J + 4 * (lane >> 4) + r;
+                            if (j <= L - 2) pp += cw_s[j] * (double)(-expm1f(-acc[q][r]));
+                        }
+                        pp += __shfl_xor(pp, 16);
+                        pp += __shfl_xor(pp, 32);
+                        if (lane < 16) part[J * kTileNu + col * 16 + (lane & 15)] = pp;
+                    }
+                }
+            };
+
+            issue(0, va0, va1);
+            issue(1, vb0, vb1);
+#pragma unroll
+            for (int st = 0; st < kStages; st += 2) {
+                extinction(st, va0, va1);
+                if (st + 2 < kStages) issue(st + 2, va0, va1);
+                __syncthreads();
+                chunks(st);
+                if (st + 1 < kStages) {
+                    extinction(st + 1, vb0, vb1);
+                    if (st + 3 < kStages) issue(st + 3, vb0, vb1);
+                    __syncthreads();
+                    chunks(st + 1);
+                }
+            }
+            __syncthreads();
+            if (wave == 0) {
+                double sum = rec.hdr->base;
+                for (int J = 0; J < nJ; ++J) sum += part[J * kTileNu + lane];
+                dval = sum / rec.hdr->rs2;
+            }
+        } else {
         // ---- phase 1: extinction into LDS --------------------------------------------
         // wave w owns layers [w*per, (w+1)*per). Their record fields are loaded once, one
         // layer per lane, and broadcast with v_readlane, so the table loads of a group of
@@ -344,6 +518,7 @@ __global__ void __launch_bounds__(kWaves * kWave)
                 dval = s / rec.hdr->rs2;
             }
         }
+        }  // unpipelined
     }
     if (wave == 0) {
         if (valid) dout[nu] = dval;
@@ -379,7 +554,7 @@ __global__ void __launch_bounds__(kWaves * kWave)
     }
 }
 
-template <typename T, int kW, bool kNT, bool kSA>
+template <typename T, int kW, bool kNT, int kMode>
 int launch_k_forward(const HostPlan& hp, const LaunchPlan& lp, size_t lds, char* ws, const int32_t* act,
                             double* depth, double* binned, double* c2, hipStream_t st, hipEvent_t ev0,
                             hipEvent_t ev1) {
@@ -387,9 +562,9 @@ int launch_k_forward(const HostPlan& hp, const LaunchPlan& lp, size_t lds, char*
     int code = BM_OK;
     switch (hp.n_species) {
 #define BM_FWD_LAUNCH(NS, CIA)                                                                     \
-    code = ensure_dynamic_lds((const void*)k_forward<T, kW, NS, CIA, kNT, kSA>, lds);              \
+    code = ensure_dynamic_lds((const void*)k_forward<T, kW, NS, CIA, kNT, kMode>, lds);            \
     if (code != BM_OK) return code;                                                                \
-    hipExtLaunchKernelGGL((k_forward<T, kW, NS, CIA, kNT, kSA>), grid, block, lds, st, ev0, ev1, 0, lp, ws, act,   \
+    hipExtLaunchKernelGGL((k_forward<T, kW, NS, CIA, kNT, kMode>), grid, block, lds, st, ev0, ev1, 0, lp, ws, act, \
                           depth, binned, c2);
 #define BM_FWD_CASE(NS)              \
     case NS:                         \

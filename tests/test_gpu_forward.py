@@ -250,32 +250,64 @@ def test_fused_channel_widths(bw):
     _check_fused(s, sigma, cia, params, rtol=1e-4, data=data, err=err)
 
 
-def test_launch_configurations_are_bit_identical_and_tunable():
-    # every launch configuration computes each optical depth and partial sum in the same
-    # order, so the outputs agree bit for bit; the first matches the oracle elsewhere
+def test_launch_configurations_match_and_tune():
+    # configurations that accumulate each optical depth in the same order (all but the
+    # pipelined ones, which take the layers top-down by stage) agree bit for bit; every
+    # configuration matches the oracle
     s, sigma, cia = small_config2(n_nu=900, n_layers=70, seed=31)
     nb = s.nu.size // s.bin_width
     data, err = np.full(nb, 0.02), np.full(nb, 6e-5)
     model = gpu_model(s, sigma, cia, data=data, err=err)
     B = 6
-    params = torch.as_tensor(prior_for(s).draw(B, seed=32), device="cuda")
+    params_np = prior_for(s).draw(B, seed=32)
+    params = torch.as_tensor(params_np, device="cuda")
     f = bm.Forward(model, B, binned=True, chi2=True)
-    ref = None
-    for c in range(len(bm.forward_configs())):
+    names = bm.forward_configs()
+    outs = []
+    for c in range(len(names)):
         f.set_config(c)
         f(params)
-        out = (f.depth.clone(), f.binned.clone(), f.chi2.clone(), f.flags.clone())
-        if ref is None:
-            ref = out
-        else:
-            for a, b in zip(ref, out):
-                assert torch.equal(a, b), c
+        outs.append((f.depth.clone(), f.binned.clone(), f.chi2.clone(), f.flags.clone()))
+    groups = {}
+    for c, name in enumerate(names):
+        groups.setdefault("pipelined" in name, []).append(c)
+    for members in groups.values():
+        for c in members[1:]:
+            for a, b in zip(outs[members[0]], outs[c]):
+                assert torch.equal(a, b), (members[0], c)
+    for c in range(len(names)):
+        for b in range(B):
+            ref = ort.forward(params_np[b], s, sigma.astype(np.float64), cia, data=data, err=err)
+            sl = slice(int(f.depth_off[b]), int(f.depth_off[b + 1]))
+            np.testing.assert_allclose(_np(outs[c][0][sl]), ref["depth"], rtol=1e-4, err_msg=str(c))
     chosen, times = f.tune(params, reps=2)
     assert 0 <= chosen < len(times) and times[chosen] > 0
     assert times[chosen] == min(t for t in times if t > 0)
     f(params)
-    assert torch.equal(f.depth, ref[0]) and torch.equal(f.chi2, ref[2])
+    assert torch.equal(f.depth, outs[chosen][0]) and torch.equal(f.chi2, outs[chosen][2])
     f.set_config(-1)
+
+
+def test_pipelined_configuration_layer_counts():
+    # the pipelined mode covers up to 112 layers in fixed stages; check small, ragged and
+    # maximal layer counts against the oracle, and its fallback above 112 layers
+    names = bm.forward_configs()
+    pipe = [c for c, n in enumerate(names) if "pipelined" in n]
+    for L in (2, 17, 63, 112, 130):
+        s, sigma, cia = small_config2(n_nu=130, n_layers=L, seed=40 + L)
+        model = gpu_model(s, sigma, cia)
+        params_np = prior_for(s).draw(2, seed=41)
+        params = torch.as_tensor(params_np, device="cuda")
+        f = bm.Forward(model, 2, binned=True)
+        for c in pipe:
+            f.set_config(c)
+            f(params)
+            torch.cuda.synchronize()
+            for b in range(2):
+                ref = ort.forward(params_np[b], s, sigma.astype(np.float64), cia)
+                sl = slice(int(f.depth_off[b]), int(f.depth_off[b + 1]))
+                np.testing.assert_allclose(_np(f.depth[sl]), ref["depth"], rtol=1e-4, err_msg=f"L={L} c={c}")
+        f.set_config(-1)
 
 
 def test_kernel_timing_counts_launches():
