@@ -47,9 +47,11 @@ __device__ void atm_compute(const ModelDev& m, const double* __restrict__ theta_
     const double* theta = sh.theta;
     // per-sample constants, each on its own thread
     if (tid < m.S) sh.x[tid] = pow10_(theta[ntp + tid]);
-    if (tid == 32 && m.tp_mode == BM_TP_LINE2013) sh.tp = line2013_consts(theta, m.pl);
+    if (m.tp_mode == BM_TP_LINE2013 && tid >= 32 && tid < 36) line2013_consts_part(theta, m.pl, tid - 32, &sh.tp);
     __syncthreads();
-    if (tid == 0) {
+    // totals, mean molecular mass and flags on the last thread, which has no layer of its
+    // own in the split profile evaluation below
+    if (tid == kAtmThreads - 1) {
         int flags = 0;
         for (int i = 0; i < np; ++i)
             if (!isfinite(theta[i])) flags |= BM_FLAG_NONFINITE;
@@ -228,8 +230,9 @@ __global__ void __launch_bounds__(kAtmThreads)
             // A fragments of v_mfma_f32_16x16x4f32: entry (kstep, lane) of row block J
             // holds W[16J + lane % 16][16J + 4 kstep + lane / 16]
             const int kg = idx / kWave, lane = idx % kWave;
-            int J = 0, off = 0;
-            while (off + mfma_ksteps(L, J) <= kg) off += mfma_ksteps(L, J++);
+            int J = 0;
+            while (mfma_kstep_offset(L, J + 1) <= kg) ++J;
+            const int off = mfma_kstep_offset(L, J);
             j = kMfmaM * J + (lane % kMfmaM);
             l = kMfmaM * J + kMfmaK * (kg - off) + lane / kMfmaM;
         } else {

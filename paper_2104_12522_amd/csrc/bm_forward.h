@@ -27,10 +27,10 @@ __host__ __device__ inline int mfma_ksteps(int L, int J) {
     const int raw = (L - kMfmaM * J + kMfmaK - 1) / kMfmaK;
     return (raw + kMfmaChunk - 1) / kMfmaChunk * kMfmaChunk;
 }
+// sum of the k-steps of row blocks 0..J-1: mfma_ksteps(L, i) = 4 (ceil(L/16) - i)
 __host__ __device__ inline int mfma_kstep_offset(int L, int J) {
-    int o = 0;
-    for (int i = 0; i < J; ++i) o += mfma_ksteps(L, i);
-    return o;
+    const int c = (L + kMfmaM - 1) / kMfmaM;
+    return kMfmaChunk * (J * c - J * (J - 1) / 2);
 }
 __host__ __device__ inline int mfma_total_ksteps(int L) { return mfma_kstep_offset(L, mfma_row_blocks(L)); }
 
