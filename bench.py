@@ -434,6 +434,42 @@ def section_mcmc(args, setup, prior):
         f"{rms_prior_post:.2f} ppm, local {rms_local:.2f} ppm")
     del Xl, Yl
 
+    # 3b. longer burn-in with delayed acceptance (exact, and cheap), then the local
+    #     surrogate is refit to the wider set of states
+    if args.da_burn > 0:
+        rd = Retrieval(model, C, prior.lo, prior.hi, seed=args.seed + 67, thin=10, hist_cap=args.da_burn,
+                       surrogate=sur, z_cap=z0.shape[0] + C * (args.da_burn // 10 + 2))
+        rd.resume(x0, z0)
+        t_db = run_graph(rd, args.da_burn)
+        hb = rd.s.history[args.da_burn // 2:args.da_burn].cpu().numpy().reshape(-1, d)
+        mu_b, cov_b = hb.mean(0), np.cov(hb.T)
+        sd_b = np.sqrt(np.diag(cov_b))
+        x0 = rd.s.x.clone()
+        m = rd.s.archive_size
+        z0 = rd.s.z[max(0, m - 10 * C):m].clone()
+        t0 = time.perf_counter()
+        lo_l = np.maximum(mu_b - 5 * sd_b, prior.lo)
+        hi_l = np.minimum(mu_b + 5 * sd_b, prior.hi)
+        Xl = dev(gaussian_states(mu_b, cov_b, args.local_spectra, lo_l, hi_l, seed=args.seed + 68,
+                                 inflate=2.0))
+        Yl = spectra(Xl)
+        mean_l, scale_l = standardisation(Yl)
+        net_l = MLP(dims, max_batch=5000, seed=7)
+        train(net_l, dev(lo_l), dev(hi_l), Xl, Yl, mean_l, scale_l, args.epochs, 1e-3, 8)
+        torch.cuda.synchronize()
+        t_local += time.perf_counter() - t0
+        sur = Surrogate(net_l, dev(lo_l), dev(hi_l), mean_l, scale_l, model.data, model.err,
+                        n_chains=5000)
+        post_np = hb[np.random.default_rng(args.seed + 69).choice(hb.shape[0], 2048, replace=False)]
+        post_x = dev(post_np)
+        post_y = spectra(post_x)
+        rms_local = rms_ppm(sur, post_x, post_y)
+        fw(post_x[:C].contiguous())
+        dchi2 = (sur(post_x[:C].contiguous()) - fw.chi2).cpu().numpy()
+        log(f"mcmc: delayed-acceptance burn-in {args.da_burn} generations in {t_db:.1f} s; local "
+            f"surrogate refit, rms {rms_local:.2f} ppm")
+        del Xl, Yl
+
     # 4. production runs from the same burned-in state and random stream
     def production(surrogate=None, per_sample=0, n_gen=G):
         r = Retrieval(model, C, prior.lo, prior.hi, seed=args.seed + 70, thin=10, hist_cap=n_gen,
@@ -489,7 +525,7 @@ def section_mcmc(args, setup, prior):
         f"delayed acceptance {da['ess_per_s']:.2f} -> {ratio:.1f}x; max |mean diff| "
         f"{np.abs(diff).max():.3f} sd")
     return {
-        "chains": C, "burn_in": BURN, "truth": truth.tolist(),
+        "chains": C, "burn_in": BURN, "da_burn_in": args.da_burn, "truth": truth.tolist(),
         "surrogate": {"dims": dims, "dtype": "bf16 weights/activations, fp32 accumulate",
                       "train_spectra": args.train_spectra, "epochs": args.epochs,
                       "data_s": t_data, "train_s": t_train, "adam_steps": net.step,
@@ -620,6 +656,8 @@ def main():
     ap.add_argument("--no-mixed", dest="mixed", action="store_false")
     ap.add_argument("--mcmc-gens", type=int, default=12000)
     ap.add_argument("--mcmc-burn", type=int, default=1000)
+    ap.add_argument("--da-burn", type=int, default=0,
+                    help="further burn-in generations with delayed acceptance before production")
     ap.add_argument("--per-sample-gens", type=int, default=200)
     ap.add_argument("--train-spectra", type=int, default=200000)
     ap.add_argument("--local-spectra", type=int, default=100000)

@@ -178,34 +178,38 @@ __global__ void __launch_bounds__(kWaves * kWave)
                 __builtin_amdgcn_global_load_lds((const void*)src, (lds_void_ptr)dst, 16, 0, 0);
             }
         }
-        // impact-parameter weights to LDS (read per optical depth in phase 2)
+        // impact-parameter weights (read per optical depth in phase 2) and this tile's
+        // columns of every CIA temperature row (read by many layers) go to LDS; all their
+        // loads are issued before the first store
         double* cw_s = reinterpret_cast<double*>(smem + lay.cw);
-        for (int i = threadIdx.x; i < L; i += kWaves * kWave) cw_s[i] = rec.cw[i];
-        // this tile's columns of every CIA temperature row (read by many layers); the
-        // loads are all issued before the first store
         double* cia_s = reinterpret_cast<double*>(smem + lay.ciat);
-        if constexpr (kCia) {
-            constexpr int kMaxPer = BM_MAX_TEMPS * kTileNu / (kWaves * kWave);
+        constexpr int kMaxPer = BM_MAX_TEMPS * kTileNu / (kWaves * kWave);
+        double cv[kMaxPer];
+        auto cia_load = [&]() {
             const int n = m.NTc * kTileNu;
-            double cv[kMaxPer];
 #pragma unroll
             for (int q = 0; q < kMaxPer; ++q) {
                 const int i = min((int)threadIdx.x + q * kWaves * kWave, n - 1);
                 const int col = min(tile * sg.tile_w + (i % kTileNu), Nnu - 1);
                 cv[q] = m.cia[(size_t)(i / kTileNu) * Nnu + col];
             }
+        };
+        auto cia_store = [&]() {
+            const int n = m.NTc * kTileNu;
 #pragma unroll
             for (int q = 0; q < kMaxPer; ++q) {
                 const int i = threadIdx.x + q * kWaves * kWave;
                 if (i < n) cia_s[i] = cv[q];
             }
+        };
+        if constexpr (!kPipe) {
+            for (int i = threadIdx.x; i < L; i += kWaves * kWave) cw_s[i] = rec.cw[i];
+            if constexpr (kCia) {
+                cia_load();
+                cia_store();
+            }
+            __syncthreads();
         }
-        if constexpr (kPipe) {
-            // zero rows past the last layer (read by the top stage against zero weights)
-            for (int i = threadIdx.x; i < (lay.es_rows - L) * kTileNu; i += kWaves * kWave) es[L * kTileNu + i] = T(0);
-            __builtin_amdgcn_s_waitcnt(0);  // the fragment copies: before any table load is issued
-        }
-        __syncthreads();
 
         if constexpr (kPipe) {
             // ---- phases 1 and 2 interleaved over stages of 16 layers, from the top ----------
@@ -226,6 +230,11 @@ __global__ void __launch_bounds__(kWaves * kWave)
             constexpr int Ltop = kPipeMaxLayers;
             const int Lk = kMfmaM * ((L + kMfmaM - 1) / kMfmaM);
             const int nJ = mfma_row_blocks(L);
+            // the prologue's own loads first (see below)
+            static_assert(kPipeMaxLayers <= kWaves * kWave, "one impact-parameter weight per thread");
+            const double cwv = rec.cw[min((int)threadIdx.x, L - 1)];
+            if constexpr (kCia) cia_load();
+            __builtin_amdgcn_sched_barrier(0);
             // record fields of this wave's layers, one per lane: lane i <-> stage i / 2,
             // layer lo + 2 wave + i % 2 (clamped; only lanes below 2S are used)
             const int my_l = max(0, min(Ltop - kMfmaM * (lane / 2 + 1) + 2 * wave + (lane & 1), L - 1));
@@ -330,8 +339,19 @@ __global__ void __launch_bounds__(kWaves * kWave)
                 }
             };
 
+            // prologue: the fragment copies (issued first), the impact-parameter weights, the
+            // CIA columns, the record fields and the first two stages' table rows are all in
+            // flight before the first wait. Vector-memory loads return in issue order, so once
+            // a wave has waited for its stage-0 rows its fragment copies have landed too.
             issue(0, va0, va1);
             issue(1, vb0, vb1);
+            // keep the stage loads ahead of the waits that the LDS stores below need
+            __builtin_amdgcn_sched_barrier(0);
+            if ((int)threadIdx.x < L) cw_s[threadIdx.x] = cwv;
+            if constexpr (kCia) cia_store();
+            // zero rows past the last layer (read by the top stages against zero weights)
+            for (int i = threadIdx.x; i < (lay.es_rows - L) * kTileNu; i += kWaves * kWave) es[L * kTileNu + i] = T(0);
+            __syncthreads();
 #pragma unroll
             for (int st = 0; st < kStages; st += 2) {
                 extinction(st, va0, va1);
