@@ -113,6 +113,11 @@ typedef struct bm_model {
     const double* err;    /* device [Nnu/bin_width] their 1-sigma errors, or NULL           */
     double mass_amu[BM_MAX_SPECIES]; /* host values: absorber masses                        */
     bm_planet planet;
+    double tau_max;       /* Sec. 4 item 7, the optical-depth limit: in bm_forward_batch every
+                             chord at or below (deeper than) one whose optical depth reaches
+                             tau_max counts as opaque, f = 1; <= 0 or infinite = no limit
+                             (the optical depth grows monotonically with depth, so this is
+                             f = 1 wherever tau >= tau_max)                                    */
 } bm_model;
 
 /* Number of parameters of a sample: (1 or 5) + S + 1. */

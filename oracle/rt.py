@@ -75,14 +75,24 @@ def optical_depth(radius: np.ndarray, ext: np.ndarray) -> np.ndarray:
     return tau
 
 
-def transit_depth(radius: np.ndarray, tau: np.ndarray, rs_cm: float) -> np.ndarray:
+def transit_depth(radius: np.ndarray, tau: np.ndarray, rs_cm: float,
+                  tau_max: float | None = None) -> np.ndarray:
     """Step a5. Transit depth: an opaque disk inside the deepest layer plus the
     absorbed fraction of each annulus, trapezoid in impact parameter,
     depth = [r_0^2 + 2 int_{r_0}^{r_top} (1 - exp(-tau(b))) b db] / Rs^2
           = [r_0^2 + sum_j (r_{j+1} - r_j)(f_j r_j + f_{j+1} r_{j+1})] / Rs^2,
-    f = 1 - exp(-tau)."""
+    f = 1 - exp(-tau).
+    With an optical-depth limit (Sec. 4 item 7: calculate only down to a user-set optical
+    depth at each wavenumber), the rays are followed from the top impact parameter down;
+    at the first one whose optical depth reaches tau_max, it and every deeper one count as
+    opaque, f = 1."""
     L, NNU = tau.shape
     f = -np.expm1(-tau)
+    if tau_max is not None and tau_max > 0:
+        reached = np.zeros(NNU, dtype=bool)
+        for j in range(L - 1, -1, -1):
+            reached |= tau[j] >= tau_max
+            f[j] = np.where(reached, 1.0, f[j])
     acc = np.full(NNU, radius[0] ** 2, dtype=np.float64)
     for j in range(L - 1):
         acc += (radius[j + 1] - radius[j]) * (f[j] * radius[j] + f[j + 1] * radius[j + 1])
@@ -117,7 +127,8 @@ def forward(params: np.ndarray, setup, sigma: np.ndarray, cia: np.ndarray | None
         out = dict(atm=atm, ext=ext, tau=None, depth=nan, flags=flags)
     else:
         tau = optical_depth(atm["radius"], ext)
-        depth = transit_depth(atm["radius"], tau, setup.planet.rs_cm)
+        depth = transit_depth(atm["radius"], tau, setup.planet.rs_cm,
+                              getattr(setup, "tau_max", None))
         out = dict(atm=atm, ext=ext, tau=tau, depth=depth, flags=flags)
     if setup.bin_width:
         out["binned"] = bin_spectrum(out["depth"], setup.bin_width)

@@ -84,7 +84,7 @@ class Model:
 
     def __init__(self, sigma: torch.Tensor, temps, p_bar, mass_amu, tp_mode: int, planet,
                  cia: torch.Tensor | None = None, cia_temps=None, bin_width: int = 0,
-                 data=None, err=None, device="cuda"):
+                 data=None, err=None, device="cuda", tau_max: float = 0.0):
         if sigma.dim() != 4:
             raise BartmiError("sigma must be [S][NT][L][Nnu]")
         self.sigma = sigma.to(device).contiguous()
@@ -116,6 +116,7 @@ class Model:
         for i in range(BM_MAX_SPECIES):
             st.mass_amu[i] = float(m[i])
         st.planet = planet_struct(planet)
+        st.tau_max = float(tau_max)
         self.struct = st
 
     @property

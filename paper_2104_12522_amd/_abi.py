@@ -29,6 +29,7 @@ class BmModel(C.Structure):
         ("err", C.c_void_p),
         ("mass_amu", C.c_double * BM_MAX_SPECIES),
         ("planet", BmPlanet),
+        ("tau_max", C.c_double),
     ]
 
 

@@ -46,6 +46,7 @@ struct ModelDev {
     int S, NT, L, Nnu, NTc, tp_mode, bin_width, nb;
     double mass[BM_MAX_SPECIES];
     bm_planet pl;
+    double tau_max;  // optical-depth limit (+infinity: none)
 };
 
 // A run of consecutive samples that use the same model.

@@ -178,6 +178,7 @@ ModelDev to_device_view(const bm_model& m) {
     d.nb = row_blocks(m.n_layers);
     for (int i = 0; i < BM_MAX_SPECIES; ++i) d.mass[i] = m.mass_amu[i];
     d.pl = m.planet;
+    d.tau_max = (m.tau_max > 0.0) ? m.tau_max : __builtin_huge_val();
     return d;
 }
 
@@ -506,7 +507,7 @@ extern "C" const char* bm_status_string(int status) {
     }
 }
 
-extern "C" int bm_version(void) { return 100; }
+extern "C" int bm_version(void) { return 101; }
 
 extern "C" int bm_n_params(const bm_model* model) {
     if (!model) return BM_EINVAL;

@@ -118,6 +118,14 @@ __device__ __forceinline__ double lane_get(double v, int i) {
 
 typedef __attribute__((address_space(3))) void* lds_void_ptr;
 
+// absorbed fraction of a chord, 1 - exp(-tau), or 1 at and beyond the optical-depth limit
+__device__ __forceinline__ double opaque_fraction(float tau, double tau_max) {
+    return (double)tau >= tau_max ? 1.0 : (double)(-expm1f(-tau));
+}
+__device__ __forceinline__ double opaque_fraction(double tau, double tau_max) {
+    return tau >= tau_max ? 1.0 : -dev_expm1(-tau);
+}
+
 template <typename T, int kWaves, int kS, bool kCia, bool kNonTemporal, int kMode>
 __global__ void __launch_bounds__(kWaves * kWave)
     k_forward(LaunchPlan plan, char* __restrict__ ws, const int32_t* __restrict__ active,
@@ -330,7 +338,7 @@ __global__ void __launch_bounds__(kWaves * kWave)
 #pragma unroll
                         for (int r = 0; r < 4; ++r) {
                             const int j = kMfmaM * J + 4 * (lane >> 4) + r;
-                            if (j <= L - 2) pp += cw_s[j] * (double)(-expm1f(-acc[q][r]));
+                            if (j <= L - 2) pp += cw_s[j] * opaque_fraction(acc[q][r], m.tau_max);
                         }
                         pp += __shfl_xor(pp, 16);
                         pp += __shfl_xor(pp, 32);
@@ -494,7 +502,7 @@ __global__ void __launch_bounds__(kWaves * kWave)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int j = kMfmaM * J + 4 * (lane >> 4) + r;
-                    if (j <= L - 2) pp += cw_s[j] * (double)(-expm1f(-acc[r]));
+                    if (j <= L - 2) pp += cw_s[j] * opaque_fraction(acc[r], m.tau_max);
                 }
                 pp += __shfl_xor(pp, 16);
                 pp += __shfl_xor(pp, 32);
@@ -527,7 +535,7 @@ __global__ void __launch_bounds__(kWaves * kWave)
 #pragma unroll
                 for (int r = 0; r < kRows; ++r) {
                     const int j = j0 + r;
-                    if (j <= L - 2) acc += cw_s[j] * (double)(-dev_expm1(-t[r]));
+                    if (j <= L - 2) acc += cw_s[j] * opaque_fraction(t[r], m.tau_max);
                 }
             }
             part[wave * kTileNu + lane] = acc;

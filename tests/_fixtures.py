@@ -31,7 +31,8 @@ def gpu_model(setup, sigma, cia=None, data=None, err=None, device="cuda"):
                     setup.tp_mode, setup.planet,
                     cia=None if cia is None else torch.as_tensor(cia),
                     cia_temps=setup.cia_temps if cia is not None else None,
-                    bin_width=setup.bin_width, data=data, err=err, device=device)
+                    bin_width=setup.bin_width, data=data, err=err, device=device,
+                    tau_max=setup.tau_max)
 
 
 def prior_for(setup):

@@ -4,6 +4,8 @@ Tolerances: FP64 mode 1e-10 relative on transit depth (1e-12 on the FP64 atmosph
 FP32 mode 1e-4 relative on depth, and the error on the atmospheric part of the depth
 (depth - r_0^2/Rs^2) is reported in ppm and held below 1e-3 of that part.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -322,3 +324,26 @@ def test_kernel_timing_counts_launches():
     with bm.KernelTiming(10) as t2:
         f(params)
     assert t2.launches == 1
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_fused_optical_depth_limit(dtype):
+    # Sec. 4 item 7: chords at and below the first one reaching tau_max are opaque
+    if dtype == "f64":
+        s, sigma = config1_table(n_nu=300)
+        cia = None
+        params = np.array([wl.config1_params(), [1500.0, -3.0, 1.2]])
+        s.tau_max, rtol = 3.0, 1e-10
+    else:
+        s, sigma, cia = small_config2(n_nu=700, n_layers=80, seed=61)
+        params = prior_for(s).draw(4, seed=62)
+        s.tau_max, rtol = 2.0, 1e-4
+    ppm = _check_fused(s, sigma, cia, params, rtol=rtol)
+    # and the limit does change the spectrum
+    s0 = dataclasses.replace(s, tau_max=0.0)
+    model0 = gpu_model(s0, sigma, cia)
+    model1 = gpu_model(s, sigma, cia)
+    p = torch.as_tensor(params, device="cuda")
+    d0 = bm.forward_batch(model0, p).depth.clone()
+    d1 = bm.forward_batch(model1, p).depth.clone()
+    assert torch.all(d1 >= d0 - 1e-15) and float((d1 - d0).max()) > 0

@@ -248,3 +248,52 @@ def test_forward_isothermal_monotone_and_bounded():
     assert np.all(np.diff(out["tau"], axis=0) <= 0)
     assert np.all(out["depth"] >= (r[0] / s.planet.rs_cm) ** 2)
     assert np.all(out["depth"] <= (r[-1] / s.planet.rs_cm) ** 2)
+
+
+def test_optical_depth_limit_saturates_the_chords_below():
+    # a limit below every nonzero optical depth makes every chord but the top one opaque:
+    # the same closed form as an infinitely opaque atmosphere
+    L = 25
+    r = _radii_geometric(L)
+    g = np.random.default_rng(7)
+    tau = np.sort(g.uniform(1e-3, 3.0, (L, 3)), axis=0)[::-1].copy()
+    tau[-1] = 0.0
+    d = rt.transit_depth(r, tau, PL.rs_cm, tau_max=1e-6)
+    np.testing.assert_allclose(d, r[-2] * r[-1] / PL.rs_cm ** 2, rtol=1e-14)
+
+
+def test_optical_depth_limit_effect_and_limits():
+    L = 30
+    r = _radii_geometric(L)
+    e = np.full((L, 4), 2e-10)
+    tau = rt.optical_depth(r, e)
+    base = rt.transit_depth(r, tau, PL.rs_cm)
+    # an unreachable limit changes nothing
+    np.testing.assert_array_equal(rt.transit_depth(r, tau, PL.rs_cm, tau_max=1e30), base)
+    # the limit only makes chords more opaque; its effect on a chord is at most exp(-tau_max)
+    for tm in (0.5, 2.0, 5.0):
+        d = rt.transit_depth(r, tau, PL.rs_cm, tau_max=tm)
+        assert np.all(d >= base)
+        area = (r[-1] ** 2 - r[0] ** 2) / PL.rs_cm ** 2
+        assert np.all(d - base <= np.exp(-tm) * area + 1e-18)
+    # with the optical depth monotone in impact parameter, the top-down rule equals the
+    # per-chord threshold f = 1 where tau >= tau_max
+    tm = 1.0
+    f = np.where(tau >= tm, 1.0, -np.expm1(-tau))
+    acc = np.full(4, r[0] ** 2)
+    for j in range(L - 1):
+        acc += (r[j + 1] - r[j]) * (f[j] * r[j] + f[j + 1] * r[j + 1])
+    np.testing.assert_allclose(rt.transit_depth(r, tau, PL.rs_cm, tau_max=tm), acc / PL.rs_cm ** 2,
+                               rtol=1e-15)
+
+
+def test_optical_depth_limit_scans_from_the_top():
+    # a non-monotone optical depth (not produced by the model, built by hand): a chord
+    # above the first one to reach the limit keeps its own absorption; every chord below
+    # it is opaque even where its own tau is small
+    r = _radii_geometric(5)
+    tau = np.array([[0.1], [0.2], [5.0], [0.3], [0.0]])
+    d = rt.transit_depth(r, tau, PL.rs_cm, tau_max=1.0)
+    f = np.array([1.0, 1.0, 1.0, -np.expm1(-0.3), 0.0])
+    acc = r[0] ** 2 + sum((r[j + 1] - r[j]) * (f[j] * r[j] + f[j + 1] * r[j + 1]) for j in range(4))
+    assert d[0] == pytest.approx(acc / PL.rs_cm ** 2, rel=1e-15)

@@ -182,6 +182,7 @@ class ForwardSetup:
     cia_temps: np.ndarray | None = None
     bin_width: int = 0
     lines_per_species: tuple = ()
+    tau_max: float = 0.0         # optical-depth limit (0: none)
 
 
 def config1() -> ForwardSetup:
