@@ -55,6 +55,25 @@ def extinction(sigma: np.ndarray, t_grid: np.ndarray, temp: np.ndarray, n_specie
     return e, flags
 
 
+def rayleigh_h2(nu: np.ndarray) -> np.ndarray:
+    """H2 Rayleigh-scattering cross section (cm^2 molecule^-1) at wavenumbers nu (cm^-1),
+    the Dalgarno & Williams (1962) expansion in the wavelength in Angstrom:
+    sigma = 8.14e-13 lam^-4 + 1.28e-6 lam^-6 + 1.61 lam^-8 (Sec. 3: transit's Rayleigh
+    scattering; the paper gives no formula, this is the standard one for H2)."""
+    lam = 1.0e8 / np.asarray(nu, dtype=np.float64)
+    return 8.14e-13 / lam ** 4 + 1.28e-6 / lam ** 6 + 1.61 / lam ** 8
+
+
+def cloud_layer(p_bar: np.ndarray, log_p_cloud: float) -> int:
+    """Gray cloud deck (Sec. 3; the cloud-top pressure of the Sec. 7 retrievals): the
+    deepest-first index of the last layer at or below the cloud top, i.e. the largest l with
+    p_l >= p_cloud (-1 when the deck lies below every layer). Chords whose impact parameter
+    lies at or below that layer are opaque."""
+    p_cloud = 10.0 ** log_p_cloud
+    below = np.nonzero(np.asarray(p_bar) >= p_cloud)[0]
+    return int(below.max()) if below.size else -1
+
+
 def chord_path(radius: np.ndarray, j: int, l: int) -> float:
     """Half-chord length from the tangent point of impact parameter b_j = r_j to the
     sphere of radius r_l (l >= j): s = sqrt(r_l^2 - r_j^2), written as a product of a
@@ -76,7 +95,7 @@ def optical_depth(radius: np.ndarray, ext: np.ndarray) -> np.ndarray:
 
 
 def transit_depth(radius: np.ndarray, tau: np.ndarray, rs_cm: float,
-                  tau_max: float | None = None) -> np.ndarray:
+                  tau_max: float | None = None, cloud_index: int = -1) -> np.ndarray:
     """Step a5. Transit depth: an opaque disk inside the deepest layer plus the
     absorbed fraction of each annulus, trapezoid in impact parameter,
     depth = [r_0^2 + 2 int_{r_0}^{r_top} (1 - exp(-tau(b))) b db] / Rs^2
@@ -85,9 +104,11 @@ def transit_depth(radius: np.ndarray, tau: np.ndarray, rs_cm: float,
     With an optical-depth limit (Sec. 4 item 7: calculate only down to a user-set optical
     depth at each wavenumber), the rays are followed from the top impact parameter down;
     at the first one whose optical depth reaches tau_max, it and every deeper one count as
-    opaque, f = 1."""
+    opaque, f = 1. A gray cloud deck makes the chords j <= cloud_index opaque too."""
     L, NNU = tau.shape
     f = -np.expm1(-tau)
+    if cloud_index >= 0:
+        f[: cloud_index + 1] = 1.0
     if tau_max is not None and tau_max > 0:
         reached = np.zeros(NNU, dtype=bool)
         for j in range(L - 1, -1, -1):
@@ -122,13 +143,18 @@ def forward(params: np.ndarray, setup, sigma: np.ndarray, cia: np.ndarray | None
     ext, f = extinction(sigma, setup.temps, atm["temp"], atm["n_species"],
                         cia, setup.cia_temps, atm["n_h2"])
     flags |= f
+    if getattr(setup, "rayleigh", False):
+        ext = ext + atm["n_h2"][:, None] * rayleigh_h2(setup.nu)[None, :]
+    jc = -1
+    if getattr(setup, "cloud", False):
+        jc = cloud_layer(setup.p_bar, float(params[-1]))
     if flags & FLAG_RADIUS:
         nan = np.full(setup.nu.size, np.nan)
         out = dict(atm=atm, ext=ext, tau=None, depth=nan, flags=flags)
     else:
         tau = optical_depth(atm["radius"], ext)
         depth = transit_depth(atm["radius"], tau, setup.planet.rs_cm,
-                              getattr(setup, "tau_max", None))
+                              getattr(setup, "tau_max", None), jc)
         out = dict(atm=atm, ext=ext, tau=tau, depth=depth, flags=flags)
     if setup.bin_width:
         out["binned"] = bin_spectrum(out["depth"], setup.bin_width)

@@ -297,3 +297,45 @@ def test_optical_depth_limit_scans_from_the_top():
     f = np.array([1.0, 1.0, 1.0, -np.expm1(-0.3), 0.0])
     acc = r[0] ** 2 + sum((r[j + 1] - r[j]) * (f[j] * r[j] + f[j + 1] * r[j + 1]) for j in range(4))
     assert d[0] == pytest.approx(acc / PL.rs_cm ** 2, rel=1e-15)
+
+
+def test_rayleigh_h2_cross_section():
+    # the inverse-fourth-power law at long wavelengths, positive and falling with
+    # wavelength, and the wavelength corrections small in the visible
+    nu = np.array([10.0, 20.0])          # 1e7 and 5e6 Angstrom
+    s = rt.rayleigh_h2(nu)
+    assert s[1] / s[0] == pytest.approx(16.0, rel=1e-6)
+    nus = np.linspace(1000.0, 25000.0, 50)
+    sr = rt.rayleigh_h2(nus)
+    assert np.all(sr > 0) and np.all(np.diff(sr) > 0)
+    lam = 1e8 / 20000.0                  # 5000 Angstrom
+    leading = 8.14e-13 / lam ** 4
+    assert 1.0 < rt.rayleigh_h2(np.array([20000.0]))[0] / leading < 1.1
+
+
+def test_cloud_layer_index():
+    p = np.logspace(2, -8, 11)            # 100 ... 1e-8 bar, deepest first
+    assert rt.cloud_layer(p, 3.0) == -1   # below every layer
+    assert rt.cloud_layer(p, 2.0) == 0
+    assert rt.cloud_layer(p, -2.0) == 4   # p_4 = 1e-2 bar
+    assert rt.cloud_layer(p, -2.5) == 4
+    assert rt.cloud_layer(p, -9.0) == 10
+
+
+def test_cloud_deck_limits_and_monotonicity():
+    L = 20
+    r = _radii_geometric(L)
+    g = np.random.default_rng(11)
+    tau = np.sort(g.uniform(0.0, 2.0, (L, 3)), axis=0)[::-1].copy()
+    tau[-1] = 0.0
+    clear = rt.transit_depth(r, tau, PL.rs_cm)
+    # a deck below the deepest layer changes nothing; a deck at the top is a saturated disk
+    np.testing.assert_array_equal(rt.transit_depth(r, tau, PL.rs_cm, cloud_index=-1), clear)
+    np.testing.assert_allclose(rt.transit_depth(r, tau, PL.rs_cm, cloud_index=L - 1),
+                               r[-1] ** 2 / PL.rs_cm ** 2, rtol=1e-14)
+    # a higher cloud top only adds absorption
+    prev = clear
+    for jc in range(L):
+        d = rt.transit_depth(r, tau, PL.rs_cm, cloud_index=jc)
+        assert np.all(d >= prev - 1e-18)
+        prev = d

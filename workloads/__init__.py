@@ -159,6 +159,11 @@ def line2013_prior(n_species: int) -> Prior:
     return Prior(lo, hi)
 
 
+def with_cloud(prior: Prior, log_p_lo: float = -6.0, log_p_hi: float = 2.0) -> Prior:
+    """The prior extended by the cloud-top pressure, log10 p_cloud (bar), last."""
+    return Prior(np.append(prior.lo, log_p_lo), np.append(prior.hi, log_p_hi))
+
+
 def isothermal_prior(n_species: int) -> Prior:
     """Parameters: T (K), log10 x_i (n_species), R_ref / R_J."""
     lo = np.array([800.0] + [-8.0] * n_species + [1.0])
@@ -183,6 +188,8 @@ class ForwardSetup:
     bin_width: int = 0
     lines_per_species: tuple = ()
     tau_max: float = 0.0         # optical-depth limit (0: none)
+    rayleigh: bool = False       # H2 Rayleigh scattering in the extinction
+    cloud: bool = False          # gray cloud deck: one more parameter, log10 p_cloud (bar)
 
 
 def config1() -> ForwardSetup:
