@@ -75,6 +75,10 @@ const char* bm_status_string(int status);
 /* Library ABI version (major * 100 + minor). */
 int bm_version(void);
 
+/* sizeof of a structure of this header, for bindings to check their own layouts:
+ * which = 0 bm_planet, 1 bm_model, 2 bm_demcz, 3 bm_mlp; 0 for any other value. */
+size_t bm_struct_size(int which);
+
 /* Fixed constants of a transmission model (host values, copied by every call).
  * Sec. 6.2 and Sec. 7: a hot Jupiter resembling HD 189733 b; the radius parameter
  * applies at p_ref; filler gas H2:He in the ratio h2_frac : 1 - h2_frac. */
@@ -118,9 +122,17 @@ typedef struct bm_model {
                              tau_max counts as opaque, f = 1; <= 0 or infinite = no limit
                              (the optical depth grows monotonically with depth, so this is
                              f = 1 wherever tau >= tau_max)                                    */
+    double nu_start;      /* wavenumber of table column 0 (cm^-1); used by Rayleigh scattering */
+    double dnu;           /* wavenumber step of the tables (cm^-1)                           */
+    int32_t rayleigh;     /* 1: add H2 Rayleigh scattering n_H2 sigma_R(nu) to the extinction
+                             (Sec. 3; sigma_R of Dalgarno & Williams 1962)                     */
+    int32_t cloud;        /* 1: gray cloud deck (Sec. 3; cloud-top pressure of Sec. 7): one more
+                             parameter, log10(p_cloud / bar), after the radius; in
+                             bm_forward_batch every chord whose impact-parameter layer has
+                             p >= p_cloud is opaque                                            */
 } bm_model;
 
-/* Number of parameters of a sample: (1 or 5) + S + 1. */
+/* Number of parameters of a sample: (1 or 5) + S + 1 (+ 1 with a cloud deck). */
 int bm_n_params(const bm_model* model);
 
 /* ---- a1-a2: atmosphere -------------------------------------------------------------
@@ -136,9 +148,10 @@ int bm_atmosphere(const bm_model* model, const double* params, int param_stride,
 /* ---- a3: extinction ------------------------------------------------------------------
  * Sec. 3 and Sec. 6.1.1 (the RT interpolates the opacity table to each layer's
  * temperature; the table lives on the layer pressures):
- *   ext[l][k] = sum_i n_species[i][l] sigma_i(T_l)[l][k] + n_h2[l]^2 cia(T_l)[k],
+ *   ext[l][k] = sum_i n_species[i][l] sigma_i(T_l)[l][k] + n_h2[l]^2 cia(T_l)[k]
+ *             (+ n_h2[l] sigma_R(nu_k) with model->rayleigh),
  * linear interpolation in T, clamped (BM_FLAG_T_CLAMP ORed into *flags).
- * temp [L], n_species [S][L], n_h2 [L] (ignored without CIA) are device doubles;
+ * temp [L], n_species [S][L], n_h2 [L] (ignored without CIA and Rayleigh) are device doubles;
  * ext is device [L][Nnu] of model->dtype; flags is a device int32 (ORed, not cleared). */
 int bm_extinction(const bm_model* model, const double* temp, const double* n_species,
                   const double* n_h2, void* ext, int32_t* flags, void* stream);

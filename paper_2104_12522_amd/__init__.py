@@ -84,7 +84,9 @@ class Model:
 
     def __init__(self, sigma: torch.Tensor, temps, p_bar, mass_amu, tp_mode: int, planet,
                  cia: torch.Tensor | None = None, cia_temps=None, bin_width: int = 0,
-                 data=None, err=None, device="cuda", tau_max: float = 0.0):
+                 data=None, err=None, device="cuda", tau_max: float = 0.0,
+                 nu_start: float = 0.0, dnu: float = 0.0, rayleigh: bool = False,
+                 cloud: bool = False):
         if sigma.dim() != 4:
             raise BartmiError("sigma must be [S][NT][L][Nnu]")
         self.sigma = sigma.to(device).contiguous()
@@ -117,6 +119,10 @@ class Model:
             st.mass_amu[i] = float(m[i])
         st.planet = planet_struct(planet)
         st.tau_max = float(tau_max)
+        if rayleigh and not dnu > 0:
+            raise BartmiError("Rayleigh scattering needs the wavenumber grid (nu_start, dnu)")
+        st.nu_start, st.dnu = float(nu_start), float(dnu)
+        st.rayleigh, st.cloud = int(bool(rayleigh)), int(bool(cloud))
         self.struct = st
 
     @property

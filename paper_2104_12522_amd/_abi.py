@@ -29,7 +29,8 @@ class BmModel(C.Structure):
         ("err", C.c_void_p),
         ("mass_amu", C.c_double * BM_MAX_SPECIES),
         ("planet", BmPlanet),
-        ("tau_max", C.c_double),
+        ("tau_max", C.c_double), ("nu_start", C.c_double), ("dnu", C.c_double),
+        ("rayleigh", C.c_int32), ("cloud", C.c_int32),
     ]
 
 
@@ -61,6 +62,7 @@ _PM = C.POINTER(BmModel)
 PROTOTYPES = {
     "bm_status_string": (C.c_char_p, [_I]),
     "bm_version": (_I, []),
+    "bm_struct_size": (C.c_size_t, [_I]),
     "bm_n_params": (_I, [_PM]),
     "bm_atmosphere": (_I, [_PM, _VP, _I, _I, _VP, _VP, _VP, _VP, _VP, _VP]),
     "bm_extinction": (_I, [_PM, _VP, _VP, _VP, _VP, _VP, _VP]),

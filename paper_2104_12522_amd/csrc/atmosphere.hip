@@ -19,23 +19,25 @@ struct AtmShared {
     double scan[BM_MAX_LAYERS];
     double wave_tot[kAtmThreads / kWave];
     double x[BM_MAX_SPECIES];
-    double theta[5 + BM_MAX_SPECIES + 1];
+    double theta[5 + BM_MAX_SPECIES + 2];
     Line2013Consts tp;
     double x_h2;
     double mu;
     double iref;
     int flags;
+    int jcloud;  // largest layer at or below the cloud top (-1: none or no cloud deck)
 };
 
 __device__ void atm_compute(const ModelDev& m, const double* __restrict__ theta_g, AtmShared& sh) {
     const int tid = threadIdx.x;
     const int L = m.L;
     const int ntp = (m.tp_mode == BM_TP_ISOTHERMAL) ? 1 : 5;
-    const int np = ntp + m.S + 1;
+    const int np = ntp + m.S + 1 + m.cloud;
     // parameters, temperature grids, layer pressures: one round of loads
     if (tid < np) sh.theta[tid] = theta_g[tid];
     if (tid < m.NT && m.temp) sh.tgrid[tid] = m.temp[tid];
     if (tid < m.NTc && m.temp_cia) sh.tgrid_cia[tid] = m.temp_cia[tid];
+    if (tid == 0) sh.jcloud = -1;
     // with L <= 128 the Line-2013 profile's two xi() terms of layer l are evaluated by
     // threads l and l + 128 (a dependent chain half as long)
     const bool split = (m.tp_mode == BM_TP_LINE2013) && (2 * L <= kAtmThreads);
@@ -48,6 +50,8 @@ __device__ void atm_compute(const ModelDev& m, const double* __restrict__ theta_
     // per-sample constants, each on its own thread
     if (tid < m.S) sh.x[tid] = pow10_(theta[ntp + tid]);
     if (m.tp_mode == BM_TP_LINE2013 && tid >= 32 && tid < 36) line2013_consts_part(theta, m.pl, tid - 32, &sh.tp);
+    // gray cloud deck: the largest layer with p_l >= p_cloud (any layer order)
+    if (m.cloud && tid < L && p >= pow10_(theta[np - 1])) atomicMax(&sh.jcloud, tid);
     __syncthreads();
     // totals, mean molecular mass and flags on the last thread, which has no layer of its
     // own in the split profile evaluation below
@@ -201,6 +205,7 @@ __global__ void __launch_bounds__(kAtmThreads)
             rec.wc[tid] = wc;
             const double nh2 = sh.x_h2 * sh.ndens[tid];
             rec.bfac[tid] = nh2 * nh2;
+            rec.rfac[tid] = (T)nh2;
             for (int i = 0; i < m.S; ++i) rec.afac[i * L + tid] = (T)(sh.x[i] * sh.ndens[tid]);
             // impact-parameter quadrature weight of f_j (trapezoid in b)
             double c;
@@ -218,6 +223,7 @@ __global__ void __launch_bounds__(kAtmThreads)
             rec.hdr->base = r[0] * r[0];
             rec.hdr->rs2 = m.pl.rs_cm * m.pl.rs_cm;
             rec.hdr->flags = sh.flags;
+            rec.hdr->jcloud = sh.jcloud;
             flags_out[b] = sh.flags;
         }
     }

@@ -47,6 +47,8 @@ struct ModelDev {
     double mass[BM_MAX_SPECIES];
     bm_planet pl;
     double tau_max;  // optical-depth limit (+infinity: none)
+    double nu_start, dnu;
+    int rayleigh, cloud;
 };
 
 // A run of consecutive samples that use the same model.
@@ -98,8 +100,9 @@ struct RecordHeader {
     double base;     // r_0^2
     double rs2;      // stellar radius squared
     int32_t flags;   // sample flags
-    int32_t counter; // tiles finished (reset to zero by the last tile)
-    int32_t pad[2];
+    int32_t counter; // unused
+    int32_t jcloud;  // chords j <= jcloud lie in or below the cloud deck (-1: none)
+    int32_t pad;
 };
 
 inline __host__ __device__ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -115,7 +118,7 @@ __host__ __device__ inline size_t chord_weight_entries(int L) {
 // Byte layout of one sample record for compute type T.
 template <typename T>
 struct RecordLayout {
-    size_t hdr, kidx, kcidx, w, wc, bfac, afac, cw, wb, total;
+    size_t hdr, kidx, kcidx, w, wc, bfac, rfac, afac, cw, wb, total;
     __host__ __device__ RecordLayout(int S, int L) {
         size_t o = 0;
         hdr = o;   o = align_up(o + sizeof(RecordHeader), 64);
@@ -124,6 +127,7 @@ struct RecordLayout {
         w = o;     o = align_up(o + sizeof(T) * L, 64);
         wc = o;    o = align_up(o + sizeof(double) * L, 64);
         bfac = o;  o = align_up(o + sizeof(double) * L, 64);
+        rfac = o;  o = align_up(o + sizeof(T) * L, 64);
         afac = o;  o = align_up(o + sizeof(T) * L * S, 64);
         cw = o;    o = align_up(o + sizeof(double) * L, 64);
         wb = o;    o = align_up(o + sizeof(T) * chord_weight_entries<T>(L), 256);
@@ -139,6 +143,7 @@ struct RecordView {
     T* w;
     double* wc;    // CIA interpolation weight
     double* bfac;  // n_H2^2 (overflows float: the CIA term is formed in double)
+    T* rfac;       // n_H2 (Rayleigh scattering)
     T* afac;       // [S][L] absorber number densities
     double* cw;    // impact-parameter weight of f_j
     T* wb;         // chord weights (layout: chord_weight_entries)
@@ -151,6 +156,7 @@ struct RecordView {
         w = (T*)(base + lay.w);
         wc = (double*)(base + lay.wc);
         bfac = (double*)(base + lay.bfac);
+        rfac = (T*)(base + lay.rfac);
         afac = (T*)(base + lay.afac);
         cw = (double*)(base + lay.cw);
         wb = (T*)(base + lay.wb);

@@ -73,6 +73,15 @@ __host__ __device__ inline double expint_e2(double x) { return expint_e2_ex(x, e
 
 __host__ __device__ inline double pow10_(double x) { return exp2(x * 3.32192809488736234787); }
 
+// H2 Rayleigh-scattering cross section (cm^2) at wavenumber nu (cm^-1): the Dalgarno &
+// Williams (1962) series in inverse powers of the wavelength in Angstrom (terms in
+// lambda^-4, lambda^-6, lambda^-8), evaluated in Horner form in lambda^-2.
+__host__ __device__ inline double rayleigh_h2_xsec(double nu) {
+    const double inv_lam = nu * 1.0e-8;  // 1 / (lambda in Angstrom)
+    const double q = inv_lam * inv_lam;
+    return q * q * (8.14e-13 + q * (1.28e-6 + q * 1.61));
+}
+
 // ---- Line et al. (2013) five-parameter temperature profile ------------------------------
 // Per-sample constants of the profile, evaluated once per sample.
 struct Line2013Consts {

@@ -75,6 +75,7 @@ __global__ void k_extinction(ModelDev m, const double* __restrict__ temp, const 
         double c0 = c[0], c1 = c[Nnu];
         e += nh2[l] * nh2[l] * ((1.0 - wc) * c0 + wc * c1);
     }
+    if (m.rayleigh) e += nh2[l] * rayleigh_h2_xsec(m.nu_start + m.dnu * nu);
     ext[(size_t)l * Nnu + nu] = (T)e;
 }
 
@@ -156,6 +157,8 @@ int validate_model(const bm_model& m, bool need_tables) {
     if (m.n_temp_cia > 0 && (!m.cia || !m.temp_cia)) return BM_EINVAL;
     if (m.bin_width < 0) return BM_ESHAPE;
     if (m.bin_width > 0 && m.n_nu / m.bin_width < 1) return BM_ESHAPE;
+    if (m.rayleigh && !(m.dnu > 0.0 && m.nu_start + m.dnu * (m.n_nu - 1) > 0.0 && m.nu_start > 0.0))
+        return BM_EINVAL;
     return BM_OK;
 }
 
@@ -179,6 +182,10 @@ ModelDev to_device_view(const bm_model& m) {
     for (int i = 0; i < BM_MAX_SPECIES; ++i) d.mass[i] = m.mass_amu[i];
     d.pl = m.planet;
     d.tau_max = (m.tau_max > 0.0) ? m.tau_max : __builtin_huge_val();
+    d.nu_start = m.nu_start;
+    d.dnu = m.dnu;
+    d.rayleigh = m.rayleigh ? 1 : 0;
+    d.cloud = m.cloud ? 1 : 0;
     return d;
 }
 
@@ -507,11 +514,21 @@ extern "C" const char* bm_status_string(int status) {
     }
 }
 
-extern "C" int bm_version(void) { return 101; }
+extern "C" int bm_version(void) { return 102; }
+
+extern "C" size_t bm_struct_size(int which) {
+    switch (which) {
+        case 0: return sizeof(bm_planet);
+        case 1: return sizeof(bm_model);
+        case 2: return sizeof(bm_demcz);
+        case 3: return sizeof(bm_mlp);
+        default: return 0;
+    }
+}
 
 extern "C" int bm_n_params(const bm_model* model) {
     if (!model) return BM_EINVAL;
-    return (model->tp_mode == BM_TP_ISOTHERMAL ? 1 : 5) + model->n_species + 1;
+    return (model->tp_mode == BM_TP_ISOTHERMAL ? 1 : 5) + model->n_species + 1 + (model->cloud ? 1 : 0);
 }
 
 extern "C" int bm_extinction(const bm_model* model, const double* temp, const double* n_species,

@@ -125,6 +125,11 @@ __device__ __forceinline__ double opaque_fraction(float tau, double tau_max) {
 __device__ __forceinline__ double opaque_fraction(double tau, double tau_max) {
     return tau >= tau_max ? 1.0 : -dev_expm1(-tau);
 }
+// chord j: opaque at and below the cloud deck's layer jcl, else as above
+template <typename F>
+__device__ __forceinline__ double chord_fraction(int j, int jcl, F tau, double tau_max) {
+    return j <= jcl ? 1.0 : opaque_fraction(tau, tau_max);
+}
 
 template <typename T, int kWaves, int kS, bool kCia, bool kNonTemporal, int kMode>
 __global__ void __launch_bounds__(kWaves * kWave)
@@ -167,6 +172,9 @@ __global__ void __launch_bounds__(kWaves * kWave)
     double* dsh = reinterpret_cast<double*>(smem + lay.bins);
     double* dout = depth + sg.depth_off + (size_t)s_in * Nnu;
     const int flags = rec.hdr->flags;
+    const int jcl = m.cloud ? rec.hdr->jcloud : -1;  // chords j <= jcl are opaque (cloud deck)
+    // this lane's H2 Rayleigh cross section (the record holds n_H2 per layer)
+    const T sray = m.rayleigh ? (T)rayleigh_h2_xsec(m.nu_start + m.dnu * nu_c) : T(0);
     double dval = __builtin_nan("");  // this lane's depth (wave 0)
 
     if (!(flags & BM_FLAG_RADIUS)) {
@@ -248,6 +256,7 @@ __global__ void __launch_bounds__(kWaves * kWave)
             const int my_l = max(0, min(Ltop - kMfmaM * (lane / 2 + 1) + 2 * wave + (lane & 1), L - 1));
             const int r_k = rec.kidx[my_l];
             const T r_w = rec.w[my_l];
+            const T r_rf = rec.rfac[my_l];
             T r_a[kS];
 #pragma unroll
             for (int i = 0; i < kS; ++i) r_a[i] = rec.afac[i * L + my_l];
@@ -300,6 +309,7 @@ __global__ void __launch_bounds__(kWaves * kWave)
                             const double* c = cia_s + lane_get(r_kc, i) * kTileNu + lane;
                             e += (T)(lane_get(r_b, i) * fma(lane_get(r_wc, i), c[kTileNu] - c[0], c[0]));
                         }
+                        if (m.rayleigh) e = fma(lane_get(r_rf, i), sray, e);
                         es[es_index<T>(l, lane)] = e;
                     }
                 }
@@ -338,7 +348,7 @@ __global__ void __launch_bounds__(kWaves * kWave)
 #pragma unroll
                         for (int r = 0; r < 4; ++r) {
                             const int j = kMfmaM * J + 4 * (lane >> 4) + r;
-                            if (j <= L - 2) pp += cw_s[j] * opaque_fraction(acc[q][r], m.tau_max);
+                            if (j <= L - 2) pp += cw_s[j] * chord_fraction(j, jcl, acc[q][r], m.tau_max);
                         }
                         pp += __shfl_xor(pp, 16);
                         pp += __shfl_xor(pp, 32);
@@ -376,6 +386,7 @@ __global__ void __launch_bounds__(kWaves * kWave)
             __syncthreads();
             if (wave == 0) {
                 double sum = rec.hdr->base;
+                if (jcl >= L - 1) sum += cw_s[L - 1];  // the top chord lies in the deck
                 for (int J = 0; J < nJ; ++J) sum += part[J * kTileNu + lane];
                 dval = sum / rec.hdr->rs2;
             }
@@ -393,6 +404,7 @@ __global__ void __launch_bounds__(kWaves * kWave)
         const int mine = min(lb + lane, L - 1);
         const int r_k = rec.kidx[mine];
         const T r_w = rec.w[mine];
+        const T r_rf = rec.rfac[mine];
         T r_a[kS];
 #pragma unroll
         for (int i = 0; i < kS; ++i) r_a[i] = rec.afac[i * L + mine];
@@ -433,6 +445,7 @@ __global__ void __launch_bounds__(kWaves * kWave)
                         e = fma(lane_get(r_a[i], uu), fma(w, s1[u][i] - s0[u][i], s0[u][i]), e);
                     if constexpr (kCia)
                         e += (T)(lane_get(r_b, uu) * fma(lane_get(r_wc, uu), c1[u] - c0[u], c0[u]));
+                    if (m.rayleigh) e = fma(lane_get(r_rf, uu), sray, e);
                     es[es_index<T>(l, lane)] = e;
                 }
             }
@@ -502,7 +515,7 @@ __global__ void __launch_bounds__(kWaves * kWave)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int j = kMfmaM * J + 4 * (lane >> 4) + r;
-                    if (j <= L - 2) pp += cw_s[j] * opaque_fraction(acc[r], m.tau_max);
+                    if (j <= L - 2) pp += cw_s[j] * chord_fraction(j, jcl, acc[r], m.tau_max);
                 }
                 pp += __shfl_xor(pp, 16);
                 pp += __shfl_xor(pp, 32);
@@ -511,6 +524,7 @@ __global__ void __launch_bounds__(kWaves * kWave)
             __syncthreads();
             if (wave == 0) {
                 double s = rec.hdr->base;
+                if (jcl >= L - 1) s += cw_s[L - 1];
                 for (int J = 0; J < nJ; ++J) s += part[J * kTileNu + lane];
                 dval = s / rec.hdr->rs2;
             }
@@ -535,13 +549,14 @@ __global__ void __launch_bounds__(kWaves * kWave)
 #pragma unroll
                 for (int r = 0; r < kRows; ++r) {
                     const int j = j0 + r;
-                    if (j <= L - 2) acc += cw_s[j] * opaque_fraction(t[r], m.tau_max);
+                    if (j <= L - 2) acc += cw_s[j] * chord_fraction(j, jcl, t[r], m.tau_max);
                 }
             }
             part[wave * kTileNu + lane] = acc;
             __syncthreads();
             if (wave == 0) {
                 double s = rec.hdr->base;
+                if (jcl >= L - 1) s += cw_s[L - 1];
                 for (int w2 = 0; w2 < kWaves; ++w2) s += part[w2 * kTileNu + lane];
                 dval = s / rec.hdr->rs2;
             }

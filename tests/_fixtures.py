@@ -32,9 +32,12 @@ def gpu_model(setup, sigma, cia=None, data=None, err=None, device="cuda"):
                     cia=None if cia is None else torch.as_tensor(cia),
                     cia_temps=setup.cia_temps if cia is not None else None,
                     bin_width=setup.bin_width, data=data, err=err, device=device,
-                    tau_max=setup.tau_max)
+                    tau_max=setup.tau_max, nu_start=float(setup.nu[0]),
+                    dnu=float(setup.nu[1] - setup.nu[0]) if setup.nu.size > 1 else 1.0,
+                    rayleigh=setup.rayleigh, cloud=setup.cloud)
 
 
 def prior_for(setup):
-    return (wl.isothermal_prior(setup.n_species) if setup.tp_mode == 0
-            else wl.line2013_prior(setup.n_species))
+    p = (wl.isothermal_prior(setup.n_species) if setup.tp_mode == 0
+         else wl.line2013_prior(setup.n_species))
+    return wl.with_cloud(p) if setup.cloud else p

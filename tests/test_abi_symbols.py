@@ -83,3 +83,13 @@ def test_model_validation(lib):
     assert lib.bm_workspace_size(C.byref(m), 1, None, 7) == 7 * one
     m.n_species = 9
     assert lib.bm_workspace_size(C.byref(m), 1, None, 1) == 0
+
+
+def test_binding_struct_layouts_match_the_library(lib):
+    # the ctypes mirrors of the header's structures have the library's sizes
+    from paper_2104_12522_amd import _abi
+    lib.bm_struct_size.restype = C.c_size_t
+    lib.bm_struct_size.argtypes = [C.c_int]
+    for which, cls in enumerate((_abi.BmPlanet, _abi.BmModel, _abi.BmDemcz, _abi.BmMlp)):
+        assert lib.bm_struct_size(which) == C.sizeof(cls), cls.__name__
+    assert lib.bm_struct_size(99) == 0

@@ -347,3 +347,71 @@ def test_fused_optical_depth_limit(dtype):
     d0 = bm.forward_batch(model0, p).depth.clone()
     d1 = bm.forward_batch(model1, p).depth.clone()
     assert torch.all(d1 >= d0 - 1e-15) and float((d1 - d0).max()) > 0
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_fused_cloud_deck_and_rayleigh(dtype):
+    # Sec. 3 (gray cloud deck, H2 Rayleigh scattering) with the cloud-top pressure of the
+    # Sec. 7 retrievals as the last parameter. Cases: a deck below every layer (no effect),
+    # a deck above the top layer (every chord opaque: depth = (r_top / Rs)^2 exactly),
+    # and decks inside the atmosphere; every launch configuration against the oracle.
+    if dtype == "f64":
+        s, sigma = config1_table(n_nu=300)
+        cia = None
+        base = np.array([wl.config1_params(), [1500.0, -3.0, 1.25], [700.0, -5.0, 1.0],
+                         [1200.0, -4.0, 1.1], [1800.0, -2.5, 1.2]])
+        rtol = 1e-10
+    else:
+        s, sigma, cia = small_config2(n_nu=700, n_layers=80, seed=71)
+        base = prior_for(s).draw(5, seed=72)
+        rtol = 1e-4
+    s.rayleigh, s.cloud = True, True
+    log_pc = np.array([3.0, -9.0, -1.3, -4.7, 0.6])
+    params = np.column_stack([base, log_pc])
+    assert [ort.cloud_layer(s.p_bar, v) for v in log_pc[:2]] == [-1, s.p_bar.size - 1]
+    model = gpu_model(s, sigma, cia)
+    assert model.n_params == params.shape[1]
+    B = params.shape[0]
+    f = bm.Forward(model, B)
+    p = torch.as_tensor(params, device="cuda")
+    refs = [ort.forward(th, s, sigma.astype(np.float64), None if cia is None else cia.astype(np.float64))
+            for th in params]
+    n_cfg = len(bm.forward_configs()) if dtype == "f32" else 1
+    for c in range(n_cfg):
+        if dtype == "f32":
+            f.set_config(c)
+        f(p)
+        torch.cuda.synchronize()
+        for b in range(B):
+            sl = slice(int(f.depth_off[b]), int(f.depth_off[b + 1]))
+            got = _np(f.depth[sl])
+            assert int(f.flags[b]) == refs[b]["flags"]
+            np.testing.assert_allclose(got, refs[b]["depth"], rtol=rtol, err_msg=f"config {c} sample {b}")
+        r_top = refs[1]["atm"]["radius"][-1]
+        sl = slice(int(f.depth_off[1]), int(f.depth_off[2]))
+        np.testing.assert_allclose(_np(f.depth[sl]), (r_top / s.planet.rs_cm) ** 2, rtol=1e-12)
+    if dtype == "f32":
+        f.set_config(-1)
+    # the deck and the scattering each raise the depth
+    s_clear = dataclasses.replace(s, rayleigh=False, cloud=False)
+    d_clear = bm.forward_batch(gpu_model(s_clear, sigma, cia),
+                               torch.as_tensor(base, device="cuda")).depth.clone()
+    s_ray = dataclasses.replace(s, cloud=False)
+    d_ray = bm.forward_batch(gpu_model(s_ray, sigma, cia),
+                             torch.as_tensor(base, device="cuda")).depth.clone()
+    assert torch.all(d_ray >= d_clear) and float((d_ray - d_clear).max()) > 0
+    assert torch.all(f.depth >= d_ray * (1 - 1e-6))
+
+
+def test_extinction_step_rayleigh():
+    # step a3 with Rayleigh scattering: the oracle's extinction plus n_H2 sigma_R(nu)
+    s, sigma = config1_table(n_nu=200)
+    s.rayleigh = True
+    model = gpu_model(s, sigma)
+    th = np.array(wl.config1_params())
+    atm = oatm.atmosphere(th, s.p_bar, s.mass_amu, s.tp_mode, s.planet)
+    ext_ref, _ = ort.extinction(sigma.astype(np.float64), s.temps, atm["temp"], atm["n_species"],
+                                None, None, atm["n_h2"])
+    ext_ref = ext_ref + atm["n_h2"][:, None] * ort.rayleigh_h2(s.nu)[None, :]
+    ext, _ = bm.extinction(model, atm["temp"], atm["n_species"], atm["n_h2"])
+    np.testing.assert_allclose(_np(ext), ext_ref, rtol=1e-12)
