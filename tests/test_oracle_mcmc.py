@@ -79,3 +79,75 @@ def test_delayed_acceptance_keeps_the_posterior():
     se = np.sqrt(np.diag(cov) / n_eff)
     assert np.all(np.abs(s.mean(0) - mu) < 5 * se)
     np.testing.assert_allclose(np.diag(np.cov(s.T)), np.diag(cov), rtol=0.2)
+
+
+# ---- snooker moves (ter Braak & Vrugt 2008) ------------------------------------------
+_MU4 = np.array([0.3, -0.2, 0.1, 0.0])
+_COV4 = np.array([[1.0, 0.6, 0.0, 0.0], [0.6, 1.0, 0.3, 0.0],
+                  [0.0, 0.3, 1.0, -0.4], [0.0, 0.0, -0.4, 1.0]]) * 0.04
+
+
+def test_snooker_move_geometry():
+    # the move stays on the line through x and z, and its length is gamma_s times the
+    # orthogonal projection of z_R1 - z_R2 onto that line (least squares onto the line's
+    # direction); the proposal factor is the (d-1)-th power of the distance ratio to z
+    g = np.random.default_rng(4)
+    for d in (2, 5, 9):
+        x, zz, z1, z2 = g.normal(size=(4, d))
+        y, log_q = mcmc.snooker(x, zz, z1, z2, 1.7)
+        u = (x - zz)[:, None]
+        coef, *_ = np.linalg.lstsq(u, z1 - z2, rcond=None)      # projection coefficient
+        np.testing.assert_allclose(y - x, 1.7 * coef[0] * (x - zz), rtol=1e-12, atol=1e-14)
+        _, res, *_ = np.linalg.lstsq(u, y - x, rcond=None)
+        assert res.size == 0 or res[0] < 1e-24                   # collinear with x - z
+        ratio = np.linalg.norm(y - zz) / np.linalg.norm(x - zz)
+        assert log_q == pytest.approx((d - 1) * np.log(ratio), rel=1e-12, abs=1e-14)
+    # x on the archive member: no line, no move
+    y, log_q = mcmc.snooker(np.ones(3), np.ones(3), np.zeros(3), np.full(3, 2.0), 1.5)
+    assert np.array_equal(y, np.ones(3)) and log_q == -np.inf
+
+
+def test_snooker_third_row_is_uniform_over_the_others():
+    for m, r1, r2 in ((3, 0, 2), (7, 2, 5), (7, 5, 2), (9, 3, 4), (5, 4, 0)):
+        n = 6000
+        rows = [mcmc.third_row((k + 0.5) / n, m, r1, r2) for k in range(n)]
+        counts = np.bincount(rows, minlength=m)
+        assert counts[r1] == 0 and counts[r2] == 0 and len(counts) == m
+        others = [counts[i] for i in range(m) if i not in (r1, r2)]
+        assert max(others) - min(others) <= 1
+
+
+def test_snooker_moves_alone_sample_a_correlated_gaussian():
+    # pure snooker (every move): a wrong proposal factor shifts these variances by
+    # 25-60 %, outside the tolerance
+    hist, acc = mcmc.run(_gauss_chi2(_MU4, _COV4), 16, 2500, np.full(4, -3.0), np.full(4, 3.0),
+                         seed=7, thin=5, p_snooker=1.0)
+    s = hist[500:].reshape(-1, 4)
+    se = np.sqrt(np.diag(_COV4) / (s.shape[0] / 25.0))
+    assert np.all(np.abs(s.mean(0) - _MU4) < 5 * se)
+    np.testing.assert_allclose(s.var(0), np.diag(_COV4), rtol=0.15)
+    assert 0.1 < acc.mean() / 2500 < 0.8
+
+
+def test_demczs_with_delayed_acceptance_keeps_the_posterior():
+    # half the moves snooker, a biased surrogate in stage 1 (which carries the snooker
+    # factor; dropping it there shrinks these variances by about 40 %)
+    surr = _gauss_chi2(_MU4 + np.array([0.05, -0.05, 0.02, 0.0]), _COV4 * 1.5)
+    hist, acc = mcmc.run(_gauss_chi2(_MU4, _COV4), 16, 3000, np.full(4, -3.0), np.full(4, 3.0),
+                         seed=9, thin=5, surrogate_chi2=surr, p_snooker=0.5)
+    s = hist[500:].reshape(-1, 4)
+    se = np.sqrt(np.diag(_COV4) / (s.shape[0] / 25.0))
+    assert np.all(np.abs(s.mean(0) - _MU4) < 5 * se)
+    np.testing.assert_allclose(s.var(0), np.diag(_COV4), rtol=0.15)
+
+
+def test_zero_snooker_rate_is_plain_demcz():
+    g = np.random.default_rng(6)
+    x, z = g.normal(size=(9, 3)), g.normal(size=(40, 3))
+    lo, hi = np.full(3, -9.0), np.full(3, 9.0)
+    y0, _, _ = mcmc.propose(x, z, 40, 3, 17, lo, hi, 1e-6)
+    y1, lq = mcmc.propose_zs(x, z, 40, 3, 17, lo, hi, 1e-6, 0.0)
+    assert np.array_equal(y0, y1) and np.all(lq == 0.0)
+    y2, lq2 = mcmc.propose_zs(x, z, 40, 3, 17, lo, hi, 1e-6, 0.5)
+    moved = lq2 != 0.0
+    assert 0 < moved.sum() < 9 and np.array_equal(y2[~moved], y0[~moved])
