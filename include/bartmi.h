@@ -248,19 +248,23 @@ int bm_timing_stop(double* total_ms, int64_t* launches);
  * Sec. 3 and Sec. 5: MC3's differential-evolution samplers (DEMC, ter Braak 2006; the
  * archive-based DEMCzs, ter Braak & Vrugt 2008), here in archive form for a whole
  * generation of chains at once, so every chain's forward model of a generation is one
- * batched bm_forward_batch call. Proposal y = x + gamma (z_r1 - z_r2) + e from two
+ * batched bm_forward_batch call. DE move: y = x + gamma (z_r1 - z_r2) + e from two
  * distinct archive rows, gamma = 2.38/sqrt(2d) (1 every 10th generation), e ~
- * N(0, (eps_scale width)^2); log posterior -chi^2/2 in the uniform prior box;
- * Metropolis acceptance. Delayed acceptance (Christen & Fox 2005): a surrogate chi^2
- * screens proposals (stage 1) and the exact model decides among the survivors with the
- * corrected ratio (stage 2), which keeps the exact posterior.
+ * N(0, (eps_scale width)^2). Snooker move (with probability p_snooker): a third distinct
+ * archive row z; z_r1 and z_r2 projected onto the line through x and z; y = x +
+ * gamma_s (projection difference), gamma_s ~ U[1.2, 2.2); proposal factor
+ * (|y - z| / |x - z|)^(d-1) (no move when x = z). Log posterior -chi^2/2 in the uniform
+ * prior box; Metropolis-Hastings acceptance. Delayed acceptance (Christen & Fox 2005): a
+ * surrogate chi^2 screens proposals (stage 1, with the proposal factor) and the exact
+ * model decides among the survivors with the corrected ratio (stage 2, in which the
+ * proposal factor cancels), which keeps the exact posterior. d <= 28.
  * Random numbers: SplitMix64 outputs addressed by (generation, chain, slot) counters.
  * All pointers are device pointers owned by the caller; the sampler state lives in them,
  * including the generation and archive counters, so a generation can be graph-captured
  * and replayed. */
 typedef struct bm_demcz {
     int32_t n_chains;   /* C, 1..1024                                                       */
-    int32_t n_params;   /* d, 1..32                                                         */
+    int32_t n_params;   /* d, 1..28                                                         */
     int32_t z_cap;      /* archive capacity in rows (>= 2)                                  */
     int32_t thin;       /* append the C chain states to the archive every `thin` generations */
     int32_t hist_cap;   /* generations the history buffer can hold (0 when history is NULL) */
@@ -277,6 +281,10 @@ typedef struct bm_demcz {
     double* history;    /* [hist_cap][C][d] states after each generation, or NULL            */
     const double* lo;   /* [d] prior box lower bounds                                        */
     const double* hi;   /* [d] prior box upper bounds                                        */
+    double p_snooker;   /* probability of a snooker move per chain and generation (DEMCzs,
+                           ter Braak & Vrugt 2008; 0.1 there), 0 = archive DE moves only     */
+    double* log_q;      /* [C] log proposal factor of each chain's current proposal (0 for DE
+                           moves); required when p_snooker > 0, else may be NULL           */
 } bm_demcz;
 
 /* Chains at uniform prior draws, archive with z_init further draws, counters reset. */

@@ -1,19 +1,22 @@
-// Differential-evolution MCMC with a past-state archive (DE-MCz) and two-stage delayed
-// acceptance, on the GPU. BART samples its posterior with MC3's differential-evolution
-// samplers (Sec. 3, Sec. 4 item 10, Sec. 5: DEMC of ter Braak 2006 and the archive-based
-// DEMCzs of ter Braak & Vrugt 2008); this file implements the archive (DE-MCz) proposal
-// for a whole generation of chains at once, so that every chain's forward model of a
-// generation runs in one batched launch.
+// Differential-evolution MCMC with a past-state archive and snooker moves (DEMCzs) and
+// two-stage delayed acceptance, on the GPU. BART samples its posterior with MC3's
+// differential-evolution samplers (Sec. 3, Sec. 4 item 10, Sec. 5: DEMC of ter Braak 2006
+// and the archive-based DEMCzs of ter Braak & Vrugt 2008); this file implements the
+// archive proposals for a whole generation of chains at once, so that every chain's
+// forward model of a generation runs in one batched launch.
 //
-// Proposal (ter Braak & Vrugt 2008): y_i = x_i + gamma (z_r1 - z_r2) + e,
+// DE move (ter Braak & Vrugt 2008): y_i = x_i + gamma (z_r1 - z_r2) + e,
 //   r1 != r2 drawn uniformly from the archive, gamma = 2.38 / sqrt(2 d) except every
 //   10th generation (gamma = 1, mode jumping), e ~ N(0, (eps_scale * width)^2) per
-//   parameter. The proposal is symmetric given the archive.
-// Acceptance: Metropolis with log pi = -chi^2 / 2 inside the uniform prior box.
+//   parameter. Symmetric given the archive.
+// Snooker move (same paper), taken with probability p_snooker: a third archive row z
+//   distinct from r1 and r2; u = (x - z) / |x - z|; y = x + gamma_s ((z_r1 - z_r2) . u) u
+//   with gamma_s ~ U[1.2, 2.2); Hastings factor (|y - z| / |x - z|)^(d - 1).
+// Acceptance: Metropolis-Hastings with log pi = -chi^2 / 2 inside the uniform prior box.
 // Delayed acceptance (Christen & Fox 2005): stage 1 accepts with
-//   min(1, exp(lp*_y - lp*_x)) using a cheap surrogate; only stage-1 survivors run the
-//   exact forward model, and stage 2 accepts with min(1, exp((lp_y - lp_x) - (lp*_y -
-//   lp*_x))), which leaves the exact posterior invariant.
+//   min(1, exp(lp*_y - lp*_x + log q)) using a cheap surrogate; only stage-1 survivors run
+//   the exact forward model, and stage 2 accepts with min(1, exp((lp_y - lp_x) - (lp*_y -
+//   lp*_x))) (the proposal factor cancels), which leaves the exact posterior invariant.
 //
 // Random numbers: a counter-based generator, SplitMix64 (Steele, Lea & Flood 2014):
 // the k-th output of the stream with seed s is mix(s + (k + 1) * 0x9E3779B97F4A7C15),
@@ -33,6 +36,8 @@ namespace bm {
 constexpr uint64_t kGolden = 0x9E3779B97F4A7C15ull;
 constexpr int kSlots = 64;           // random draws reserved per (generation, chain)
 constexpr int kSlotR1 = 0, kSlotR2 = 1, kSlotU = 2, kSlotU1 = 3, kSlotNormal = 8;
+constexpr int kSlotMove = 4, kSlotZ = 5, kSlotGammaS = 6;  // snooker: choice, row z, gamma_s
+constexpr int kMaxParams = (kSlots - kSlotNormal) / 2;     // two normal uniforms per parameter
 
 __host__ __device__ inline uint64_t splitmix64(uint64_t seed, uint64_t k) {
     uint64_t z = seed + (k + 1) * kGolden;
@@ -71,15 +76,52 @@ __global__ void k_demcz_propose(bm_demcz s, double gamma_de) {
     if (r1 >= M) r1 = M - 1;
     if (r2 >= M - 1) r2 = M - 2;
     if (r2 >= r1) r2 += 1;
-    const double gamma = (g % 10 == 9) ? 1.0 : gamma_de;
-    for (int p = 0; p < d; ++p) {
-        const double width = s.hi[p] - s.lo[p];
-        // written operation by operation; contraction is off in this file
-        const double e = (s.eps_scale * width) * normal_draw(s.seed, g, c, s.n_chains, p);
-        const double diff = s.z[(size_t)r1 * d + p] - s.z[(size_t)r2 * d + p];
-        const double step = gamma * diff;
-        s.prop[(size_t)c * d + p] = (s.x[(size_t)c * d + p] + step) + e;
+    const double* x = s.x + (size_t)c * d;
+    double* y = s.prop + (size_t)c * d;
+    const bool snooker = s.p_snooker > 0.0 && M >= 3 && u01(s.seed, counter(g, c, s.n_chains, kSlotMove)) < s.p_snooker;
+    if (!snooker) {
+        const double gamma = (g % 10 == 9) ? 1.0 : gamma_de;
+        for (int p = 0; p < d; ++p) {
+            const double width = s.hi[p] - s.lo[p];
+            // written operation by operation; contraction is off in this file
+            const double e = (s.eps_scale * width) * normal_draw(s.seed, g, c, s.n_chains, p);
+            const double diff = s.z[(size_t)r1 * d + p] - s.z[(size_t)r2 * d + p];
+            const double step = gamma * diff;
+            y[p] = (x[p] + step) + e;
+        }
+        if (s.log_q) s.log_q[c] = 0.0;
+        return;
     }
+    // snooker: a third row, uniform over the M - 2 rows other than r1 and r2
+    int rz = (int)(u01(s.seed, counter(g, c, s.n_chains, kSlotZ)) * (M - 2));
+    if (rz >= M - 2) rz = M - 3;
+    const int ra = min(r1, r2), rb = max(r1, r2);
+    if (rz >= ra) rz += 1;
+    if (rz >= rb) rz += 1;
+    const double* zz = s.z + (size_t)rz * d;
+    const double* z1 = s.z + (size_t)r1 * d;
+    const double* z2 = s.z + (size_t)r2 * d;
+    double nn = 0.0, dot = 0.0;
+    for (int p = 0; p < d; ++p) {
+        const double e = x[p] - zz[p];
+        nn = nn + e * e;
+        dot = dot + (z1[p] - z2[p]) * e;
+    }
+    double lq = -INFINITY;  // x on z: no line, no move
+    if (nn > 0.0) {
+        const double gamma_s = 1.2 + u01(s.seed, counter(g, c, s.n_chains, kSlotGammaS));
+        const double coef = gamma_s * (dot / nn);
+        double n2 = 0.0;
+        for (int p = 0; p < d; ++p) {
+            y[p] = x[p] + coef * (x[p] - zz[p]);
+            const double f = y[p] - zz[p];
+            n2 = n2 + f * f;
+        }
+        if (n2 > 0.0) lq = (0.5 * (d - 1)) * (log(n2) - log(nn));
+    } else {
+        for (int p = 0; p < d; ++p) y[p] = x[p];
+    }
+    s.log_q[c] = lq;
 }
 
 __device__ inline bool in_box(const bm_demcz& s, const double* y) {
@@ -108,7 +150,8 @@ __global__ void k_demcz_accept(bm_demcz s, const double* __restrict__ chi2, cons
         if (mode == 0) {
             const double lpy = log_post(s, y, chi2[c], flags ? flags[c] : 0);
             const double u = u01(s.seed, counter(g, c, C, kSlotU));
-            take = isfinite(lpy) && log(u) < lpy - s.lp[c];
+            const double lq = s.log_q ? s.log_q[c] : 0.0;
+            take = isfinite(lpy) && log(u) < (lpy - s.lp[c]) + lq;
             if (take) s.lp[c] = lpy;
         } else {
             // delayed acceptance, stage 2: only stage-1 survivors were evaluated
@@ -151,7 +194,8 @@ __global__ void k_da_screen(bm_demcz s, const double* __restrict__ chi2_surr, in
     int a = 0;
     if (in_box(s, y) && isfinite(chi2_surr[c])) {
         const double u = u01(s.seed, counter(g, c, s.n_chains, kSlotU1));
-        a = log(u) < (-0.5 * chi2_surr[c]) - s.lp_surr[c];
+        const double lq = s.log_q ? s.log_q[c] : 0.0;
+        a = log(u) < ((-0.5 * chi2_surr[c]) - s.lp_surr[c]) + lq;
     }
     active[c] = a;
 }
@@ -200,9 +244,11 @@ using namespace bm;
 static int check_demcz(const bm_demcz* s) {
     if (!s || !s->x || !s->lp || !s->prop || !s->z || !s->counters || !s->n_accept || !s->lo || !s->hi)
         return BM_EINVAL;
-    if (s->n_chains < 1 || s->n_chains > 1024 || s->n_params < 1 || s->n_params > 32) return BM_ESHAPE;
+    if (s->n_chains < 1 || s->n_chains > 1024 || s->n_params < 1 || s->n_params > kMaxParams) return BM_ESHAPE;
     if (s->thin < 1 || s->z_cap < 2) return BM_ESHAPE;
     if (!(s->eps_scale >= 0.0)) return BM_EINVAL;
+    if (!(s->p_snooker >= 0.0 && s->p_snooker <= 1.0)) return BM_EINVAL;
+    if (s->p_snooker > 0.0 && !s->log_q) return BM_EINVAL;
     return BM_OK;
 }
 

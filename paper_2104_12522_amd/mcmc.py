@@ -18,11 +18,12 @@ from . import (BartmiError, BmDemcz, BmModel, Forward, _check, _ptr, _stream, li
 
 
 class DEMCz:
-    """GPU state of a DE-MCz sampler (see bm_demcz in bartmi.h)."""
+    """GPU state of a DE-MCz sampler with snooker moves at rate p_snooker (see bm_demcz in
+    bartmi.h)."""
 
     def __init__(self, n_chains: int, lo, hi, seed: int, thin: int = 10, z_cap: int | None = None,
                  hist_cap: int = 0, eps_scale: float = 1e-6, surrogate: bool = False,
-                 device="cuda"):
+                 p_snooker: float = 0.0, device="cuda"):
         lo = np.asarray(lo, dtype=np.float64)
         hi = np.asarray(hi, dtype=np.float64)
         d = lo.size
@@ -39,12 +40,15 @@ class DEMCz:
         self.history = torch.zeros(hist_cap, n_chains, d, **f64) if hist_cap else None
         self.lo = torch.as_tensor(lo, **f64)
         self.hi = torch.as_tensor(hi, **f64)
+        self.log_q = torch.zeros(n_chains, **f64)
         st = BmDemcz()
         st.n_chains, st.n_params, st.z_cap, st.thin = n_chains, d, self.z_cap, thin
         st.hist_cap = hist_cap
         st.seed = seed & 0xFFFFFFFFFFFFFFFF
         st.eps_scale = eps_scale
-        for name in ("x", "lp", "lp_surr", "prop", "z", "counters", "n_accept", "history", "lo", "hi"):
+        st.p_snooker = float(p_snooker)
+        for name in ("x", "lp", "lp_surr", "prop", "z", "counters", "n_accept", "history", "lo", "hi",
+                     "log_q"):
             setattr(st, name, _ptr(getattr(self, name)))
         self.struct = st
 
@@ -143,11 +147,12 @@ class Retrieval:
     ``surrogate`` (optional) maps a [C][d] parameter tensor to a [C] surrogate chi^2 on
     the same stream; it enables two-stage delayed acceptance. ``per_sample_workers`` > 0
     selects the plain per-sample form (PerSampleForward) instead of one batched call per
-    generation."""
+    generation. ``p_snooker`` is the rate of snooker moves (DEMCzs; 0.1 as in ter Braak &
+    Vrugt 2008)."""
 
     def __init__(self, model, n_chains: int, lo, hi, seed: int, thin: int = 10,
                  hist_cap: int = 0, surrogate=None, eps_scale: float = 1e-6, z_cap=None,
-                 per_sample_workers: int = 0):
+                 per_sample_workers: int = 0, p_snooker: float = 0.1):
         self.model = model
         if per_sample_workers:
             if surrogate is not None:
@@ -156,7 +161,7 @@ class Retrieval:
         else:
             self.fwd = Forward(model, n_chains, binned=True, chi2=True)
         self.s = DEMCz(n_chains, lo, hi, seed, thin=thin, hist_cap=hist_cap, z_cap=z_cap,
-                       eps_scale=eps_scale, surrogate=surrogate is not None)
+                       eps_scale=eps_scale, surrogate=surrogate is not None, p_snooker=p_snooker)
         self.surrogate = surrogate
         self.active = torch.ones(n_chains, dtype=torch.int32, device=self.s.x.device)
 

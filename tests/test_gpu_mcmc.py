@@ -26,9 +26,10 @@ def _np(t):
 PRIOR = wl.line2013_prior(4)
 
 
-def test_init_and_proposals_match_reference():
+@pytest.mark.parametrize("p_snooker", [0.0, 0.5])
+def test_init_and_proposals_match_reference(p_snooker):
     C, seed, z_init = 37, 987654321, 100
-    s = DEMCz(C, PRIOR.lo, PRIOR.hi, seed, z_cap=400)
+    s = DEMCz(C, PRIOR.lo, PRIOR.hi, seed, z_cap=400, p_snooker=p_snooker)
     s.init(z_init)
     x_ref, z_ref = om.init_state(seed, C, z_init, PRIOR.lo, PRIOR.hi)
     torch.cuda.synchronize()
@@ -36,13 +37,20 @@ def test_init_and_proposals_match_reference():
     assert np.array_equal(_np(s.z)[:z_init], z_ref)
     assert s.archive_size == z_init and s.generation == 0
     s.propose()
-    y_ref, _, _ = om.propose(x_ref, z_ref, z_init, 0, seed, PRIOR.lo, PRIOR.hi, 1e-6)
+    y_ref, lq_ref = om.propose_zs(x_ref, z_ref, z_init, 0, seed, PRIOR.lo, PRIOR.hi, 1e-6, p_snooker)
+    # DE moves carry normals (device log/cos); snooker moves are +-*/ only: bit-exact
     np.testing.assert_allclose(_np(s.prop), y_ref, rtol=4.5e-16, atol=1e-300)
+    snk = lq_ref != 0.0
+    assert np.array_equal(_np(s.prop)[snk], y_ref[snk])
+    np.testing.assert_allclose(_np(s.log_q), lq_ref, rtol=1e-13, atol=1e-15)
+    if p_snooker > 0:
+        assert 5 < snk.sum() < C - 5
 
 
-def test_accept_bookkeeping_matches_reference():
+@pytest.mark.parametrize("p_snooker", [0.0, 0.5])
+def test_accept_bookkeeping_matches_reference(p_snooker):
     C, seed, d = 64, 4242, PRIOR.lo.size
-    s = DEMCz(C, PRIOR.lo, PRIOR.hi, seed, thin=3, z_cap=1000, hist_cap=8)
+    s = DEMCz(C, PRIOR.lo, PRIOR.hi, seed, thin=3, z_cap=1000, hist_cap=8, p_snooker=p_snooker)
     s.init(50)
     g = np.random.default_rng(1)
     chi2_x = g.uniform(50, 100, C)
@@ -56,9 +64,11 @@ def test_accept_bookkeeping_matches_reference():
         chi2_y = g.uniform(45, 105, C)
         flags = (g.random(C) < 0.05).astype(np.int32)
         s.accept(torch.as_tensor(chi2_y, device="cuda"), torch.as_tensor(flags, device="cuda"))
-        y_ref, _, _ = om.propose(x, z, len(z), gen, seed, PRIOR.lo, PRIOR.hi, 1e-6)
+        y_ref, lq_ref = om.propose_zs(x, z, len(z), gen, seed, PRIOR.lo, PRIOR.hi, 1e-6, p_snooker)
         np.testing.assert_allclose(y, y_ref, rtol=4.5e-16, atol=1e-300)
-        x, lp, taken = om.accept(x, lp, y, chi2_y, flags, gen, seed, PRIOR.lo, PRIOR.hi)
+        lq = _np(s.log_q).copy()
+        np.testing.assert_allclose(lq, lq_ref, rtol=1e-13, atol=1e-15)
+        x, lp, taken = om.accept(x, lp, y, chi2_y, flags, gen, seed, PRIOR.lo, PRIOR.hi, lq)
         if (gen + 1) % 3 == 0:
             z = np.vstack([z, x])
         torch.cuda.synchronize()
@@ -69,9 +79,10 @@ def test_accept_bookkeeping_matches_reference():
     np.testing.assert_array_equal(_np(s.z)[:len(z)], z)
 
 
-def test_delayed_acceptance_steps_match_reference():
+@pytest.mark.parametrize("p_snooker", [0.0, 0.5])
+def test_delayed_acceptance_steps_match_reference(p_snooker):
     C, seed = 48, 77
-    s = DEMCz(C, PRIOR.lo, PRIOR.hi, seed, thin=10, z_cap=500, surrogate=True)
+    s = DEMCz(C, PRIOR.lo, PRIOR.hi, seed, thin=10, z_cap=500, surrogate=True, p_snooker=p_snooker)
     s.init(60)
     g = np.random.default_rng(2)
     chi2_x, chi2s_x = g.uniform(50, 100, C), g.uniform(50, 100, C)
@@ -84,7 +95,11 @@ def test_delayed_acceptance_steps_match_reference():
         y = _np(s.prop)
         cs = g.uniform(45, 105, C)
         s.da_screen(torch.as_tensor(cs, device="cuda"), active)
-        act_ref = om.da_screen(y, cs, ls, gen, seed, PRIOR.lo, PRIOR.hi)
+        lq = _np(s.log_q).copy()
+        if p_snooker > 0:
+            _, lq_ref = om.propose_zs(x, z, len(z), gen, seed, PRIOR.lo, PRIOR.hi, 1e-6, p_snooker)
+            np.testing.assert_allclose(lq, lq_ref, rtol=1e-13, atol=1e-15)
+        act_ref = om.da_screen(y, cs, ls, gen, seed, PRIOR.lo, PRIOR.hi, lq)
         torch.cuda.synchronize()
         assert np.array_equal(_np(active), act_ref)
         ce = g.uniform(45, 105, C)
@@ -96,12 +111,13 @@ def test_delayed_acceptance_steps_match_reference():
         np.testing.assert_array_equal(_np(s.lp_surr), ls)
 
 
-def test_gaussian_target_on_gpu():
+@pytest.mark.parametrize("p_snooker", [0.0, 0.1, 1.0])
+def test_gaussian_target_on_gpu(p_snooker):
     mu = torch.tensor([0.3, -0.2, 0.5], dtype=torch.float64, device="cuda")
     sd = torch.tensor([0.2, 0.1, 0.3], dtype=torch.float64, device="cuda")
     lo, hi = np.full(3, -3.0), np.full(3, 3.0)
     C, n_gen = 64, 1500
-    s = DEMCz(C, lo, hi, 5, thin=5, z_cap=30 + C * n_gen // 5 + C, hist_cap=n_gen)
+    s = DEMCz(C, lo, hi, 5, thin=5, z_cap=30 + C * n_gen // 5 + C, hist_cap=n_gen, p_snooker=p_snooker)
 
     def chi2(y):
         return (((y - mu) / sd) ** 2).sum(1).contiguous()
