@@ -34,6 +34,18 @@ __host__ __device__ inline int mfma_kstep_offset(int L, int J) {
 }
 __host__ __device__ inline int mfma_total_ksteps(int L) { return mfma_kstep_offset(L, mfma_row_blocks(L)); }
 
+// broadcast lane `i` (uniform) of a per-lane value to the whole wave (v_readlane)
+__device__ __forceinline__ int lane_get(int v, int i) { return __builtin_amdgcn_readlane(v, i); }
+__device__ __forceinline__ float lane_get(float v, int i) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), i));
+}
+__device__ __forceinline__ double lane_get(double v, int i) {
+    const long long u = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffLL), i);
+    const int hi = __builtin_amdgcn_readlane((int)(u >> 32), i);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
 // Device view of a bm_model (passed by value in kernel arguments).
 struct ModelDev {
     const void* sigma;
@@ -44,11 +56,11 @@ struct ModelDev {
     const double* data;
     const double* err;
     int S, NT, L, Nnu, NTc, tp_mode, bin_width, nb;
+    int rayleigh, cloud;
     double mass[BM_MAX_SPECIES];
     bm_planet pl;
     double tau_max;  // optical-depth limit (+infinity: none)
     double nu_start, dnu;
-    int rayleigh, cloud;
 };
 
 // A run of consecutive samples that use the same model.
@@ -198,7 +210,9 @@ template <typename T, int kW, bool kNT, int kMode>
 int launch_k_forward(const HostPlan& hp, const LaunchPlan& lp, size_t lds, char* ws, const int32_t* act,
                      double* depth, double* binned, double* c2, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1);
 
-template <typename T>
+// record preparation; kSingle: a single-segment plan whose model is in slot 0;
+// kMasked: `active` is not null
+template <typename T, bool kSingle, bool kMasked>
 __global__ void k_atm_prep(LaunchPlan plan, const double* __restrict__ params, int stride,
                            const int32_t* __restrict__ active, char* __restrict__ ws,
                            int32_t* __restrict__ flags_out);

@@ -91,23 +91,6 @@ struct Line2013Consts {
     double tirr4, tint4;   // T_irr^4, T_int^4
 };
 
-// one quarter of the constants (part 0: kappa/g, 1: gamma_1, 2: gamma_2, 3: alpha and the
-// stream temperatures), so that four threads evaluate them at once
-__host__ __device__ inline void line2013_consts_part(const double* tp, const bm_planet& pl, int part,
-                                                     Line2013Consts* c) {
-    switch (part) {
-        case 0: c->kappa_over_g = pow10_(tp[0]) / pl.g_nom; break;
-        case 1: c->g1 = pow10_(tp[1]); break;
-        case 2: c->g2 = pow10_(tp[2]); break;
-        default: {
-            c->alpha = tp[3];
-            const double tirr = tp[4] * sqrt(pl.rstar_cm / (2.0 * pl.a_cm)) * pl.tstar;
-            c->tirr4 = (tirr * tirr) * (tirr * tirr);
-            c->tint4 = (pl.tint * pl.tint) * (pl.tint * pl.tint);
-        }
-    }
-}
-
 __host__ __device__ inline Line2013Consts line2013_consts(const double* tp, const bm_planet& pl) {
     Line2013Consts c;
     c.kappa_over_g = pow10_(tp[0]) / pl.g_nom;

@@ -46,6 +46,26 @@ __global__ void __launch_bounds__(256)
     if (threadIdx.x == 0) chi2[b] = cp[0];
 }
 
+// The same sum for a single-segment plan, from plain pointers: sample b's n partials
+// start at part + b * stride (doubles). Each wave sums its lanes' partials with shuffles
+// (a fixed tree, so the result does not depend on timing), then one thread adds the
+// waves' sums in order.
+__global__ void __launch_bounds__(256)
+    k_chi2_sum(const double* __restrict__ part, size_t stride, int n, const int32_t* __restrict__ active,
+               double* __restrict__ chi2) {
+    __shared__ double ws[4];
+    const int b = blockIdx.x;
+    const double* p = part + (size_t)b * stride;
+    double v = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) v += p[i];
+    if (active && !active[b]) return;
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    if ((threadIdx.x & (kWave - 1)) == 0) ws[threadIdx.x / kWave] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) chi2[b] = ((ws[0] + ws[1]) + ws[2]) + ws[3];
+}
+
 // ---------------------------------------------------------------------------------------
 // standalone step kernels (a3, a4, a5, a6)
 // ---------------------------------------------------------------------------------------
@@ -390,8 +410,25 @@ static int launch_forward(const HostPlan& hp, int cfg, const double* params, int
         // Segment offsets inside a plan are absolute (workspace, depth, binned); sample
         // indices are relative to the plan, so params/flags/chi2 are shifted here.
         const int32_t* act = active ? active + b0 : nullptr;
-        hipLaunchKernelGGL((k_atm_prep<T>), dim3(nb, prep_slices(hp, nb)), dim3(kAtmThreads), 0, st, lp,
-                           params + (size_t)b0 * stride, stride, act, ws, flags + b0);
+        {
+            // one run of samples: its model moves to slot 0 (fixed argument offsets)
+            LaunchPlan lp1 = lp;
+            const bool single = lp.n_seg == 1;
+            if (single) {
+                lp1.model[0] = lp.model[lp.seg[0].model];
+                lp1.seg[0].model = 0;
+            }
+            const dim3 grid(nb, prep_slices(hp, nb));
+            const double* pp = params + (size_t)b0 * stride;
+            if (single && act)
+                hipLaunchKernelGGL((k_atm_prep<T, true, true>), grid, dim3(kAtmThreads), 0, st, lp1, pp, stride, act, ws, flags + b0);
+            else if (single)
+                hipLaunchKernelGGL((k_atm_prep<T, true, false>), grid, dim3(kAtmThreads), 0, st, lp1, pp, stride, act, ws, flags + b0);
+            else if (act)
+                hipLaunchKernelGGL((k_atm_prep<T, false, true>), grid, dim3(kAtmThreads), 0, st, lp1, pp, stride, act, ws, flags + b0);
+            else
+                hipLaunchKernelGGL((k_atm_prep<T, false, false>), grid, dim3(kAtmThreads), 0, st, lp1, pp, stride, act, ws, flags + b0);
+        }
         BM_CHECK_HIP(hipGetLastError());
         double* c2 = chi2 ? chi2 + b0 : nullptr;
         hipEvent_t e0, e1;
@@ -415,7 +452,16 @@ static int launch_forward(const HostPlan& hp, int cfg, const double* params, int
         if (c2 && binned) {
             bool any_fused = false;
             for (int si = 0; si < lp.n_seg; ++si) any_fused |= lp.seg[si].fused_bins != 0;
-            if (any_fused) {
+            if (any_fused && lp.n_seg == 1) {
+                // records are rec_bytes apart; the partials sit at a fixed offset in each
+                const Segment& sg = lp.seg[0];
+                const ModelDev& m = lp.model[sg.model];
+                const char* base = ws + sg.ws_off;
+                const double* part0 = RecordView<T>(const_cast<char*>(base), m.S, m.L).chi2part;
+                hipLaunchKernelGGL(k_chi2_sum, dim3(nb), dim3(256), 0, st, part0, sg.rec_bytes / sizeof(double),
+                                   sg.tiles, act, c2);
+                BM_CHECK_HIP(hipGetLastError());
+            } else if (any_fused) {
                 hipLaunchKernelGGL((k_chi2_reduce<T>), dim3(nb), dim3(256), 0, st, lp, ws, act, c2);
                 BM_CHECK_HIP(hipGetLastError());
             }

@@ -104,17 +104,6 @@ __device__ __forceinline__ int es_index(int l, int c) {
     return l * kTileNu + c;
 }
 
-// broadcast lane `i` (uniform) of a per-lane value to the whole wave (v_readlane)
-__device__ __forceinline__ int lane_get(int v, int i) { return __builtin_amdgcn_readlane(v, i); }
-__device__ __forceinline__ float lane_get(float v, int i) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), i));
-}
-__device__ __forceinline__ double lane_get(double v, int i) {
-    const long long u = __builtin_bit_cast(long long, v);
-    const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffLL), i);
-    const int hi = __builtin_amdgcn_readlane((int)(u >> 32), i);
-    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
-}
 
 typedef __attribute__((address_space(3))) void* lds_void_ptr;
 
