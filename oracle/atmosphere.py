@@ -136,12 +136,13 @@ def atmosphere(params: np.ndarray, p_bar: np.ndarray, mass_amu: np.ndarray, tp_m
         temp = temperature_line2013(p_bar, params[:5], planet)
     if not (np.all(np.isfinite(temp)) and np.all(temp > 0.0)):
         flags |= FLAG_NONFINITE
-    x, x_h2, _x_he, mu, f = composition(params[ntp:ntp + S], mass_amu, planet)
+    x, x_h2, x_he, mu, f = composition(params[ntp:ntp + S], mass_amu, planet)
     flags |= f
     n = number_density(p_bar, temp)
     n_species = x[:, None] * n[None, :]
     n_h2 = x_h2 * n
+    n_he = x_he * n
     r, f = radii(p_bar, temp, mu, params[ntp + S] * R_JUP_CM, planet)
     flags |= f
-    return dict(temp=temp, n_species=n_species, n_h2=n_h2, radius=r, mu=mu, x=x,
+    return dict(temp=temp, n_species=n_species, n_h2=n_h2, n_he=n_he, radius=r, mu=mu, x=x,
                 x_h2=x_h2, flags=flags)

@@ -29,11 +29,15 @@ def interp_index(t_grid: np.ndarray, temp: float):
 
 def extinction(sigma: np.ndarray, t_grid: np.ndarray, temp: np.ndarray, n_species: np.ndarray,
                cia: np.ndarray | None = None, cia_t_grid: np.ndarray | None = None,
-               n_h2: np.ndarray | None = None):
+               n_h2: np.ndarray | None = None, cia_he: np.ndarray | None = None,
+               n_he: np.ndarray | None = None):
     """Step a3. sigma[S][NT][L][Nnu] in cm^2/molecule on the layer pressures;
     e_l(nu) = sum_i n_{i,l} sigma_i(T_l, p_l, nu)
-              + n_{H2,l}^2 K(T_l, nu)            (CIA, cm^5 molecule^-2)
-    with sigma and K interpolated linearly in T. Returns (e[L][Nnu], flags)."""
+              + n_{H2,l}^2 K(T_l, nu)            (H2-H2 CIA, cm^5 molecule^-2)
+              + n_{H2,l} n_{He,l} K_He(T_l, nu)  (H2-He CIA, when given; Sec. 3 and the
+                                                  HITRAN CIA source the paper cites)
+    with sigma and the CIA coefficients interpolated linearly in T (both CIA tables on
+    the same temperature grid). Returns (e[L][Nnu], flags)."""
     S, NT, L, NNU = sigma.shape
     e = np.zeros((L, NNU), dtype=np.float64)
     flags = 0
@@ -52,6 +56,10 @@ def extinction(sigma: np.ndarray, t_grid: np.ndarray, temp: np.ndarray, n_specie
             c_lo = cia[kc].astype(np.float64)
             c_hi = cia[kc + 1].astype(np.float64)
             e[l] += n_h2[l] ** 2 * ((1.0 - wc) * c_lo + wc * c_hi)
+            if cia_he is not None:
+                h_lo = cia_he[kc].astype(np.float64)
+                h_hi = cia_he[kc + 1].astype(np.float64)
+                e[l] += n_h2[l] * n_he[l] * ((1.0 - wc) * h_lo + wc * h_hi)
     return e, flags
 
 
@@ -134,14 +142,15 @@ def chi_squared(model: np.ndarray, data: np.ndarray, err: np.ndarray) -> float:
 
 
 def forward(params: np.ndarray, setup, sigma: np.ndarray, cia: np.ndarray | None = None,
-            data: np.ndarray | None = None, err: np.ndarray | None = None):
+            data: np.ndarray | None = None, err: np.ndarray | None = None,
+            cia_he: np.ndarray | None = None):
     """Steps a1-a6 for one parameter vector. Returns a dict with the spectrum, the
     intermediate arrays, binned depths and chi^2 (when data are given), and flags.
     A sample whose radii are invalid gets a NaN spectrum."""
     atm = atmosphere(params, setup.p_bar, setup.mass_amu, setup.tp_mode, setup.planet)
     flags = atm["flags"]
     ext, f = extinction(sigma, setup.temps, atm["temp"], atm["n_species"],
-                        cia, setup.cia_temps, atm["n_h2"])
+                        cia, setup.cia_temps, atm["n_h2"], cia_he, atm["n_he"])
     flags |= f
     if getattr(setup, "rayleigh", False):
         ext = ext + atm["n_h2"][:, None] * rayleigh_h2(setup.nu)[None, :]

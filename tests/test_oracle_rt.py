@@ -339,3 +339,53 @@ def test_cloud_deck_limits_and_monotonicity():
         d = rt.transit_depth(r, tau, PL.rs_cm, cloud_index=jc)
         assert np.all(d >= prev - 1e-18)
         prev = d
+
+
+def _helium_case(h2_frac, seed=3):
+    """A small isothermal atmosphere with the given H2 share of the filler gas."""
+    import dataclasses
+    pl = dataclasses.replace(wl.Planet(), h2_frac=h2_frac)
+    p_bar = wl.layer_pressures(12)
+    mass = wl.ABSORBER_MASS_AMU[:2].copy()
+    a = atm.atmosphere(np.array([1300.0, -3.0, -4.0, 1.1]), p_bar, mass, 0, pl)
+    temps = np.linspace(500.0, 3000.0, 6)
+    nu = np.linspace(1000.0, 9000.0, 40)
+    g = np.random.default_rng(seed)
+    sigma = g.uniform(1e-24, 1e-22, size=(2, temps.size, p_bar.size, nu.size))
+    return a, temps, nu, sigma
+
+
+def test_h2he_cia_vanishes_without_helium():
+    # an all-H2 filler has n_He = 0: the H2-He term adds nothing
+    a, temps, nu, sigma = _helium_case(1.0)
+    k1, k2 = wl.cia_table(temps, nu), wl.cia_he_table(temps, nu)
+    e0, _ = rt.extinction(sigma, temps, a["temp"], a["n_species"], k1, temps, a["n_h2"])
+    e1, _ = rt.extinction(sigma, temps, a["temp"], a["n_species"], k1, temps, a["n_h2"], k2, a["n_he"])
+    assert np.all(a["n_he"] == 0.0) and np.array_equal(e0, e1)
+
+
+def test_h2he_cia_at_equal_filler_shares_is_the_h2h2_form():
+    # with H2:He = 1:1 the densities agree, n_H2 n_He = n_H2^2, so the H2-He term with
+    # table K equals the (separately pinned) H2-H2 term with the same table
+    a, temps, nu, sigma = _helium_case(0.5)
+    np.testing.assert_allclose(a["n_he"], a["n_h2"], rtol=1e-15)
+    k2 = wl.cia_he_table(temps, nu)
+    zero = np.zeros_like(k2)
+    e_he, _ = rt.extinction(sigma, temps, a["temp"], a["n_species"], zero, temps, a["n_h2"], k2, a["n_he"])
+    e_hh, _ = rt.extinction(sigma, temps, a["temp"], a["n_species"], k2, temps, a["n_h2"])
+    np.testing.assert_allclose(e_he, e_hh, rtol=1e-14)
+
+
+def test_cia_tables_combine_into_one_h2h2_table():
+    # n_He / n_H2 = (1 - h) / h in every layer, so both CIA terms equal one H2-H2 term
+    # with the table K_H2H2 + ((1 - h) / h) K_H2He
+    h = 0.85
+    a, temps, nu, sigma = _helium_case(h)
+    np.testing.assert_allclose(a["n_he"] / a["n_h2"], (1 - h) / h, rtol=1e-14)
+    k1, k2 = wl.cia_table(temps, nu), wl.cia_he_table(temps, nu)
+    e_sep, _ = rt.extinction(sigma, temps, a["temp"], a["n_species"], k1, temps, a["n_h2"], k2, a["n_he"])
+    e_one, _ = rt.extinction(sigma, temps, a["temp"], a["n_species"], k1 + (1 - h) / h * k2, temps, a["n_h2"])
+    np.testing.assert_allclose(e_sep, e_one, rtol=1e-13)
+    # and the H2-He term is not negligible in the band it covers
+    e_hh, _ = rt.extinction(sigma, temps, a["temp"], a["n_species"], k1, temps, a["n_h2"])
+    assert np.max((e_sep - e_hh) / e_hh) > 1e-3

@@ -97,6 +97,16 @@ def cia_table(temps: np.ndarray, nu: np.ndarray) -> np.ndarray:
     return 1e-45 * np.sqrt(t / 1000.0) * band + 1e-48
 
 
+def cia_he_table(temps: np.ndarray, nu: np.ndarray) -> np.ndarray:
+    """Smooth synthetic H2-He CIA coefficient [NTc][Nnu] in cm^5 molecule^-2: one broad
+    band below the H2 fundamental, growing as T^0.7, plus a floor. A stand-in for the
+    HITRAN H2-He table."""
+    t = np.asarray(temps, dtype=np.float64)[:, None]
+    v = np.asarray(nu, dtype=np.float64)[None, :]
+    band = np.exp(-((v - 3800.0) / 900.0) ** 2)
+    return 4e-46 * (t / 1000.0) ** 0.7 * band + 5e-49
+
+
 def random_opacity_table(n_species: int, temps: np.ndarray, n_layers: int, nu: np.ndarray,
                          seed: int, line_density: float = 0.02, dtype=np.float64) -> np.ndarray:
     """Cross-section table [S][NT][L][Nnu] (cm^2/molecule) with line-like spikes on a
