@@ -156,6 +156,16 @@ int bm_atmosphere(const bm_model* model, const double* params, int param_stride,
 int bm_extinction(const bm_model* model, const double* temp, const double* n_species,
                   const double* n_h2, void* ext, int32_t* flags, void* stream);
 
+/* ---- a3 (model setup): H2-He collision-induced absorption ------------------------------
+ * Sec. 3 (CIA opacity sources): with the filler gas split H2:He in a fixed ratio h : 1 - h,
+ * n_He = ((1 - h) / h) n_H2 in every layer, so the H2-He term n_H2 n_He K_He joins the
+ * H2-H2 term as one table:
+ *   out[i] = k_h2h2[i] + ratio * k_h2he[i],   ratio = (1 - h) / h,
+ * to be passed as bm_model.cia (both tables on the same temperature grid). Device
+ * doubles of n elements; out may alias k_h2h2. Asynchronous on `stream`. */
+int bm_cia_combine(const double* k_h2h2, const double* k_h2he, double ratio, int64_t n, double* out,
+                   void* stream);
+
 /* ---- a4: chord optical depth ---------------------------------------------------------
  * Sec. 6.1 (slant path lengths through the layers at several altitudes): impact
  * parameters b_j = radius[j]; trapezoid in path length along both chord halves,

@@ -86,7 +86,10 @@ class Model:
                  cia: torch.Tensor | None = None, cia_temps=None, bin_width: int = 0,
                  data=None, err=None, device="cuda", tau_max: float = 0.0,
                  nu_start: float = 0.0, dnu: float = 0.0, rayleigh: bool = False,
-                 cloud: bool = False):
+                 cloud: bool = False, cia_he: torch.Tensor | None = None):
+        """cia_he: an H2-He CIA table on the CIA temperature grid; it is folded into the
+        H2-H2 table once here (bm_cia_combine), since n_He / n_H2 is fixed by the filler
+        split."""
         if sigma.dim() != 4:
             raise BartmiError("sigma must be [S][NT][L][Nnu]")
         self.sigma = sigma.to(device).contiguous()
@@ -96,6 +99,17 @@ class Model:
         self.p_bar = _dev(p_bar, device=device)
         # CIA coefficients (~1e-45 cm^5/molecule^2) are kept in double whatever the dtype
         self.cia = None if cia is None else _dev(cia, device=device)
+        if cia_he is not None:
+            if self.cia is None:
+                raise BartmiError("an H2-He CIA table needs the H2-H2 table and its temperature grid")
+            he = _dev(cia_he, device=device)
+            if tuple(he.shape) != tuple(self.cia.shape):
+                raise BartmiError("the CIA tables must share the temperature and wavenumber grids")
+            h = float(planet.h2_frac)
+            combined = torch.empty_like(self.cia)
+            _check(lib().bm_cia_combine(_ptr(self.cia), _ptr(he), (1.0 - h) / h if h > 0 else 0.0,
+                                        self.cia.numel(), _ptr(combined), _stream(None)), "bm_cia_combine")
+            self.cia = combined
         self.cia_temps = None if cia_temps is None else _dev(cia_temps, device=device)
         self.data = None if data is None else _dev(data, device=device)
         self.err = None if err is None else _dev(err, device=device)

@@ -64,6 +64,7 @@ PROTOTYPES = {
     "bm_status_string": (C.c_char_p, [_I]),
     "bm_version": (_I, []),
     "bm_struct_size": (C.c_size_t, [_I]),
+    "bm_cia_combine": (_I, [C.c_void_p, C.c_void_p, C.c_double, C.c_int64, C.c_void_p, C.c_void_p]),
     "bm_n_params": (_I, [_PM]),
     "bm_atmosphere": (_I, [_PM, _VP, _I, _I, _VP, _VP, _VP, _VP, _VP, _VP]),
     "bm_extinction": (_I, [_PM, _VP, _VP, _VP, _VP, _VP, _VP]),

@@ -273,19 +273,27 @@ __global__ void __launch_bounds__(kAtmThreads)
     const int L = m.L;
     RecordView<T> rec(ws + sg.ws_off + (size_t)(b - sg.first) * sg.rec_bytes, m.S, L);
     // slice 0 writes the per-layer record fields: interpolation brackets (temperature and
-    // CIA grids) and density factors, by the helper threads while the radii are solved
+    // CIA grids), then density factors, by the helper threads while the radii are solved
     // (or by the layer's own thread afterwards when there are no helpers)
     AtmSample a;
     int k = 0, kc = 0, fl = 0;
     double w = 0.0, wc = 0.0;
     auto fields = [&](int phase, int l) {
         if (slice != 0) return;
-        const double t = sh.temp[l];
         if (phase == 0) {
-            if (bracket_search(sh.tgrid, m.NT, t, &k, &w)) fl |= BM_FLAG_T_CLAMP;
+            // both searches back to back, with no branch between them, so that their
+            // dependent read chains overlap (without CIA the second repeats the first)
+            const double t = sh.temp[l];
+            const bool c1 = bracket_search(sh.tgrid, m.NT, t, &k, &w);
+            int kc2;
+            double wc2;
+            const bool c2 = bracket_search(cia ? sh.tgrid_cia : sh.tgrid, cia ? m.NTc : m.NT, t, &kc2, &wc2);
+            if (c1 || (cia && c2)) fl |= BM_FLAG_T_CLAMP;
+            if (cia) {
+                kc = kc2;
+                wc = wc2;
+            }
         } else if (phase == 1) {
-            if (cia && bracket_search(sh.tgrid_cia, m.NTc, t, &kc, &wc)) fl |= BM_FLAG_T_CLAMP;
-        } else {
             rec.kidx[l] = k;
             rec.kcidx[l] = kc;
             rec.w[l] = (T)w;
@@ -293,6 +301,7 @@ __global__ void __launch_bounds__(kAtmThreads)
             const double nh2 = a.x_h2 * sh.ndens[l];
             rec.bfac[l] = nh2 * nh2;
             rec.rfac[l] = (T)nh2;
+        } else {
 #pragma unroll
             for (int i = 0; i < BM_MAX_SPECIES; ++i)
                 if (i < m.S) rec.afac[i * L + l] = (T)(a.x[i] * sh.ndens[l]);

@@ -31,11 +31,13 @@ constexpr int kWave = 64;
 
 // ---- E2 exponential integral -------------------------------------------------------------
 // x <= 2.5: E2 = e^-x - x E1, E1 by its power series (Abramowitz & Stegun 5.1.11),
-//           E1(x) = -gamma - ln x - sum_{k>=1} (-x)^k / (k k!), 24 terms in Horner form;
+//           E1(x) = -gamma - ln x - sum_{k>=1} (-x)^k / (k k!), 24 terms;
 // x >  2.5: E2 by the even continued fraction (A&S 5.1.22),
 //           E2 = e^-x / (x + 2 - 1*2 / (x + 4 - 2*3 / (x + 6 - ...))),
 //           through its convergents P_n / Q_n (three-term recurrence, one division) at
-//           depth 8 + 75/x (about 1e-14 relative).
+//           a fixed depth of 39, at least what 8 + 75/x (about 1e-14 relative) asks for at the
+//           smallest x = 2.5: every larger x has converged further, and a loop of the
+//           same length on every lane needs no per-lane exit tests.
 struct E1SeriesCoef {
     double c[24];  // c[k-1] = (-1)^k / (k k!)
     constexpr E1SeriesCoef() : c() {
@@ -51,20 +53,37 @@ struct E1SeriesCoef {
 __host__ __device__ inline double expint_e2_ex(double x, double ex) {
     if (x <= 0.0) return 1.0;
     if (x <= 2.5) {
+        // the polynomial sum_{k<24} c_k x^k as its even and odd parts in x^2, two
+        // independent Horner chains of 12 steps
         constexpr E1SeriesCoef cs;
-        double s = cs.c[23];
-        for (int k = 22; k >= 0; --k) s = fma(s, x, cs.c[k]);
-        s *= x;  // sum_{k>=1} c_k x^k
+        const double x2 = x * x;
+        double se = cs.c[22], so = cs.c[23];
+        for (int k = 20; k >= 0; k -= 2) {
+            se = fma(se, x2, cs.c[k]);
+            so = fma(so, x2, cs.c[k + 1]);
+        }
+        const double s = x * fma(so, x, se);  // sum_{k>=1} c_k x^k
         double e1 = -kEulerGamma - log(x) - s;
         return ex - x * e1;
     }
-    // denominator b_1 - a_2/(b_2 - a_3/(...)), b_m = x + 2m, a_m = (m-1) m
-    const int depth = 8 + (int)(75.0 / x);
-    double p0 = 1.0, p1 = x + 2.0, q0 = 0.0, q1 = 1.0;
-    for (int m = 2; m <= depth; ++m) {
-        const double bm = x + 2.0 * m, am = (double)(m - 1) * m;
-        const double p2 = bm * p1 - am * p0, q2 = bm * q1 - am * q0;
-        p0 = p1; p1 = p2; q0 = q1; q1 = q2;
+    // denominator b_1 - a_2/(b_2 - a_3/(...)), b_m = x + 2m, a_m = (m-1) m, with the
+    // recurrence P_m = b_m P_{m-1} - a_m P_{m-2} (same for Q) software-pipelined: the term
+    // a_{m+1} P_{m-1} of the next step is formed alongside step m, so one multiply-add per
+    // step lies on the dependent chain
+    constexpr int kDepth = 39;  // 38 steps (an even count for the unrolled loop)
+    double p1 = x + 2.0, q1 = 1.0;  // P_1, Q_1
+    double tp = -2.0, tq = 0.0;     // -a_2 P_0, -a_2 Q_0 (P_0 = 1, Q_0 = 0)
+    double bm = x + 2.0;            // b_{m-1}; b_m = b_{m-1} + 2
+    double an = 2.0;                // a_m; a_{m+1} = a_m + 2 m (exact in double)
+#pragma unroll 2
+    for (int m = 2; m <= kDepth; ++m) {
+        bm += 2.0;
+        an += 2.0 * m;
+        const double p2 = fma(bm, p1, tp), q2 = fma(bm, q1, tq);
+        tp = -an * p1;
+        tq = -an * q1;
+        p1 = p2;
+        q1 = q2;
     }
     return ex * q1 / p1;
 }

@@ -3,6 +3,8 @@
 // standalone step kernels, the autotuner and the kernel-timing hook.
 #include "fwd_kernel.h"
 
+#include <algorithm>
+#include <cmath>
 #include <map>
 #include <mutex>
 #include <string>
@@ -591,6 +593,27 @@ extern "C" int bm_extinction(const bm_model* model, const double* temp, const do
     else
         hipLaunchKernelGGL(k_extinction<double>, grid, dim3(256), 0, (hipStream_t)stream, m, temp, n_species,
                            n_h2, (double*)ext, flags);
+    BM_CHECK_HIP(hipGetLastError());
+    return BM_OK;
+}
+
+namespace bm {
+__global__ void k_cia_combine(const double* __restrict__ a, const double* __restrict__ b, double r, int64_t n,
+                              double* out) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = a[i] + r * b[i];
+}
+}  // namespace bm
+
+extern "C" int bm_cia_combine(const double* k_h2h2, const double* k_h2he, double ratio, int64_t n, double* out,
+                              void* stream) {
+    using namespace bm;
+    if (n < 0) return BM_ESHAPE;
+    if (n == 0) return BM_OK;
+    if (!k_h2h2 || !k_h2he || !out || !std::isfinite(ratio) || ratio < 0.0) return BM_EINVAL;
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_cia_combine, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, k_h2h2, k_h2he,
+                       ratio, n, out);
     BM_CHECK_HIP(hipGetLastError());
     return BM_OK;
 }

@@ -24,7 +24,7 @@ def config1_table(n_nu=1000, seed=12):
     return s, sigma
 
 
-def gpu_model(setup, sigma, cia=None, data=None, err=None, device="cuda"):
+def gpu_model(setup, sigma, cia=None, data=None, err=None, device="cuda", cia_he=None):
     import torch
     import paper_2104_12522_amd as bm
     return bm.Model(torch.as_tensor(sigma), setup.temps, setup.p_bar, setup.mass_amu,
@@ -34,7 +34,8 @@ def gpu_model(setup, sigma, cia=None, data=None, err=None, device="cuda"):
                     bin_width=setup.bin_width, data=data, err=err, device=device,
                     tau_max=setup.tau_max, nu_start=float(setup.nu[0]),
                     dnu=float(setup.nu[1] - setup.nu[0]) if setup.nu.size > 1 else 1.0,
-                    rayleigh=setup.rayleigh, cloud=setup.cloud)
+                    rayleigh=setup.rayleigh, cloud=setup.cloud,
+                    cia_he=None if cia_he is None else torch.as_tensor(cia_he))
 
 
 def prior_for(setup):

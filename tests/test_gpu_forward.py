@@ -415,3 +415,37 @@ def test_extinction_step_rayleigh():
     ext_ref = ext_ref + atm["n_h2"][:, None] * ort.rayleigh_h2(s.nu)[None, :]
     ext, _ = bm.extinction(model, atm["temp"], atm["n_species"], atm["n_h2"])
     np.testing.assert_allclose(_np(ext), ext_ref, rtol=1e-12)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_fused_h2he_cia(dtype):
+    # H2-H2 and H2-He CIA (Sec. 3): the library folds the H2-He table into the H2-H2 one
+    # (the filler split fixes n_He / n_H2); the oracle adds the two terms layer by layer
+    s, sigma, cia = small_config2(n_nu=400, n_layers=60, seed=81)
+    if dtype == "f64":
+        sigma, rtol = sigma.astype(np.float64), 1e-10
+    else:
+        rtol = 1e-4
+    cia_he = wl.cia_he_table(s.cia_temps, s.nu)
+    params = prior_for(s).draw(4, seed=82)
+    model = gpu_model(s, sigma, cia, cia_he=cia_he)
+    f = bm.forward_batch(model, torch.as_tensor(params, device="cuda"))
+    torch.cuda.synchronize()
+    for b, th in enumerate(params):
+        ref = ort.forward(th, s, sigma.astype(np.float64), cia.astype(np.float64), cia_he=cia_he)
+        ref0 = ort.forward(th, s, sigma.astype(np.float64), cia.astype(np.float64))
+        assert int(f.flags[b]) == ref["flags"]
+        np.testing.assert_allclose(_np(f.spectrum(b)), ref["depth"], rtol=rtol, err_msg=f"sample {b}")
+        assert np.max(ref["depth"] - ref0["depth"]) > 0      # the H2-He term is visible
+
+
+def test_cia_combine_entry_point():
+    g = np.random.default_rng(9)
+    a, b = g.uniform(1e-48, 1e-45, 1000), g.uniform(1e-48, 1e-45, 1000)
+    ta, tb = torch.as_tensor(a, device="cuda"), torch.as_tensor(b, device="cuda")
+    out = torch.empty_like(ta)
+    lib = bm.lib()
+    assert lib.bm_cia_combine(bm._ptr(ta), bm._ptr(tb), 0.15 / 0.85, 1000, bm._ptr(out), bm._stream()) == 0
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(_np(out), a + (0.15 / 0.85) * b, rtol=1e-15)
+    assert lib.bm_cia_combine(bm._ptr(ta), bm._ptr(tb), float("nan"), 1000, bm._ptr(out), bm._stream()) != 0
