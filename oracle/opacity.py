@@ -5,10 +5,14 @@ on the output wavenumber grid at the atmosphere's layer pressures and over a gri
 temperatures (Sec. 3, Sec. 4); each line is a Voigt profile (Sec. 6.1.1, Eqs. 2-11)
 point-sampled at the output wavenumbers rather than bin-averaged (Sec. 4).
 
-This oracle evaluates the Voigt profile of every line at every grid point inside
-its cutoff window, directly from the Faddeeva function (scipy.special.wofz, the
-routine BARTTest itself compares against, Sec. 6.1.1), with no profile table,
-no strength summing and no strength cutoff.
+The direct mode evaluates the Voigt profile of every line at every grid point inside
+its cutoff window from the Faddeeva function (scipy.special.wofz, the routine BARTTest
+itself compares against, Sec. 6.1.1), with no profile table, no strength summing and no
+strength cutoff. The profile-table mode follows the paper's own procedure (Sec. 4 items
+4-6): a precomputed table of profiles over a grid of Doppler and Lorentz widths, finely
+sampled and aligned to the output grid, the nearest profile shifted by a whole number of
+fine samples to each line centre, strengths of lines that share profile and shift summed
+before broadening, and a strength threshold relative to the strongest line.
 """
 from __future__ import annotations
 
@@ -124,3 +128,104 @@ def point_cross_section(lines, temp: float, p_bar: float, nu: float) -> float:
     d = nu - lines.nu0
     m = np.abs(d) <= CUTOFF_HWHM * hw
     return float(np.sum(s_t[m] * voigt(d[m], sig[m], gam[m])))
+
+
+# ---- the paper's profile-table mode (Sec. 4 items 4-6; Sec. 4, integer-shift sampling) ----
+# Widths and positions that decide an integer (profile node, shift, extent) are written with
+# the operation order the library uses, so that both sides take the same decisions.
+
+TWO_LN2 = 1.3862943611198906  # 2 ln 2
+
+
+def table_hwhm(sigma, gamma):
+    """Olivero-Longbothum Voigt HWHM, 0.5346 gamma + sqrt(0.2166 gamma^2 + 2 ln2 sigma^2)."""
+    return 0.5346 * gamma + np.sqrt(0.2166 * gamma * gamma + TWO_LN2 * sigma * sigma)
+
+
+def profile_table(sigma_nodes, gamma_nodes, dnu: float, oversample: int, cutoff_hwhm: float):
+    """Sec. 4 item 4: the 3D table of Voigt profiles. Profile (i, j) has Doppler width
+    sigma_i and Lorentz half width gamma_j; it is sampled oversample times per output
+    interval (fine step delta = dnu / oversample, so that the samples align with the
+    output grid) over t = -T..T fine steps, T = floor(cutoff_hwhm HWHM_ij / delta), and
+    stored in single precision. Returns dict(ext[i][j] = T, prof[(i, j)] = values at
+    t = -T..T, delta, oversample, sigma_nodes, gamma_nodes)."""
+    sigma_nodes = np.asarray(sigma_nodes, dtype=np.float64)
+    gamma_nodes = np.asarray(gamma_nodes, dtype=np.float64)
+    delta = dnu / oversample
+    ext = np.zeros((sigma_nodes.size, gamma_nodes.size), dtype=np.int64)
+    for i, s in enumerate(sigma_nodes):
+        for j, g in enumerate(gamma_nodes):
+            ext[i, j] = int(math.floor(cutoff_hwhm * table_hwhm(s, g) / delta))
+
+    class _Profiles(dict):
+        # the values of a profile are evaluated when first used
+        def __missing__(self, key):
+            i, j = key
+            t = np.arange(-ext[i, j], ext[i, j] + 1, dtype=np.float64)
+            val = voigt(t * delta, sigma_nodes[i], gamma_nodes[j]).astype(np.float32)
+            self[key] = val
+            return val
+
+    return dict(ext=ext, prof=_Profiles(), delta=delta, oversample=int(oversample), dnu=float(dnu),
+                sigma_nodes=sigma_nodes, gamma_nodes=gamma_nodes)
+
+
+def nearest_node(x, nodes):
+    """Index of the node closest to x in ratio (log) terms: the number of geometric
+    midpoints sqrt(n_i n_{i+1}) at or below x."""
+    nodes = np.asarray(nodes, dtype=np.float64)
+    mids = np.sqrt(nodes[:-1] * nodes[1:])
+    return np.searchsorted(mids, x, side="right")
+
+
+def table_line_parameters(lines, temp: float, p_bar: float):
+    """S(T), Doppler sigma and Lorentz gamma of every line, as in the direct mode."""
+    s_t = line_strength(lines.s296, lines.nu0, lines.elow, temp)
+    sig = lines.nu0 / C_LIGHT * np.sqrt(K_B * temp / (lines.mass_amu * M_U))
+    gam = lines.gamma296 * (p_bar / ATM_BAR) * np.sqrt(T_REF / temp)
+    return s_t, sig, gam
+
+
+def table_cell_cross_section(lines, temp: float, p_bar: float, nu_start: float, n_nu: int, table,
+                             strength_cutoff: float = 0.0) -> np.ndarray:
+    """One (T, p) cell in the profile-table mode:
+    - item 6: lines weaker than strength_cutoff times the strongest line at this T (and
+      p) are ignored;
+    - each remaining line takes the profile whose (sigma, gamma) nodes are nearest and
+      the integer fine shift s = rint((nu0 - nu_start) / delta) that best matches its
+      centre;
+    - item 5: lines with the same profile and shift have their strengths summed first;
+    - each group adds S P(k O - s) at the output points k with |k O - s| <= T."""
+    O = table["oversample"]
+    delta = table["delta"]
+    s_t, sig, gam = table_line_parameters(lines, temp, p_bar)
+    keep = s_t >= strength_cutoff * np.max(s_t) if s_t.size else np.zeros(0, bool)
+    isg = nearest_node(sig, table["sigma_nodes"])
+    igm = nearest_node(gam, table["gamma_nodes"])
+    shift = np.rint((lines.nu0 - nu_start) / delta).astype(np.int64)
+    groups = {}
+    for n in np.nonzero(keep)[0]:
+        key = (int(isg[n]), int(igm[n]), int(shift[n]))
+        groups[key] = groups.get(key, 0.0) + float(s_t[n])
+    out = np.zeros(n_nu, dtype=np.float64)
+    for (i, j, s), strength in groups.items():
+        t_max = int(table["ext"][i, j])
+        k_lo = max(0, -((t_max - s) // O))      # ceil((s - t_max) / O)
+        k_hi = min(n_nu - 1, (s + t_max) // O)   # floor((s + t_max) / O)
+        if k_hi < k_lo:
+            continue
+        k = np.arange(k_lo, k_hi + 1, dtype=np.int64)
+        vals = table["prof"][i, j][k * O - s + t_max].astype(np.float64)
+        out[k_lo:k_hi + 1] += strength * vals
+    return out
+
+
+def table_opacity(lines, temps, p_bar, nu_start: float, n_nu: int, table,
+                  strength_cutoff: float = 0.0) -> np.ndarray:
+    """The table-mode cross sections sigma[T][p][nu]."""
+    out = np.zeros((len(temps), len(p_bar), n_nu), dtype=np.float64)
+    for it, t in enumerate(temps):
+        for ip, p in enumerate(p_bar):
+            out[it, ip] = table_cell_cross_section(lines, float(t), float(p), nu_start, n_nu, table,
+                                                   strength_cutoff)
+    return out

@@ -153,3 +153,90 @@ def test_cell_matches_pointwise_sum():
     for k in range(0, nn, 13):
         assert cell[k] == pytest.approx(op.point_cross_section(ln, T, p, nu_start + dnu * k),
                                         rel=1e-12, abs=1e-300)
+
+
+# ---- profile-table mode (Sec. 4 items 4-6) ---------------------------------------------
+F04_T, F04_P = 1442.58, 0.33516      # the f04broadening layer (Sec. 6.1.1)
+
+
+def _widths(ln, T=F04_T, p=F04_P):
+    s_t, sig, gam = op.table_line_parameters(ln, T, p)
+    return float(s_t[0]), float(sig[0]), float(gam[0])
+
+
+def test_table_mode_line_on_node_and_sample_equals_direct():
+    # a line whose widths are grid nodes and whose centre is a fine sample: the table
+    # mode samples exactly the direct-mode profile (to single-precision storage)
+    ln = _single_line(nu0=2000.1)
+    _, sig, gam = _widths(ln)
+    tab = op.profile_table([sig / 2, sig, 2 * sig], [gam / 3, gam, 3 * gam], 0.005, 100, 25.0)
+    nu_start, n = 1990.0, 4001
+    got = op.table_cell_cross_section(ln, F04_T, F04_P, nu_start, n, tab)
+    ref = op.cell_cross_section(ln, F04_T, F04_P, nu_start, 0.005, n)
+    t_max = int(tab["ext"][1, 1])
+    s = int(np.rint((ln.nu0[0] - nu_start) / tab["delta"]))
+    t = np.arange(n) * 100 - s
+    core = np.abs(t) < t_max - 100
+    np.testing.assert_allclose(got[core], ref[core], rtol=2e-7)
+    assert np.all(got[np.abs(t) > t_max] == 0.0) and np.all(got[np.abs(t) <= t_max] > 0.0)
+
+
+def test_table_mode_translates_by_whole_output_intervals():
+    # moving the centre by one output interval moves the sampled profile by one point
+    a, b = _single_line(nu0=2000.1), _single_line(nu0=2000.105)
+    _, sig, gam = _widths(a)
+    tab = op.profile_table([sig], [gam], 0.005, 100, 25.0)
+    ga = op.table_cell_cross_section(a, F04_T, F04_P, 1990.0, 4001, tab)
+    gb = op.table_cell_cross_section(b, F04_T, F04_P, 1990.0, 4001, tab)
+    sa, sb = _widths(a)[0], _widths(b)[0]
+    np.testing.assert_allclose(gb[1:] / sb, ga[:-1] / sa, rtol=1e-15, atol=0)
+
+
+def test_table_mode_nearest_node_is_nearest_in_ratio():
+    nodes = np.array([1.0, 2.0, 4.0, 8.0])
+    x = np.array([0.5, 1.4, 1.42, 2.9, 2.8, 5.6, 5.7, 100.0])
+    # midpoints sqrt(2) = 1.414..., sqrt(8) = 2.828..., sqrt(32) = 5.657...
+    assert list(op.nearest_node(x, nodes)) == [0, 0, 1, 2, 1, 2, 3, 3]
+
+
+def test_table_mode_sums_coincident_strengths():
+    # item 5: lines sharing profile and shift act as one line with the summed strength
+    a = _single_line(nu0=2000.1, s=1e-20)
+    two = LineList(np.array([2000.1, 2000.1]), np.array([1e-20, 3e-21]), np.array([0.07, 0.07]),
+                   np.array([300.0, 300.0]), np.array([18.015, 18.015]))
+    one = _single_line(nu0=2000.1, s=1.3e-20)
+    _, sig, gam = _widths(a)
+    tab = op.profile_table([sig], [gam], 0.005, 100, 25.0)
+    g2 = op.table_cell_cross_section(two, F04_T, F04_P, 1990.0, 4001, tab)
+    g1 = op.table_cell_cross_section(one, F04_T, F04_P, 1990.0, 4001, tab)
+    np.testing.assert_allclose(g2, g1, rtol=1e-14, atol=0)
+
+
+def test_table_mode_strength_cutoff():
+    # item 6: lines below the threshold relative to the strongest line are ignored
+    strong, weak = _single_line(nu0=2000.1, s=1e-20), _single_line(nu0=2003.2, s=1e-23)
+    both = LineList(*(np.concatenate([getattr(strong, f), getattr(weak, f)])
+                      for f in ("nu0", "s296", "gamma296", "elow", "mass_amu")))
+    _, sig, gam = _widths(strong)
+    tab = op.profile_table([sig], [gam], 0.005, 100, 25.0)
+    args = (F04_T, F04_P, 1990.0, 4001, tab)
+    g_s = op.table_cell_cross_section(strong, *args)
+    g_w = op.table_cell_cross_section(weak, *args)
+    assert np.array_equal(op.table_cell_cross_section(both, *args, strength_cutoff=1e-2), g_s)
+    np.testing.assert_allclose(op.table_cell_cross_section(both, *args, strength_cutoff=1e-4), g_s + g_w,
+                               rtol=1e-15, atol=0)
+
+
+def test_table_mode_meets_the_f04_accuracy_bar():
+    # Sec. 6.1.1: with a 60 x 60 profile grid the table mode stays within 0.1 % of the
+    # directly evaluated profile; here the line's widths are nodes and its centre falls
+    # between fine samples (thousands per output interval), so only the shift rounds
+    ln = _single_line(nu0=2000.123456)
+    _, sig, gam = _widths(ln)
+    r = 1.05 ** np.arange(-30, 30)
+    tab = op.profile_table(sig * r, gam * r, 0.005, 2000, 25.0)
+    assert tab["sigma_nodes"][30] == sig and tab["gamma_nodes"][30] == gam
+    got = op.table_cell_cross_section(ln, F04_T, F04_P, 1999.0, 451, tab)
+    ref = op.cell_cross_section(ln, F04_T, F04_P, 1999.0, 0.005, 451)
+    big = ref > 1e-3 * ref.max()
+    assert np.max(np.abs(got[big] - ref[big]) / ref[big]) < 1e-3
