@@ -76,7 +76,7 @@ const char* bm_status_string(int status);
 int bm_version(void);
 
 /* sizeof of a structure of this header, for bindings to check their own layouts:
- * which = 0 bm_planet, 1 bm_model, 2 bm_demcz, 3 bm_mlp; 0 for any other value. */
+ * which = 0 bm_planet, 1 bm_model, 2 bm_demcz, 3 bm_mlp, 4 bm_voigt_grid; 0 for any other. */
 size_t bm_struct_size(int which);
 
 /* Fixed constants of a transmission model (host values, copied by every call).
@@ -253,6 +253,55 @@ int bm_forward_set_config(const bm_model* models, int n_models, const int32_t* i
  * the events. */
 int bm_timing_start(int capacity);
 int bm_timing_stop(double* total_ms, int64_t* launches);
+
+/* ---- opacity table build, profile-table mode (secondary path) ----------------------------
+ * Sec. 4 items 4-6 and the paragraph after them, Sec. 6.1.1 (a 60 x 60 grid of profiles in
+ * the f04 broadening test): the paper's own procedure.
+ * Profile table: profile (i, j) is V(t delta; sigma_i, gamma_j) for fine offsets
+ * t = -T..T, delta = dnu / oversample (samples aligned to the output grid),
+ * T = floor(cutoff_hwhm HWHM(sigma_i, gamma_j) / delta) with the Olivero-Longbothum HWHM,
+ * stored in single precision.
+ * Build: for every (T, p) cell, each line takes S(T) and its Doppler and Lorentz widths
+ * (as in bm_opacity_table_build), the nodes nearest its widths in ratio (geometric
+ * midpoints of neighbouring nodes decide), the shift s = rint((nu0 - nu_start) / delta),
+ * and is ignored when S(T) < strength_cutoff max_lines S(T) (S does not depend on p);
+ * runs of consecutive lines (in centre order) with the same profile and shift have their
+ * strengths summed before their profile is added; a line adds S P(k oversample - s) at
+ * the output points k with |k oversample - s| <= T, summed in double in line order.
+ * Node arrays are HOST doubles, strictly increasing and positive. */
+typedef struct bm_voigt_grid {
+    int32_t n_sigma;            /* Doppler-width nodes, 1..256                                   */
+    int32_t n_gamma;            /* Lorentz-width nodes, 1..256                                   */
+    int32_t oversample;         /* fine samples per output interval, 1..65536                    */
+    int32_t pad;
+    const double* sigma_nodes;  /* host [n_sigma], cm^-1                                         */
+    const double* gamma_nodes;  /* host [n_gamma], cm^-1                                         */
+    double dnu;                 /* output grid spacing (cm^-1) the profiles align to             */
+    double cutoff_hwhm;         /* profile half extent in Voigt HWHMs                            */
+} bm_voigt_grid;
+
+/* Bytes of the device profile table for this grid (header + profiles); 0 when the grid is
+ * invalid or the table would exceed 1.6e12 bytes. */
+size_t bm_voigt_table_bytes(const bm_voigt_grid* grid);
+/* Fills a caller-allocated device table of at least bm_voigt_table_bytes(grid) bytes: the
+ * header is copied synchronously (the call returns after that copy), the profile values
+ * are computed asynchronously on `stream`. */
+int bm_voigt_table_build(const bm_voigt_grid* grid, void* table, size_t table_bytes, void* stream);
+/* Bytes of the device workspace bm_opacity_table_build_profiles needs (0 if n_temp is out
+ * of range): per-temperature strongest lines and the widest-window inputs. */
+size_t bm_opacity_profiles_workspace(int n_temp);
+/* The table-mode cross sections. Line arrays as bm_opacity_table_build (device doubles,
+ * sorted by nu0); temp [n_temp] and p_bar [n_p] host doubles; grid and table as built by
+ * bm_voigt_table_build (the grid's dnu is the output spacing); strength_cutoff >= 0 (0
+ * keeps every line); sigma_out device [n_temp][n_p][n_nu] of dtype, every element written
+ * once; deterministic. */
+int bm_opacity_table_build_profiles(const double* nu0, const double* s296, const double* gamma296,
+                                    const double* elow, const double* mass_amu, int64_t n_lines,
+                                    const double* temp, int n_temp, const double* p_bar, int n_p,
+                                    double nu_start, int n_nu, const bm_voigt_grid* grid,
+                                    const void* table, double strength_cutoff, int dtype,
+                                    void* sigma_out, void* workspace, size_t workspace_bytes,
+                                    void* stream);
 
 /* ---- DE-MCz sampler with delayed acceptance ----------------------------------------------
  * Sec. 3 and Sec. 5: MC3's differential-evolution samplers (DEMC, ter Braak 2006; the

@@ -378,6 +378,56 @@ def opacity_table_build(lines, temps, p_bar, nu_start: float, dnu: float, n_nu: 
     return out
 
 
+class VoigtTable:
+    """The paper's 3D table of Voigt profiles on the device (bm_voigt_table_build): nodes of
+    Doppler and Lorentz widths (host arrays, strictly increasing), ``oversample`` fine
+    samples per output interval ``dnu``, each profile reaching ``cutoff_hwhm`` Voigt HWHMs."""
+
+    def __init__(self, sigma_nodes, gamma_nodes, dnu: float, oversample: int, cutoff_hwhm: float = 25.0,
+                 device="cuda", stream=None):
+        from ._abi import BmVoigtGrid
+        self.sigma_nodes = np.ascontiguousarray(np.asarray(sigma_nodes, dtype=np.float64))
+        self.gamma_nodes = np.ascontiguousarray(np.asarray(gamma_nodes, dtype=np.float64))
+        g = BmVoigtGrid()
+        g.n_sigma, g.n_gamma, g.oversample = self.sigma_nodes.size, self.gamma_nodes.size, int(oversample)
+        g.sigma_nodes = self.sigma_nodes.ctypes.data
+        g.gamma_nodes = self.gamma_nodes.ctypes.data
+        g.dnu, g.cutoff_hwhm = float(dnu), float(cutoff_hwhm)
+        self.grid = g
+        self.bytes = int(lib().bm_voigt_table_bytes(C.byref(g)))
+        if self.bytes == 0:
+            raise BartmiError("invalid Voigt profile grid")
+        self.table = torch.empty(self.bytes, dtype=torch.uint8, device=device)
+        _check(lib().bm_voigt_table_build(C.byref(g), _ptr(self.table), self.bytes, _stream(stream)),
+               "bm_voigt_table_build")
+
+
+def opacity_table_build_profiles(lines, temps, p_bar, nu_start: float, n_nu: int, table: VoigtTable,
+                                 strength_cutoff: float = 0.0, dtype=torch.float32, device="cuda",
+                                 out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Cross-section table [NT][NP][Nnu] in the paper's profile-table mode (Sec. 4 items 4-6):
+    nearest tabulated profile, integer fine shift, strengths of lines sharing profile and
+    shift summed, lines below strength_cutoff times the strongest ignored."""
+    arrs = [_dev(getattr(lines, f), device=device) for f in
+            ("nu0", "s296", "gamma296", "elow", "mass_amu")]
+    n = int(arrs[0].numel())
+    temps = np.ascontiguousarray(np.asarray(temps, dtype=np.float64))
+    p_bar = np.ascontiguousarray(np.asarray(p_bar, dtype=np.float64))
+    if out is None:
+        out = torch.empty(len(temps), len(p_bar), n_nu, dtype=dtype, device=device)
+    wsb = int(lib().bm_opacity_profiles_workspace(len(temps)))
+    if wsb == 0:
+        raise BartmiError("too many temperatures")
+    ws = torch.empty(wsb, dtype=torch.uint8, device=device)
+    dp = C.POINTER(C.c_double)
+    _check(lib().bm_opacity_table_build_profiles(
+        *[_ptr(a) for a in arrs], n, temps.ctypes.data_as(dp), len(temps), p_bar.ctypes.data_as(dp),
+        len(p_bar), C.c_double(nu_start), n_nu, C.byref(table.grid), _ptr(table.table),
+        C.c_double(strength_cutoff), _dtype_code(out.dtype), _ptr(out), _ptr(ws), wsb, _stream(stream)),
+        "bm_opacity_table_build_profiles")
+    return out
+
+
 def voigt(x: torch.Tensor, sigma: float, gamma: float, stream=None) -> torch.Tensor:
     x = _dev(x)
     out = torch.empty_like(x)

@@ -46,6 +46,14 @@ class BmDemcz(C.Structure):
     ]
 
 
+class BmVoigtGrid(C.Structure):
+    _fields_ = [
+        ("n_sigma", C.c_int32), ("n_gamma", C.c_int32), ("oversample", C.c_int32), ("pad", C.c_int32),
+        ("sigma_nodes", C.c_void_p), ("gamma_nodes", C.c_void_p), ("dnu", C.c_double),
+        ("cutoff_hwhm", C.c_double),
+    ]
+
+
 class BmMlp(C.Structure):
     _fields_ = [("n_layers", C.c_int32), ("max_batch", C.c_int32),
                 ("dims", C.c_int32 * (BM_MLP_MAX_LAYERS + 1))] + [
@@ -65,6 +73,12 @@ PROTOTYPES = {
     "bm_version": (_I, []),
     "bm_struct_size": (C.c_size_t, [_I]),
     "bm_cia_combine": (_I, [C.c_void_p, C.c_void_p, C.c_double, C.c_int64, C.c_void_p, C.c_void_p]),
+    "bm_voigt_table_bytes": (C.c_size_t, [C.c_void_p]),
+    "bm_voigt_table_build": (_I, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "bm_opacity_profiles_workspace": (C.c_size_t, [_I]),
+    "bm_opacity_table_build_profiles": (_I, [C.c_void_p] * 5 + [C.c_int64, C.c_void_p, _I, C.c_void_p, _I,
+                                             C.c_double, _I, C.c_void_p, C.c_void_p, C.c_double, _I,
+                                             C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
     "bm_n_params": (_I, [_PM]),
     "bm_atmosphere": (_I, [_PM, _VP, _I, _I, _VP, _VP, _VP, _VP, _VP, _VP]),
     "bm_extinction": (_I, [_PM, _VP, _VP, _VP, _VP, _VP, _VP]),

@@ -570,6 +570,7 @@ extern "C" size_t bm_struct_size(int which) {
         case 1: return sizeof(bm_model);
         case 2: return sizeof(bm_demcz);
         case 3: return sizeof(bm_mlp);
+        case 4: return sizeof(bm_voigt_grid);
         default: return 0;
     }
 }

@@ -8,107 +8,12 @@
 // Lorentz widths and window computed once per workgroup), and every lane sums the
 // profiles of the staged lines whose window contains its wavenumber, in double, in line
 // order. No atomics: each output element is written once, so results are deterministic.
-//
-// Faddeeva function (double precision, real part only):
-//   |z| >= 8   Laplace continued fraction of w(z), evaluated through its convergents
-//              P_m / Q_m (one division), 4-10 levels depending on |z|;
-//   |z| <  8   Weideman (1994) rational expansion with N = 40 terms, whose coefficients
-//              are computed on the host from the FFT (here a direct cosine sum) of
-//              (L^2 + t^2) exp(-t^2) sampled at t = L tan(theta / 2).
-#include "bm_internal.h"
-
-#include <vector>
+// The Faddeeva function is in voigt.h.
+#include "voigt.h"
 
 namespace bm {
 
-constexpr int kWeidemanN = 40;
 constexpr int kOpThreads = 256;
-
-struct WeidemanCoef {
-    double L;
-    double a[kWeidemanN];  // a_1 .. a_N
-};
-
-static WeidemanCoef weideman_coefficients() {
-    WeidemanCoef c{};
-    const int N = kWeidemanN;
-    const int M = 2 * N;
-    const double L = sqrt(N / sqrt(2.0));
-    c.L = L;
-    const double pi = 3.14159265358979323846;
-    std::vector<double> g(2 * M);
-    for (int m = 0; m < 2 * M; ++m) {
-        if (m == M) {
-            g[m] = 0.0;  // theta = pi, t = infinity
-            continue;
-        }
-        const double t = L * tan(0.5 * pi * m / M);
-        g[m] = exp(-t * t) * (L * L + t * t);
-    }
-    for (int n = 1; n <= N; ++n) {
-        double s = 0.0;
-        for (int m = 0; m < 2 * M; ++m) s += g[m] * cos(pi * (double)n * m / M);
-        c.a[n - 1] = s / (2.0 * M);
-    }
-    return c;
-}
-
-// Re w(x + i y), y > 0.
-__device__ __forceinline__ double faddeeva_re(double x, double y, const WeidemanCoef& wc) {
-    x = fabs(x);
-    const double r2 = x * x + y * y;
-    if (r2 >= 64.0) {
-        int n;
-        if (r2 >= 1600.0)
-            n = 4;
-        else if (r2 >= 225.0)
-            n = 6;
-        else if (r2 >= 100.0)
-            n = 8;
-        else
-            n = 10;
-        // convergents of 1/(z - (1/2)/(z - (2/2)/(z - ...))): h_m = z h_{m-1} - ((m-1)/2) h_{m-2}
-        // start: P_0 = 0, P_1 = 1; Q_0 = 1, Q_1 = z
-        double pr0 = 0.0, pi0 = 0.0, pr1 = 1.0, pi1 = 0.0;
-        double qr0 = 1.0, qi0 = 0.0, qr1 = x, qi1 = y;
-        for (int m = 2; m <= n + 1; ++m) {
-            const double am = -0.5 * (m - 1);
-            const double prn = x * pr1 - y * pi1 + am * pr0;
-            const double pin = x * pi1 + y * pr1 + am * pi0;
-            const double qrn = x * qr1 - y * qi1 + am * qr0;
-            const double qin = x * qi1 + y * qr1 + am * qi0;
-            pr0 = pr1; pi0 = pi1; pr1 = prn; pi1 = pin;
-            qr0 = qr1; qi0 = qi1; qr1 = qrn; qi1 = qin;
-        }
-        // w = (i / sqrt(pi)) P / Q ;  Re w = -Im(P / Q) / sqrt(pi)
-        const double den = qr1 * qr1 + qi1 * qi1;
-        const double im_ratio = (pi1 * qr1 - pr1 * qi1) / den;
-        return -im_ratio * 0.56418958354775628695;  // 1/sqrt(pi)
-    }
-    // Weideman: Z = (L + iz)/(L - iz), w = (2 p(Z) / (L - iz) + 1/sqrt(pi)) / (L - iz)
-    const double L = wc.L;
-    const double dr = L + y, di = -x;            // L - iz
-    const double dd = 1.0 / (dr * dr + di * di);
-    const double ir = dr * dd, ii = -di * dd;    // 1 / (L - iz)
-    const double nr = L - y, ni = x;             // L + iz
-    const double zr = nr * ir - ni * ii, zi = nr * ii + ni * ir;
-    double pr = wc.a[kWeidemanN - 1], pim = 0.0;
-#pragma unroll
-    for (int n = kWeidemanN - 2; n >= 0; --n) {
-        const double tr = pr * zr - pim * zi + wc.a[n];
-        const double ti = pr * zi + pim * zr;
-        pr = tr;
-        pim = ti;
-    }
-    // t = 2 p / (L - iz) + 1/sqrt(pi)
-    const double tr = 2.0 * (pr * ir - pim * ii) + 0.56418958354775628695;
-    const double ti = 2.0 * (pr * ii + pim * ir);
-    return tr * ir - ti * ii;
-}
-
-__device__ __forceinline__ double voigt_hwhm(double sig, double gam) {
-    return 0.5346 * gam + sqrt(0.2166 * gam * gam + 2.0 * 0.69314718055994530942 * sig * sig);
-}
 
 struct LineArrays {
     const double* nu0;
@@ -227,11 +132,6 @@ __global__ void k_voigt(const double* __restrict__ x, int64_t n, double sig, dou
     out[i] = faddeeva_re(x[i] * inv, gam * inv, wc) / (sig * 2.50662827463100050242);
 }
 
-static const WeidemanCoef& coef() {
-    static const WeidemanCoef c = weideman_coefficients();
-    return c;
-}
-
 }  // namespace bm
 
 using namespace bm;
@@ -243,7 +143,7 @@ extern "C" int bm_voigt(const double* x, int64_t n, double sigma, double gamma, 
     if (n == 0) return BM_OK;
     const int threads = 256;
     hipLaunchKernelGGL(k_voigt, dim3((unsigned)((n + threads - 1) / threads)), dim3(threads), 0,
-                       (hipStream_t)stream, x, n, sigma, gamma, coef(), out);
+                       (hipStream_t)stream, x, n, sigma, gamma, weideman(), out);
     BM_CHECK_HIP(hipGetLastError());
     return BM_OK;
 }
@@ -292,10 +192,10 @@ extern "C" int bm_opacity_table_build(const double* nu0, const double* s296, con
     dim3 grid((n_nu + kOpThreads - 1) / kOpThreads, n_temp * n_p);
     if (dtype == BM_F32)
         hipLaunchKernelGGL(k_opacity_gather<float>, grid, dim3(kOpThreads), 0, st, ln, cg, nu_start, dnu, n_nu,
-                           cutoff_hwhm, d_ext, coef(), (float*)sigma_out);
+                           cutoff_hwhm, d_ext, weideman(), (float*)sigma_out);
     else
         hipLaunchKernelGGL(k_opacity_gather<double>, grid, dim3(kOpThreads), 0, st, ln, cg, nu_start, dnu,
-                           n_nu, cutoff_hwhm, d_ext, coef(), (double*)sigma_out);
+                           n_nu, cutoff_hwhm, d_ext, weideman(), (double*)sigma_out);
     BM_CHECK_HIP(hipGetLastError());
     return BM_OK;
 }

@@ -1,0 +1,117 @@
+// Faddeeva function and Voigt helpers shared by the opacity builds (internal).
+//
+// Re w(z), double precision:
+//   |z| >= 8   Laplace continued fraction of w(z), evaluated through its convergents
+//              P_m / Q_m (one division), 4-10 levels depending on |z|;
+//   |z| <  8   Weideman (1994) rational expansion with N = 40 terms, whose coefficients
+//              are computed on the host from the FFT (here a direct cosine sum) of
+//              (L^2 + t^2) exp(-t^2) sampled at t = L tan(theta / 2).
+#pragma once
+
+#include <vector>
+
+#include "bm_internal.h"
+
+namespace bm {
+
+constexpr int kWeidemanN = 40;
+
+struct WeidemanCoef {
+    double L;
+    double a[kWeidemanN];  // a_1 .. a_N
+};
+
+inline WeidemanCoef weideman_coefficients() {
+    WeidemanCoef c{};
+    const int N = kWeidemanN;
+    const int M = 2 * N;
+    const double L = sqrt(N / sqrt(2.0));
+    c.L = L;
+    const double pi = 3.14159265358979323846;
+    std::vector<double> g(2 * M);
+    for (int m = 0; m < 2 * M; ++m) {
+        if (m == M) {
+            g[m] = 0.0;  // theta = pi, t = infinity
+            continue;
+        }
+        const double t = L * tan(0.5 * pi * m / M);
+        g[m] = exp(-t * t) * (L * L + t * t);
+    }
+    for (int n = 1; n <= N; ++n) {
+        double s = 0.0;
+        for (int m = 0; m < 2 * M; ++m) s += g[m] * cos(pi * (double)n * m / M);
+        c.a[n - 1] = s / (2.0 * M);
+    }
+    return c;
+}
+
+// Re w(x + i y), y > 0.
+__device__ __forceinline__ double faddeeva_re(double x, double y, const WeidemanCoef& wc) {
+    x = fabs(x);
+    const double r2 = x * x + y * y;
+    if (r2 >= 64.0) {
+        int n;
+        if (r2 >= 1600.0)
+            n = 4;
+        else if (r2 >= 225.0)
+            n = 6;
+        else if (r2 >= 100.0)
+            n = 8;
+        else
+            n = 10;
+        // convergents of 1/(z - (1/2)/(z - (2/2)/(z - ...))): h_m = z h_{m-1} - ((m-1)/2) h_{m-2}
+        // start: P_0 = 0, P_1 = 1; Q_0 = 1, Q_1 = z
+        double pr0 = 0.0, pi0 = 0.0, pr1 = 1.0, pi1 = 0.0;
+        double qr0 = 1.0, qi0 = 0.0, qr1 = x, qi1 = y;
+        for (int m = 2; m <= n + 1; ++m) {
+            const double am = -0.5 * (m - 1);
+            const double prn = x * pr1 - y * pi1 + am * pr0;
+            const double pin = x * pi1 + y * pr1 + am * pi0;
+            const double qrn = x * qr1 - y * qi1 + am * qr0;
+            const double qin = x * qi1 + y * qr1 + am * qi0;
+            pr0 = pr1; pi0 = pi1; pr1 = prn; pi1 = pin;
+            qr0 = qr1; qi0 = qi1; qr1 = qrn; qi1 = qin;
+        }
+        // w = (i / sqrt(pi)) P / Q ;  Re w = -Im(P / Q) / sqrt(pi)
+        const double den = qr1 * qr1 + qi1 * qi1;
+        const double im_ratio = (pi1 * qr1 - pr1 * qi1) / den;
+        return -im_ratio * 0.56418958354775628695;  // 1/sqrt(pi)
+    }
+    // Weideman: Z = (L + iz)/(L - iz), w = (2 p(Z) / (L - iz) + 1/sqrt(pi)) / (L - iz)
+    const double L = wc.L;
+    const double dr = L + y, di = -x;            // L - iz
+    const double dd = 1.0 / (dr * dr + di * di);
+    const double ir = dr * dd, ii = -di * dd;    // 1 / (L - iz)
+    const double nr = L - y, ni = x;             // L + iz
+    const double zr = nr * ir - ni * ii, zi = nr * ii + ni * ir;
+    double pr = wc.a[kWeidemanN - 1], pim = 0.0;
+#pragma unroll
+    for (int n = kWeidemanN - 2; n >= 0; --n) {
+        const double tr = pr * zr - pim * zi + wc.a[n];
+        const double ti = pr * zi + pim * zr;
+        pr = tr;
+        pim = ti;
+    }
+    // t = 2 p / (L - iz) + 1/sqrt(pi)
+    const double tr = 2.0 * (pr * ir - pim * ii) + 0.56418958354775628695;
+    const double ti = 2.0 * (pr * ii + pim * ir);
+    return tr * ir - ti * ii;
+}
+
+__device__ __forceinline__ double voigt_hwhm(double sig, double gam) {
+    return 0.5346 * gam + sqrt(0.2166 * gam * gam + 2.0 * 0.69314718055994530942 * sig * sig);
+}
+
+// the coefficients, computed once per process
+inline const WeidemanCoef& weideman() {
+    static const WeidemanCoef c = weideman_coefficients();
+    return c;
+}
+
+// Voigt profile V(x; sig, gam) = Re w((x + i gam) / (sig sqrt 2)) / (sig sqrt(2 pi))
+__device__ __forceinline__ double voigt_profile(double x, double sig, double gam, const WeidemanCoef& wc) {
+    const double inv = 1.0 / (sig * 1.41421356237309504880);
+    return faddeeva_re(x * inv, gam * inv, wc) / (sig * 2.50662827463100050242);
+}
+
+}  // namespace bm

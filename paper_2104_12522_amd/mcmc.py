@@ -201,6 +201,70 @@ class Retrieval:
         for _ in range(n_gen):
             self.generation()
 
+    def run_monitored(self, n_gen: int, burn: int = 0, n_saves: int = 10, chunk: int = 50,
+                      checkpoint: str | None = None) -> dict:
+        """Sec. 5's run cadence: the n_gen generations run in n_saves parts (whole graph
+        replays of `chunk` generations); after each part the state can be saved
+        (`checkpoint`, see save) and, once past the `burn` generations to discard, the
+        Gelman-Rubin statistic of the kept samples is logged; at the end SPEIS and ESS of
+        the kept samples. Needs a history buffer for every generation of the run."""
+        from . import diagnostics as dg
+        g0 = self.s.generation
+        if self.s.history is None or self.s.history.shape[0] < g0 + n_gen:
+            raise BartmiError("run_monitored needs a history of every generation")
+        if n_gen % chunk or n_saves < 1:
+            raise BartmiError("n_gen must be whole chunks")
+        graph = self.capture(chunk)
+        n_chunks = n_gen // chunk
+        bounds = sorted({round(n_chunks * (i + 1) / n_saves) for i in range(n_saves)})
+        log = []
+        done = 0
+        for b in bounds:
+            for _ in range(b - done):
+                graph.replay()
+            done = b
+            torch.cuda.synchronize()
+            gen = self.s.generation
+            if checkpoint:
+                self.save(checkpoint)
+            entry = {"generation": gen}
+            if gen - g0 > burn + 1:
+                kept = self.s.history[g0 + burn:gen].cpu().numpy()
+                gr = dg.gelman_rubin(kept)
+                entry.update(gr_max=float(np.max(gr)), gr=gr.tolist())
+            log.append(entry)
+        kept = self.s.history[g0 + burn:g0 + n_gen].cpu().numpy()
+        sp = dg.speis_per_chain(kept)
+        return {"log": log, "speis_max": float(sp.max()), "ess": float(kept.shape[0] * kept.shape[1] / sp.max()),
+                "gelman_rubin": dg.gelman_rubin(kept).tolist()}
+
+    def save(self, path: str):
+        """Checkpoint of the sampler state (chains, archive, counters, log posteriors,
+        acceptance counts, history) as a numpy archive of plain arrays."""
+        s = self.s
+        m = s.archive_size
+        arrays = {"x": s.x, "z": s.z[:m], "counters": s.counters, "lp": s.lp, "n_accept": s.n_accept}
+        if s.lp_surr is not None:
+            arrays["lp_surr"] = s.lp_surr
+        if s.history is not None:
+            arrays["history"] = s.history[:min(s.generation, s.history.shape[0])]
+        np.savez(path, **{k: v.cpu().numpy() for k, v in arrays.items()})
+
+    def load(self, path: str):
+        """Resume from a checkpoint written by save: the run continues with the same random
+        stream (draws are addressed by generation), so it reproduces an uninterrupted run."""
+        s = self.s
+        with np.load(path, allow_pickle=False) as f:
+            z = torch.as_tensor(f["z"], device=s.x.device)
+            s.load_state(torch.as_tensor(f["x"], device=s.x.device), z, int(f["counters"][0]))
+            s.lp.copy_(torch.as_tensor(f["lp"]))
+            s.n_accept.copy_(torch.as_tensor(f["n_accept"]))
+            if s.lp_surr is not None and "lp_surr" in f:
+                s.lp_surr.copy_(torch.as_tensor(f["lp_surr"]))
+            if s.history is not None and "history" in f:
+                h = torch.as_tensor(f["history"])
+                s.history[:h.shape[0]].copy_(h)
+
     def capture(self, n_gen: int) -> torch.cuda.CUDAGraph:
         """A HIP graph of n_gen generations (replay it to advance the chains)."""
         side = torch.cuda.Stream()

@@ -90,6 +90,6 @@ def test_binding_struct_layouts_match_the_library(lib):
     from paper_2104_12522_amd import _abi
     lib.bm_struct_size.restype = C.c_size_t
     lib.bm_struct_size.argtypes = [C.c_int]
-    for which, cls in enumerate((_abi.BmPlanet, _abi.BmModel, _abi.BmDemcz, _abi.BmMlp)):
+    for which, cls in enumerate((_abi.BmPlanet, _abi.BmModel, _abi.BmDemcz, _abi.BmMlp, _abi.BmVoigtGrid)):
         assert lib.bm_struct_size(which) == C.sizeof(cls), cls.__name__
     assert lib.bm_struct_size(99) == 0
