@@ -7,3 +7,4 @@ G_GRAV = 6.67430e-8         # cm^3 g^-1 s^-2
 BAR = 1.0e6                 # dyn / cm^2
 ATM_BAR = 1.01325           # 1 atm in bar
 T_REF = 296.0               # line-list reference temperature, K
+H_PLANCK = 6.62607015e-27     # erg s

@@ -12,6 +12,7 @@ from __future__ import annotations
 import numpy as np
 
 from .atmosphere import atmosphere, FLAG_T_CLAMP, FLAG_RADIUS
+from .constants import C2, C_LIGHT, H_PLANCK
 
 
 def interp_index(t_grid: np.ndarray, temp: float):
@@ -128,6 +129,40 @@ def transit_depth(radius: np.ndarray, tau: np.ndarray, rs_cm: float,
     return acc / rs_cm ** 2
 
 
+def planck(nu: np.ndarray, temp: float) -> np.ndarray:
+    """Planck function per unit wavenumber, B_nu(T) = 2 h c^2 nu^3 / (exp(c2 nu / T) - 1)
+    in erg s^-1 cm^-2 sr^-1 (cm^-1)^-1, nu in cm^-1 (c2 = h c / k_B)."""
+    nu = np.asarray(nu, dtype=np.float64)
+    return 2.0 * H_PLANCK * C_LIGHT ** 2 * nu ** 3 / np.expm1(C2 * nu / temp)
+
+
+def vertical_optical_depth(radius: np.ndarray, ext: np.ndarray) -> np.ndarray:
+    """Emission (eclipse) geometry, plane-parallel layers at the hydrostatic radii:
+    optical depth along the vertical from the top, trapezoid in height,
+    tau_{L-1} = 0, tau_l = tau_{l+1} + (r_{l+1} - r_l)(e_l + e_{l+1}) / 2."""
+    L, NNU = ext.shape
+    tau = np.zeros((L, NNU), dtype=np.float64)
+    for l in range(L - 2, -1, -1):
+        tau[l] = tau[l + 1] + (radius[l + 1] - radius[l]) * 0.5 * (ext[l] + ext[l + 1])
+    return tau
+
+
+def emergent_intensity(temp: np.ndarray, tau: np.ndarray, nu: np.ndarray) -> np.ndarray:
+    """Emission spectrum: the intensity emerging along the normal (the intensity spectra the
+    paper's eclipse-geometry tests compare, Sec. 6), no scattering, the Planck function as
+    source. The deepest layer radiates as a blackbody from below (no rays reach the abyss);
+    between layers the source is the mean of the two layers' Planck functions:
+    I = B(T_0) e^{-tau_0} + sum_l (B(T_l) + B(T_{l+1}))/2 (e^{-tau_{l+1}} - e^{-tau_l}).
+    An isothermal atmosphere therefore emits exactly B(T) (the f08 test)."""
+    L = tau.shape[0]
+    b = np.array([planck(nu, float(t)) for t in temp])
+    att = np.exp(-tau)
+    out = b[0] * att[0]
+    for l in range(L - 1):
+        out = out + 0.5 * (b[l] + b[l + 1]) * (att[l + 1] - att[l])
+    return out
+
+
 def bin_spectrum(depth: np.ndarray, bin_width: int) -> np.ndarray:
     """Step a6 (spectrum integrator). Channels with perfect transmission over their
     range (Sec. 6.3): the mean of each group of ``bin_width`` consecutive points;
@@ -146,7 +181,8 @@ def forward(params: np.ndarray, setup, sigma: np.ndarray, cia: np.ndarray | None
             cia_he: np.ndarray | None = None):
     """Steps a1-a6 for one parameter vector. Returns a dict with the spectrum, the
     intermediate arrays, binned depths and chi^2 (when data are given), and flags.
-    A sample whose radii are invalid gets a NaN spectrum."""
+    A sample whose radii are invalid gets a NaN spectrum. With setup.geometry == "eclipse"
+    the spectrum (key "depth") is the emergent intensity instead of the transit depth."""
     atm = atmosphere(params, setup.p_bar, setup.mass_amu, setup.tp_mode, setup.planet)
     flags = atm["flags"]
     ext, f = extinction(sigma, setup.temps, atm["temp"], atm["n_species"],
@@ -160,6 +196,10 @@ def forward(params: np.ndarray, setup, sigma: np.ndarray, cia: np.ndarray | None
     if flags & FLAG_RADIUS:
         nan = np.full(setup.nu.size, np.nan)
         out = dict(atm=atm, ext=ext, tau=None, depth=nan, flags=flags)
+    elif getattr(setup, "geometry", "transit") == "eclipse":
+        tau = vertical_optical_depth(atm["radius"], ext)
+        out = dict(atm=atm, ext=ext, tau=tau, depth=emergent_intensity(atm["temp"], tau, setup.nu),
+                   flags=flags)
     else:
         tau = optical_depth(atm["radius"], ext)
         depth = transit_depth(atm["radius"], tau, setup.planet.rs_cm,

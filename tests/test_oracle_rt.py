@@ -389,3 +389,80 @@ def test_cia_tables_combine_into_one_h2h2_table():
     # and the H2-He term is not negligible in the band it covers
     e_hh, _ = rt.extinction(sigma, temps, a["temp"], a["n_species"], k1, temps, a["n_h2"])
     assert np.max((e_sep - e_hh) / e_hh) > 1e-3
+
+
+# ---- emission (eclipse) geometry ---------------------------------------------------------
+def test_planck_wien_peak_and_stefan_boltzmann():
+    # the peak of B_nu (per wavenumber) sits at x = c2 nu / T solving 3 (1 - e^-x) = x
+    # (Wien's law for this form, Sec. 6 f08 test); its integral is sigma T^4 / pi
+    from scipy import optimize
+    x_w = optimize.brentq(lambda x: 3.0 * (1.0 - math.exp(-x)) - x, 1.0, 5.0)
+    for T in (700.0, 1500.0, 2900.0):
+        nu = np.linspace(1.0, 40.0 * T, 400001)
+        b = rt.planck(nu, T)
+        nu_peak = nu[np.argmax(b)]
+        assert nu_peak == pytest.approx(x_w * T / 1.4387769, rel=2e-4)
+        total, _ = integrate.quad(lambda v: rt.planck(np.array([v]), T)[0], 1e-6, 60.0 * T, limit=400)
+        assert total == pytest.approx(5.670374419e-5 * T ** 4 / math.pi, rel=1e-7)
+
+
+def _emission_layers(L=40):
+    r = np.linspace(8.0e9, 8.3e9, L)
+    return r
+
+
+def test_vertical_optical_depth_exact_for_uniform_extinction():
+    r = _emission_layers()
+    e = np.full((r.size, 3), 2.5e-9)
+    tau = rt.vertical_optical_depth(r, e)
+    np.testing.assert_allclose(tau, 2.5e-9 * (r[-1] - r)[:, None] * np.ones(3), rtol=1e-13, atol=1e-18)
+
+
+def test_isothermal_atmosphere_emits_a_blackbody():
+    # f08isothermal (Sec. 6): an isothermal atmosphere of any opacity emits B(T) exactly
+    r = _emission_layers()
+    nu = np.linspace(500.0, 9000.0, 50)
+    g = np.random.default_rng(2)
+    ext = g.uniform(0.0, 3e-8, size=(r.size, nu.size))
+    tau = rt.vertical_optical_depth(r, ext)
+    got = rt.emergent_intensity(np.full(r.size, 1234.5), tau, nu)
+    np.testing.assert_allclose(got, rt.planck(nu, 1234.5), rtol=1e-13)
+
+
+def test_transparent_atmosphere_shows_the_deep_blackbody_and_two_layer_closed_form():
+    nu = np.linspace(500.0, 9000.0, 20)
+    r = np.array([8.0e9, 8.0e9 + 3.0e6])
+    temp = np.array([1600.0, 900.0])
+    tau0 = rt.vertical_optical_depth(r, np.zeros((2, nu.size)))
+    np.testing.assert_array_equal(rt.emergent_intensity(temp, tau0, nu), rt.planck(nu, 1600.0))
+    e = np.full((2, nu.size), 4e-7)
+    t = 4e-7 * 3.0e6
+    b0, b1 = rt.planck(nu, 1600.0), rt.planck(nu, 900.0)
+    want = b0 * math.exp(-t) + 0.5 * (b0 + b1) * (1.0 - math.exp(-t))
+    np.testing.assert_allclose(rt.emergent_intensity(temp, rt.vertical_optical_depth(r, e), nu), want,
+                               rtol=1e-14)
+
+
+def test_emission_thin_limit_linearity():
+    # f05abundance (Sec. 6, Table 3): in the optically thin limit the absorbed fraction
+    # scales with the absorber abundance, f = (F0 - Fh) / (F0 - Fl) -> x_h / x_l; with
+    # saturation the ratio falls slightly below f, more so for larger f (as in Table 3)
+    L = 40
+    r = _emission_layers(L)
+    temp = np.linspace(1500.0, 900.0, L)       # non-inverted: cooler upward
+    nu = np.linspace(1990.0, 2010.0, 201)
+    line = 1e-7 * np.exp(-((nu - 2000.0) / 0.5) ** 2)   # extinction per unit abundance, cm^-1
+    base = np.full(L, 1e-10)[:, None] * np.ones(nu.size)
+    def spectrum(x):
+        ext = base + x * np.ones(L)[:, None] * line[None, :]
+        return rt.emergent_intensity(temp, rt.vertical_optical_depth(r, ext), nu)
+    f0, fl = spectrum(0.0), spectrum(1e-5)
+    c = np.argmin(np.abs(nu - 2000.0))
+    ratios = []
+    for f in range(2, 11):
+        fh = spectrum(f * 1e-5)
+        ratios.append((f0[c] - fh[c]) / (f0[c] - fl[c]))
+    ratios = np.array(ratios)
+    fs = np.arange(2, 11)
+    assert np.all(ratios < fs) and np.all(np.abs(ratios - fs) / fs < 2e-3)
+    assert np.all(np.diff(fs - ratios) > 0)
