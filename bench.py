@@ -572,12 +572,58 @@ def section_opacity(args):
     ms = start.elapsed_time(end)
     log(f"opacity: build in {ms / 1e3:.2f} s")
     evals = window_evaluations(lines, nu, temps, p_bar, sample=20000, seed=args.seed + 80)
-    return {"lines": n_lines, "n_nu": int(nu.size), "n_temp": int(len(temps)),
-            "n_p": int(len(p_bar)), "dtype": "f32 out, f64 accumulation", "cutoff_hwhm": 25.0,
-            "seconds": ms / 1e3, "output_gb": out.numel() * 4 / 1e9,
-            "profile_evaluations": evals, "evaluations_per_s": evals / (ms * 1e-3),
-            "evaluations_note": "window points summed over lines and cells, counted on the host "
-                                "from a 20000-line sample scaled to all lines"}
+    res = {"lines": n_lines, "n_nu": int(nu.size), "n_temp": int(len(temps)),
+           "n_p": int(len(p_bar)), "dtype": "f32 out, f64 accumulation", "cutoff_hwhm": 25.0,
+           "seconds": ms / 1e3, "output_gb": out.numel() * 4 / 1e9,
+           "profile_evaluations": evals, "evaluations_per_s": evals / (ms * 1e-3),
+           "evaluations_note": "window points summed over lines and cells, counted on the host "
+                               "from a 20000-line sample scaled to all lines"}
+    del out
+    res["profile_table_mode"] = table_mode_comparison(args, lines, nu, temps, p_bar)
+    return res
+
+
+def table_mode_comparison(args, lines, nu, temps, p_bar):
+    """The paper's profile-table mode (60 x 60 Voigt profiles, oversampled and aligned to the
+    output grid) against the direct build on the same subset: every 10th line, every 4th
+    temperature and every 10th pressure of the grid."""
+    import torch
+    import paper_2104_12522_amd as bm
+    sub = lines.subset(np.arange(0, lines.nu0.size, 10))
+    t_sub, p_sub = temps[::4], p_bar[::10]
+    dnu = float(nu[1] - nu[0])
+    sn, gn = bm.VoigtTable.nodes_for(sub, t_sub, p_sub, 60, 60)
+    t0 = time.perf_counter()
+    tab = bm.VoigtTable(sn, gn, dnu, args.opacity_oversample, 25.0)
+    torch.cuda.synchronize()
+    t_table = time.perf_counter() - t0
+    log(f"opacity: profile table {tab.bytes / 1e9:.2f} GB built in {t_table:.2f} s")
+    shape = (len(t_sub), len(p_sub), nu.size)
+    direct = torch.empty(shape, dtype=torch.float32, device="cuda")
+    table = torch.empty(shape, dtype=torch.float32, device="cuda")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ev[0].record()
+    bm.opacity_table_build(sub, t_sub, p_sub, float(nu[0]), dnu, nu.size, out=direct)
+    ev[1].record()
+    bm.opacity_table_build_profiles(sub, t_sub, p_sub, float(nu[0]), nu.size, tab, out=table)
+    ev[2].record()
+    torch.cuda.synchronize()
+    ms_d, ms_t = ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])
+    d = direct.double()
+    big = d > 1e-3 * d.amax(dim=2, keepdim=True)
+    rel = ((table.double() - d).abs() / d)[big]
+    evals = window_evaluations(sub, nu, t_sub, p_sub, sample=20000, seed=args.seed + 81)
+    log(f"opacity: subset direct {ms_d / 1e3:.2f} s, profile table {ms_t / 1e3:.2f} s; table vs direct "
+        f"max {float(rel.max()):.2e}, median {float(rel.median()):.2e}")
+    return {"lines": int(sub.nu0.size), "n_temp": int(len(t_sub)), "n_p": int(len(p_sub)),
+            "profiles": "60 x 60", "oversample": args.opacity_oversample, "table_gb": tab.bytes / 1e9,
+            "table_build_s": t_table, "direct_s": ms_d / 1e3, "table_mode_s": ms_t / 1e3,
+            "profile_evaluations": evals, "direct_evaluations_per_s": evals / (ms_d * 1e-3),
+            "table_evaluations_per_s": evals / (ms_t * 1e-3),
+            "rel_diff_vs_direct_where_above_1e-3_of_max": {"max": float(rel.max()),
+                                                           "median": float(rel.median()),
+                                                           "p99": float(rel.quantile(0.99)) if rel.numel() < 16_000_000
+                                                           else None}}
 
 
 def window_evaluations(lines, nu, temps, p_bar, sample: int, seed: int) -> float:
@@ -654,6 +700,8 @@ def main():
     ap.add_argument("--chains", type=int, default=256)
     ap.add_argument("--batched-gens", type=int, default=200)
     ap.add_argument("--no-mixed", dest="mixed", action="store_false")
+    ap.add_argument("--opacity-oversample", type=int, default=1000,
+                    help="fine samples per output interval of the profile table (opacity section)")
     ap.add_argument("--mcmc-gens", type=int, default=12000)
     ap.add_argument("--mcmc-burn", type=int, default=1000)
     ap.add_argument("--da-burn", type=int, default=0,

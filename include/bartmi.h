@@ -130,7 +130,23 @@ typedef struct bm_model {
                              parameter, log10(p_cloud / bar), after the radius; in
                              bm_forward_batch every chord whose impact-parameter layer has
                              p >= p_cloud is opaque                                            */
+    int32_t geometry;     /* BM_GEOM_TRANSIT (transit depth) or BM_GEOM_ECLIPSE (emergent
+                             intensity, below); eclipse takes no cloud deck and no tau_max     */
+    int32_t pad2;
 } bm_model;
+
+/* Geometries of bm_forward_batch's spectrum (bm_model.geometry).
+ * BM_GEOM_ECLIPSE (Sec. 3 and Sec. 4, transit's emission spectra; Sec. 6, the intensity
+ * spectra of the eclipse-geometry tests): plane-parallel layers at the hydrostatic radii,
+ * vertical optical depth from the top by the trapezoid in height,
+ *   tau_{L-1} = 0, tau_l = tau_{l+1} + (r_{l+1} - r_l)(e_l + e_{l+1}) / 2,
+ * and the intensity emerging along the normal with the Planck function as source, the
+ * deepest layer radiating from below and the two layers' mean source between them:
+ *   I = B(T_0) e^{-tau_0} + sum_l (B(T_l) + B(T_{l+1}))/2 (e^{-tau_{l+1}} - e^{-tau_l}),
+ *   B(T) = 2 h c^2 nu^3 / (exp(c2 nu / T) - 1)   (erg s^-1 cm^-2 sr^-1 (cm^-1)^-1),
+ * which needs the wavenumber grid (nu_start, dnu). The spectrum buffer then holds I. */
+#define BM_GEOM_TRANSIT 0
+#define BM_GEOM_ECLIPSE 1
 
 /* Number of parameters of a sample: (1 or 5) + S + 1 (+ 1 with a cloud deck). */
 int bm_n_params(const bm_model* model);

@@ -86,7 +86,7 @@ class Model:
                  cia: torch.Tensor | None = None, cia_temps=None, bin_width: int = 0,
                  data=None, err=None, device="cuda", tau_max: float = 0.0,
                  nu_start: float = 0.0, dnu: float = 0.0, rayleigh: bool = False,
-                 cloud: bool = False, cia_he: torch.Tensor | None = None):
+                 cloud: bool = False, cia_he: torch.Tensor | None = None, geometry: str = "transit"):
         """cia_he: an H2-He CIA table on the CIA temperature grid; it is folded into the
         H2-H2 table once here (bm_cia_combine), since n_He / n_H2 is fixed by the filler
         split."""
@@ -137,6 +137,10 @@ class Model:
             raise BartmiError("Rayleigh scattering needs the wavenumber grid (nu_start, dnu)")
         st.nu_start, st.dnu = float(nu_start), float(dnu)
         st.rayleigh, st.cloud = int(bool(rayleigh)), int(bool(cloud))
+        if geometry not in ("transit", "eclipse"):
+            raise BartmiError("geometry is 'transit' or 'eclipse'")
+        st.geometry = 0 if geometry == "transit" else 1
+        self.geometry = geometry
         self.struct = st
 
     @property
@@ -400,6 +404,24 @@ class VoigtTable:
         self.table = torch.empty(self.bytes, dtype=torch.uint8, device=device)
         _check(lib().bm_voigt_table_build(C.byref(g), _ptr(self.table), self.bytes, _stream(stream)),
                "bm_voigt_table_build")
+
+    @staticmethod
+    def nodes_for(lines, temps, p_bar, n_sigma: int = 60, n_gamma: int = 60, margin: float = 1.01):
+        """Log-spaced nodes over the Doppler and Lorentz widths the lines take in these
+        cells (the range of expected widths), widened by `margin` at both ends."""
+        k_b, amu, c_light, atm, t_ref = 1.380649e-16, 1.66053906660e-24, 2.99792458e10, 1.01325, 296.0
+        nu0 = np.asarray(lines.nu0, dtype=np.float64)
+        mass = np.asarray(lines.mass_amu, dtype=np.float64)
+        g296 = np.asarray(lines.gamma296, dtype=np.float64)
+        temps = np.asarray(temps, dtype=np.float64)
+        p_bar = np.asarray(p_bar, dtype=np.float64)
+        s0 = nu0 / c_light / np.sqrt(mass * amu)
+        s_lo = s0.min() * np.sqrt(k_b * temps.min())
+        s_hi = s0.max() * np.sqrt(k_b * temps.max())
+        g_lo = g296.min() * (p_bar.min() / atm) * np.sqrt(t_ref / temps.max())
+        g_hi = g296.max() * (p_bar.max() / atm) * np.sqrt(t_ref / temps.min())
+        return (np.geomspace(s_lo / margin, s_hi * margin, n_sigma),
+                np.geomspace(g_lo / margin, g_hi * margin, n_gamma))
 
 
 def opacity_table_build_profiles(lines, temps, p_bar, nu_start: float, n_nu: int, table: VoigtTable,

@@ -30,7 +30,7 @@ class BmModel(C.Structure):
         ("mass_amu", C.c_double * BM_MAX_SPECIES),
         ("planet", BmPlanet),
         ("tau_max", C.c_double), ("nu_start", C.c_double), ("dnu", C.c_double),
-        ("rayleigh", C.c_int32), ("cloud", C.c_int32),
+        ("rayleigh", C.c_int32), ("cloud", C.c_int32), ("geometry", C.c_int32), ("pad2", C.c_int32),
     ]
 
 

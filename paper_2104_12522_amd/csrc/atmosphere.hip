@@ -301,6 +301,7 @@ __global__ void __launch_bounds__(kAtmThreads)
             const double nh2 = a.x_h2 * sh.ndens[l];
             rec.bfac[l] = nh2 * nh2;
             rec.rfac[l] = (T)nh2;
+            rec.tl[l] = sh.temp[l];
         } else {
 #pragma unroll
             for (int i = 0; i < BM_MAX_SPECIES; ++i)
@@ -324,6 +325,7 @@ __global__ void __launch_bounds__(kAtmThreads)
             else
                 c = r[tid] * (r[tid + 1] - r[tid - 1]);
             rec.cw[tid] = c;
+            rec.rl[tid] = r[tid];
         }
         __syncthreads();
         if (tid == 0) {

@@ -56,7 +56,7 @@ struct ModelDev {
     const double* data;
     const double* err;
     int S, NT, L, Nnu, NTc, tp_mode, bin_width, nb;
-    int rayleigh, cloud;
+    int rayleigh, cloud, geometry;
     double mass[BM_MAX_SPECIES];
     bm_planet pl;
     double tau_max;  // optical-depth limit (+infinity: none)
@@ -130,7 +130,7 @@ __host__ __device__ inline size_t chord_weight_entries(int L) {
 // Byte layout of one sample record for compute type T.
 template <typename T>
 struct RecordLayout {
-    size_t hdr, kidx, kcidx, w, wc, bfac, rfac, afac, cw, wb, total;
+    size_t hdr, kidx, kcidx, w, wc, bfac, rfac, afac, cw, tl, rl, wb, total;
     __host__ __device__ RecordLayout(int S, int L) {
         size_t o = 0;
         hdr = o;   o = align_up(o + sizeof(RecordHeader), 64);
@@ -142,6 +142,8 @@ struct RecordLayout {
         rfac = o;  o = align_up(o + sizeof(T) * L, 64);
         afac = o;  o = align_up(o + sizeof(T) * L * S, 64);
         cw = o;    o = align_up(o + sizeof(double) * L, 64);
+        tl = o;    o = align_up(o + sizeof(double) * L, 64);
+        rl = o;    o = align_up(o + sizeof(double) * L, 64);
         wb = o;    o = align_up(o + sizeof(T) * chord_weight_entries<T>(L), 256);
         total = o;
     }
@@ -158,6 +160,8 @@ struct RecordView {
     T* rfac;       // n_H2 (Rayleigh scattering)
     T* afac;       // [S][L] absorber number densities
     double* cw;    // impact-parameter weight of f_j
+    double* tl;    // layer temperatures (emission source)
+    double* rl;    // layer radii (emission path lengths)
     T* wb;         // chord weights (layout: chord_weight_entries)
     double* chi2part;  // [tiles] chi^2 of each tile's channels (after the fixed layout)
     __host__ __device__ RecordView(char* base, int S, int L) {
@@ -171,6 +175,8 @@ struct RecordView {
         rfac = (T*)(base + lay.rfac);
         afac = (T*)(base + lay.afac);
         cw = (double*)(base + lay.cw);
+        tl = (double*)(base + lay.tl);
+        rl = (double*)(base + lay.rl);
         wb = (T*)(base + lay.wb);
         chi2part = (double*)(base + lay.total);
     }
@@ -198,9 +204,14 @@ struct HostPlan {
     int n_species = 0;
     bool cia = false;
     int max_ntc = 0;          // largest CIA temperature grid (LDS staging rows)
+    int geometry = 0;         // BM_GEOM_TRANSIT or BM_GEOM_ECLIPSE (all models of a batch)
     int total_samples = 0;
     size_t max_entries = 0;   // chord-weight entries of the largest record
 };
+
+// emission geometry: intensity of samples [first, first + count) of one segment
+template <typename T>
+int launch_k_emission(const LaunchPlan& lp, int seg, char* ws, const int32_t* act, double* out, hipStream_t st);
 
 // launch of the fused kernel for one plan with kW waves per workgroup, non-temporal (kNT)
 // or cached table loads, and phase-2 mode kMode (chord weights streamed from L2, staged in

@@ -181,6 +181,9 @@ int validate_model(const bm_model& m, bool need_tables) {
     if (m.bin_width > 0 && m.n_nu / m.bin_width < 1) return BM_ESHAPE;
     if (m.rayleigh && !(m.dnu > 0.0 && m.nu_start + m.dnu * (m.n_nu - 1) > 0.0 && m.nu_start > 0.0))
         return BM_EINVAL;
+    if (m.geometry != BM_GEOM_TRANSIT && m.geometry != BM_GEOM_ECLIPSE) return BM_EINVAL;
+    if (m.geometry == BM_GEOM_ECLIPSE && (m.cloud || m.tau_max > 0.0 || !(m.dnu > 0.0) || !(m.nu_start > 0.0)))
+        return BM_EINVAL;
     return BM_OK;
 }
 
@@ -208,6 +211,7 @@ ModelDev to_device_view(const bm_model& m) {
     d.dnu = m.dnu;
     d.rayleigh = m.rayleigh ? 1 : 0;
     d.cloud = m.cloud ? 1 : 0;
+    d.geometry = m.geometry;
     return d;
 }
 
@@ -240,7 +244,9 @@ static int build_plans(const bm_model* models, int n_models, const int32_t* inst
         if (models[i].n_species != models[0].n_species) return BM_ESHAPE;
         // one launch is specialised on the presence of CIA
         if ((models[i].n_temp_cia > 0) != (models[0].n_temp_cia > 0)) return BM_ESHAPE;
+        if (models[i].geometry != models[0].geometry) return BM_EINVAL;
     }
+    hp.geometry = models[0].geometry;
     hp.n_species = models[0].n_species;
     hp.cia = models[0].n_temp_cia > 0;
     size_t ws = 0, depth_off = 0, bin_off = 0;
@@ -260,7 +266,7 @@ static int build_plans(const bm_model* models, int n_models, const int32_t* inst
             s.model = mi;
             s.first = b - first_of_plan;
             s.count = e - b;
-            s.fused_bins = (md.bin_width > 0 && md.bin_width <= kTileNu) ? 1 : 0;
+            s.fused_bins = (md.geometry == BM_GEOM_TRANSIT && md.bin_width > 0 && md.bin_width <= kTileNu) ? 1 : 0;
             s.tile_w = s.fused_bins ? (kTileNu / md.bin_width) * md.bin_width : kTileNu;
             s.tiles = (md.n_nu + s.tile_w - 1) / s.tile_w;
             s.tiles_per_xcd = (s.tiles + kXcds - 1) / kXcds;
@@ -433,9 +439,15 @@ static int launch_forward(const HostPlan& hp, int cfg, const double* params, int
         }
         BM_CHECK_HIP(hipGetLastError());
         double* c2 = chi2 ? chi2 + b0 : nullptr;
+        int code;
+        if (hp.geometry == BM_GEOM_ECLIPSE) {
+            for (int si = 0; si < lp.n_seg; ++si) {
+                code = launch_k_emission<T>(lp, si, ws, act, depth, st);
+                if (code != BM_OK) return code;
+            }
+        } else {
         hipEvent_t e0, e1;
         timing_slot(st, &e0, &e1);
-        int code;
         if constexpr (sizeof(T) == 8) {
             code = launch_k_forward<T, 8, true, kModeStreamed>(hp, lp, lds, ws, act, depth, binned, c2, st, e0, e1);
         } else {
@@ -451,6 +463,7 @@ static int launch_forward(const HostPlan& hp, int cfg, const double* params, int
 #undef BM_CFG
         }
         if (code != BM_OK) return code;
+        }
         if (c2 && binned) {
             bool any_fused = false;
             for (int si = 0; si < lp.n_seg; ++si) any_fused |= lp.seg[si].fused_bins != 0;

@@ -34,7 +34,7 @@ def gpu_model(setup, sigma, cia=None, data=None, err=None, device="cuda", cia_he
                     bin_width=setup.bin_width, data=data, err=err, device=device,
                     tau_max=setup.tau_max, nu_start=float(setup.nu[0]),
                     dnu=float(setup.nu[1] - setup.nu[0]) if setup.nu.size > 1 else 1.0,
-                    rayleigh=setup.rayleigh, cloud=setup.cloud,
+                    rayleigh=setup.rayleigh, cloud=setup.cloud, geometry=setup.geometry,
                     cia_he=None if cia_he is None else torch.as_tensor(cia_he))
 
 

@@ -449,3 +449,41 @@ def test_cia_combine_entry_point():
     torch.cuda.synchronize()
     np.testing.assert_allclose(_np(out), a + (0.15 / 0.85) * b, rtol=1e-15)
     assert lib.bm_cia_combine(bm._ptr(ta), bm._ptr(tb), float("nan"), 1000, bm._ptr(out), bm._stream()) != 0
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_emission_geometry_matches_oracle(dtype):
+    # eclipse geometry (emergent intensity, Planck source, vertical optical depth) through
+    # bm_forward_batch, with channels and chi^2 from the separate binning pass
+    s, sigma, cia = small_config2(n_nu=700, n_layers=70, seed=91)
+    s.geometry = "eclipse"
+    if dtype == "f64":
+        sigma, rtol = sigma.astype(np.float64), 1e-10
+    else:
+        rtol = 1e-4
+    params = prior_for(s).draw(4, seed=92)
+    ref0 = ort.forward(params[0], s, sigma.astype(np.float64), cia.astype(np.float64))
+    nb = s.nu.size // s.bin_width
+    data = ref0["binned"] * (1.0 + 1e-3 * np.sin(np.arange(nb)))
+    err = 1e-3 * ref0["binned"]
+    _check_fused(s, sigma, cia, params, rtol=rtol, data=data, err=err)
+
+
+def test_emission_isothermal_is_a_blackbody():
+    # f08isothermal (Sec. 6): an isothermal atmosphere emits the Planck function
+    s, sigma = config1_table(n_nu=300)
+    s.geometry = "eclipse"
+    model = gpu_model(s, sigma)
+    params = np.array([[1200.0, -4.0, 1.14], [2100.0, -3.0, 1.2]])
+    f = bm.forward_batch(model, torch.as_tensor(params, device="cuda"))
+    torch.cuda.synchronize()
+    for b in range(2):
+        np.testing.assert_allclose(_np(f.spectrum(b)), ort.planck(s.nu, params[b, 0]), rtol=1e-12)
+
+
+def test_emission_rejects_transit_only_options():
+    s, sigma = config1_table(n_nu=64)
+    s.geometry, s.tau_max = "eclipse", 2.0
+    model = gpu_model(s, sigma)
+    with pytest.raises(bm.BartmiError):
+        bm.forward_batch(model, torch.as_tensor(np.array([[1200.0, -4.0, 1.14]]), device="cuda"))

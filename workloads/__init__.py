@@ -200,6 +200,7 @@ class ForwardSetup:
     tau_max: float = 0.0         # optical-depth limit (0: none)
     rayleigh: bool = False       # H2 Rayleigh scattering in the extinction
     cloud: bool = False          # gray cloud deck: one more parameter, log10 p_cloud (bar)
+    geometry: str = "transit"    # "transit" (transit depth) or "eclipse" (emergent intensity)
 
 
 def config1() -> ForwardSetup:
