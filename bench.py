@@ -518,6 +518,9 @@ def section_mcmc(args, setup, prior):
                 "chains_identical_to_batched": identical, "ess": plain_b["ess"],
                 "ess_per_s": plain_b["ess"] / ps_wall}
     diff = (mu_d - mu_b2) / sd_b2
+    # the same differences in units of their standard error, sd / sqrt(ESS) for each run
+    se = np.sqrt(sd_b2 ** 2 / plain_b["ess"] + sd_d ** 2 / da["ess"])
+    diff_z = (mu_d - mu_b2) / se
     ratio = da["ess_per_s"] / plain_ps["ess_per_s"]
     # end to end: surrogate data and training charged to the delayed-acceptance run
     e2e = (da["ess"] / (w_d + t_local)) / (plain_b["ess"] / ps_wall)
@@ -543,6 +546,8 @@ def section_mcmc(args, setup, prior):
         "ess_per_s_ratio_end_to_end": e2e,
         "marginal_mean_diff_sd": diff.tolist(),
         "max_abs_mean_diff_sd": float(np.abs(diff).max()),
+        "marginal_mean_diff_in_standard_errors": diff_z.tolist(),
+        "max_abs_mean_diff_in_standard_errors": float(np.abs(diff_z).max()),
         "marginal_mean": {"plain": mu_b2.tolist(), "delayed_acceptance": mu_d.tolist()},
         "marginal_sd": {"plain": sd_b2.tolist(), "delayed_acceptance": sd_d.tolist()},
     }
