@@ -529,6 +529,7 @@ def section_mcmc(args, setup, prior):
         f"{np.abs(diff).max():.3f} sd")
     return {
         "chains": C, "burn_in": BURN, "da_burn_in": args.da_burn, "truth": truth.tolist(),
+        "prior": {"lo": prior.lo.tolist(), "hi": prior.hi.tolist()},
         "surrogate": {"dims": dims, "dtype": "bf16 weights/activations, fp32 accumulate",
                       "train_spectra": args.train_spectra, "epochs": args.epochs,
                       "data_s": t_data, "train_s": t_train, "adam_steps": net.step,
@@ -707,7 +708,7 @@ def main():
     ap.add_argument("--no-mixed", dest="mixed", action="store_false")
     ap.add_argument("--opacity-oversample", type=int, default=1000,
                     help="fine samples per output interval of the profile table (opacity section)")
-    ap.add_argument("--mcmc-gens", type=int, default=12000)
+    ap.add_argument("--mcmc-gens", type=int, default=20000)
     ap.add_argument("--mcmc-burn", type=int, default=1000)
     ap.add_argument("--da-burn", type=int, default=0,
                     help="further burn-in generations with delayed acceptance before production")
@@ -763,7 +764,9 @@ def main():
     if "batched" in sections:
         out["batched"] = section_batched(args, setup, model, prior)
     if "mcmc" in sections:
-        out["mcmc"] = section_mcmc(args, setup, prior)
+        # the retrieval labels the two visible streams (alpha <= 1/2), so that the
+        # posterior has no mirror mode in (gamma1, gamma2, alpha)
+        out["mcmc"] = section_mcmc(args, setup, wl.line2013_prior(S, alpha_max=0.5))
     if "copy" in sections:
         out["copy"] = section_copy(args)
     if "opacity" in sections:

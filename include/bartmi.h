@@ -133,6 +133,12 @@ typedef struct bm_model {
     int32_t geometry;     /* BM_GEOM_TRANSIT (transit depth) or BM_GEOM_ECLIPSE (emergent
                              intensity, below); eclipse takes no cloud deck and no tau_max     */
     int32_t pad2;
+    const void* sigma_tiles; /* device, or NULL: tile-major copy of sigma written by
+                             bm_sigma_tiles for this model and tile width tile_w; read by
+                             bm_forward_batch's fused kernel in place of sigma wherever its
+                             tile width equals tile_w (else sigma is read)                   */
+    int32_t tile_w;       /* 1..64: the wavenumbers per tile of sigma_tiles (ignored if NULL) */
+    int32_t pad3;
 } bm_model;
 
 /* Geometries of bm_forward_batch's spectrum (bm_model.geometry).
@@ -227,6 +233,21 @@ int bm_bin_chi2(const double* depth, int B, int n_nu, int bin_width, const doubl
  * in a HIP graph. */
 size_t bm_workspace_size(const bm_model* models, int n_models, const int32_t* instance,
                          int B);
+/* Tile-major copy of a model's opacity tables (the same values as sigma, rearranged).
+ * bm_forward_batch's fused kernel reads the tables in tiles of tile_w consecutive
+ * wavenumbers, one 64-wide column block per tile; in the row-major [S][NT][L][Nnu] layout
+ * each (species, temperature, layer) row piece of a tile is a separate short read, which
+ * the copy turns into one contiguous block per tile:
+ *   out[s][k][t][l][c] = sigma[s][k][l][min(t tile_w + c, Nnu - 1)],
+ *   t < n_tiles = ceil(Nnu / tile_w), c < 64, element type model->dtype.
+ * bm_sigma_tiles_bytes gives the size (0 on invalid arguments); bm_sigma_tiles writes
+ * `out` (device, caller-owned, out_bytes >= that size) on `stream` from model->sigma.
+ * Set model->sigma_tiles = out and model->tile_w = tile_w to use it; the fused kernel
+ * takes it for a run whose tile width is tile_w: floor(64 / bin_width) bin_width when the
+ * call bins with 1 <= bin_width <= 64, else 64. Errors: BM_EINVAL (tile_w outside 1..64,
+ * or a bad model), BM_ENOSPACE (out_bytes too small). */
+size_t bm_sigma_tiles_bytes(const bm_model* model, int tile_w);
+int bm_sigma_tiles(const bm_model* model, int tile_w, void* out, size_t out_bytes, void* stream);
 int bm_forward_batch(const bm_model* models, int n_models, const int32_t* instance,
                      const double* params, int param_stride, int B, const int32_t* active,
                      double* depth, double* binned, double* chi2, int32_t* flags,

@@ -86,10 +86,14 @@ class Model:
                  cia: torch.Tensor | None = None, cia_temps=None, bin_width: int = 0,
                  data=None, err=None, device="cuda", tau_max: float = 0.0,
                  nu_start: float = 0.0, dnu: float = 0.0, rayleigh: bool = False,
-                 cloud: bool = False, cia_he: torch.Tensor | None = None, geometry: str = "transit"):
+                 cloud: bool = False, cia_he: torch.Tensor | None = None, geometry: str = "transit",
+                 tiles: bool = True):
         """cia_he: an H2-He CIA table on the CIA temperature grid; it is folded into the
         H2-H2 table once here (bm_cia_combine), since n_He / n_H2 is fixed by the filler
-        split."""
+        split. tiles: also keep a tile-major copy of the tables (bm_sigma_tiles, 64/60 of the
+        table size for 30-point channels) for the tile width of binned calls,
+        floor(64 / bin_width) bin_width (64 without channels); the fused kernel reads it
+        for calls with that tile width (transit geometry)."""
         if sigma.dim() != 4:
             raise BartmiError("sigma must be [S][NT][L][Nnu]")
         self.sigma = sigma.to(device).contiguous()
@@ -142,6 +146,25 @@ class Model:
         st.geometry = 0 if geometry == "transit" else 1
         self.geometry = geometry
         self.struct = st
+        self.sigma_tiles = None
+        tw = (64 // bin_width) * bin_width if 1 <= bin_width <= 64 else 64
+        # transit only (the emission kernel reads sigma); a model the library rejects gets no
+        # copy here, and its calls report the error
+        if tiles and geometry == "transit" and lib().bm_sigma_tiles_bytes(C.byref(st), tw) > 0:
+            self.build_tiles(tw)
+
+    def build_tiles(self, tile_w: int):
+        """(Re)builds the tile-major table copy for tile width tile_w (bm_sigma_tiles)."""
+        st = self.struct
+        st.sigma_tiles, st.tile_w = None, 0
+        self.sigma_tiles = None
+        n = lib().bm_sigma_tiles_bytes(C.byref(st), int(tile_w))
+        if n == 0:
+            raise BartmiError(f"bm_sigma_tiles_bytes: invalid model or tile width {tile_w}")
+        self.sigma_tiles = torch.empty(n // self.sigma.element_size(), dtype=self.dtype, device=self.sigma.device)
+        _check(lib().bm_sigma_tiles(C.byref(st), int(tile_w), _ptr(self.sigma_tiles), n, _stream(None)),
+               "bm_sigma_tiles")
+        st.sigma_tiles, st.tile_w = _ptr(self.sigma_tiles), int(tile_w)
 
     @property
     def n_species(self):

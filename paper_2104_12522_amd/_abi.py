@@ -31,6 +31,7 @@ class BmModel(C.Structure):
         ("planet", BmPlanet),
         ("tau_max", C.c_double), ("nu_start", C.c_double), ("dnu", C.c_double),
         ("rayleigh", C.c_int32), ("cloud", C.c_int32), ("geometry", C.c_int32), ("pad2", C.c_int32),
+        ("sigma_tiles", C.c_void_p), ("tile_w", C.c_int32), ("pad3", C.c_int32),
     ]
 
 
@@ -86,6 +87,8 @@ PROTOTYPES = {
     "bm_transit_depth": (_I, [_VP, _VP, _I, _I, _I, _D, _VP, _VP]),
     "bm_bin_chi2": (_I, [_VP, _I, _I, _I, _VP, _VP, _VP, _VP, _VP]),
     "bm_workspace_size": (C.c_size_t, [_PM, _I, C.POINTER(C.c_int32), _I]),
+    "bm_sigma_tiles_bytes": (C.c_size_t, [_PM, _I]),
+    "bm_sigma_tiles": (_I, [_PM, _I, C.c_void_p, C.c_size_t, C.c_void_p]),
     "bm_forward_batch": (_I, [_PM, _I, C.POINTER(C.c_int32), _VP, _I, _I, _VP, _VP, _VP, _VP, _VP,
                               _VP, C.c_size_t, _VP]),
     "bm_forward_config_count": (_I, []),

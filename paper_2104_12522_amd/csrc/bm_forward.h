@@ -49,6 +49,7 @@ __device__ __forceinline__ double lane_get(double v, int i) {
 // Device view of a bm_model (passed by value in kernel arguments).
 struct ModelDev {
     const void* sigma;
+    const void* sigma_tiles;  // tile-major copy [S][NT][tiles][L][64] for tile width tile_w, or null
     const double* temp;
     const double* cia;
     const double* temp_cia;
@@ -57,6 +58,7 @@ struct ModelDev {
     const double* err;
     int S, NT, L, Nnu, NTc, tp_mode, bin_width, nb;
     int rayleigh, cloud, geometry;
+    int tile_w;  // tile width of sigma_tiles
     double mass[BM_MAX_SPECIES];
     bm_planet pl;
     double tau_max;  // optical-depth limit (+infinity: none)

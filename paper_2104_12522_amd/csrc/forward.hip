@@ -184,6 +184,7 @@ int validate_model(const bm_model& m, bool need_tables) {
     if (m.geometry != BM_GEOM_TRANSIT && m.geometry != BM_GEOM_ECLIPSE) return BM_EINVAL;
     if (m.geometry == BM_GEOM_ECLIPSE && (m.cloud || m.tau_max > 0.0 || !(m.dnu > 0.0) || !(m.nu_start > 0.0)))
         return BM_EINVAL;
+    if (m.sigma_tiles && (m.tile_w < 1 || m.tile_w > kTileNu)) return BM_EINVAL;
     return BM_OK;
 }
 
@@ -212,7 +213,35 @@ ModelDev to_device_view(const bm_model& m) {
     d.rayleigh = m.rayleigh ? 1 : 0;
     d.cloud = m.cloud ? 1 : 0;
     d.geometry = m.geometry;
+    d.sigma_tiles = m.sigma_tiles;
+    d.tile_w = m.sigma_tiles ? m.tile_w : 0;
     return d;
+}
+
+// ---- tile-major copy of the opacity tables ---------------------------------------------
+// out[s][k][t][l][c] = sigma[s][k][l][min(t tw + c, Nnu - 1)]: one element per thread,
+// consecutive threads write consecutive elements.
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_sigma_tiles(const T* __restrict__ sigma, int L, int Nnu, int tw, int n_tiles, size_t n_rows,
+                  T* __restrict__ out) {
+    const size_t total = n_rows * (size_t)n_tiles * L * kTileNu;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (size_t)gridDim.x * 256) {
+        const int c = (int)(i % kTileNu);
+        size_t q = i / kTileNu;
+        const int l = (int)(q % L);
+        q /= L;
+        const int t = (int)(q % n_tiles);
+        const size_t sk = q / n_tiles;  // species-major (species, temperature) row index
+        const int nu = min(t * tw + c, Nnu - 1);
+        out[i] = sigma[(sk * L + l) * (size_t)Nnu + nu];
+    }
+}
+
+static size_t sigma_tiles_bytes(const bm_model& m, int tile_w) {
+    const size_t n_tiles = (size_t)(m.n_nu + tile_w - 1) / tile_w;
+    return (size_t)m.n_species * m.n_temp * n_tiles * m.n_layers * kTileNu *
+           (m.dtype == BM_F32 ? sizeof(float) : sizeof(double));
 }
 
 static size_t record_bytes(const bm_model& m, int tiles) {
@@ -683,6 +712,33 @@ extern "C" size_t bm_workspace_size(const bm_model* models, int n_models, const 
     HostPlan hp;
     if (build_plans(models, n_models, instance, B, hp) != BM_OK) return 0;
     return hp.ws_bytes;
+}
+
+extern "C" size_t bm_sigma_tiles_bytes(const bm_model* model, int tile_w) {
+    if (!model || validate_model(*model, true) != BM_OK || tile_w < 1 || tile_w > kTileNu) return 0;
+    return sigma_tiles_bytes(*model, tile_w);
+}
+
+extern "C" int bm_sigma_tiles(const bm_model* model, int tile_w, void* out, size_t out_bytes, void* stream) {
+    if (!model || !out) return BM_EINVAL;
+    const int v = validate_model(*model, true);
+    if (v != BM_OK) return v;
+    if (tile_w < 1 || tile_w > kTileNu) return BM_EINVAL;
+    const size_t need = sigma_tiles_bytes(*model, tile_w);
+    if (out_bytes < need) return BM_ENOSPACE;
+    const int n_tiles = (model->n_nu + tile_w - 1) / tile_w;
+    const size_t n_rows = (size_t)model->n_species * model->n_temp;
+    const size_t total = n_rows * (size_t)n_tiles * model->n_layers * kTileNu;
+    const unsigned grid = (unsigned)std::min<size_t>((total + 255) / 256, 1u << 16);
+    hipStream_t st = (hipStream_t)stream;
+    if (model->dtype == BM_F32)
+        hipLaunchKernelGGL(k_sigma_tiles<float>, dim3(grid), dim3(256), 0, st, static_cast<const float*>(model->sigma),
+                           model->n_layers, model->n_nu, tile_w, n_tiles, n_rows, static_cast<float*>(out));
+    else
+        hipLaunchKernelGGL(k_sigma_tiles<double>, dim3(grid), dim3(256), 0, st, static_cast<const double*>(model->sigma),
+                           model->n_layers, model->n_nu, tile_w, n_tiles, n_rows, static_cast<double*>(out));
+    BM_CHECK_HIP(hipGetLastError());
+    return BM_OK;
 }
 
 extern "C" int bm_forward_batch(const bm_model* models, int n_models, const int32_t* instance,

@@ -120,7 +120,34 @@ __device__ __forceinline__ double chord_fraction(int j, int jcl, F tau, double t
     return j <= jcl ? 1.0 : opaque_fraction(tau, tau_max);
 }
 
-template <typename T, int kWaves, int kS, bool kCia, bool kNonTemporal, int kMode>
+// Record fields of the pipelined path, one layer per lane: lane i holds stage i / 2, layer
+// Ltop - 16 (i / 2 + 1) + 2 wave + i % 2 (clamped to the model). The bracket indices are
+// clamped into the tables, so that a record flagged for a failed radius solve still loads
+// in bounds (its depth is set to NaN at the end).
+template <typename T, int kS, bool kCia>
+struct PipeFields {
+    int k = 0, kc = 0;
+    T w, rf, a[kS];
+    double wc = 0.0, b = 0.0;
+    __device__ __forceinline__ void load(const RecordView<T>& rec, int L, int Ltop, int wave, int lane,
+                                         int nt, int ntc) {
+        const int l = max(0, min(Ltop - kMfmaM * (lane / 2 + 1) + 2 * wave + (lane & 1), L - 1));
+        k = min(max(rec.kidx[l], 0), nt - 2);
+        w = rec.w[l];
+        rf = rec.rfac[l];
+#pragma unroll
+        for (int i = 0; i < kS; ++i) a[i] = rec.afac[i * L + l];
+        if constexpr (kCia) {
+            kc = min(max(rec.kcidx[l], 0), ntc - 2);
+            wc = rec.wc[l];
+            b = rec.bfac[l];
+        }
+    }
+};
+
+// kSingle: the launch holds one run of samples whose model is in slot 0, so the segment and
+// model fields sit at fixed argument offsets and are read without a dependent lookup
+template <typename T, int kWaves, int kS, bool kCia, bool kNonTemporal, int kMode, bool kSingle = false>
 __global__ void __launch_bounds__(kWaves * kWave)
     k_forward(LaunchPlan plan, char* __restrict__ ws, const int32_t* __restrict__ active,
               double* __restrict__ depth, double* __restrict__ binned, double* __restrict__ chi2) {
@@ -132,9 +159,9 @@ __global__ void __launch_bounds__(kWaves * kWave)
     __shared__ __align__(16) float wa_s[kStageA ? StageSize<kMode>::floats : 1];
     __shared__ __align__(16) float wa_dummy[kStageA ? 4 * kWave : 1];
     static_assert(!kStageA || (kWaves == 8 && sizeof(T) == 4), "staging is laid out for 8 FP32 waves");
-    const int si = plan.segment_of_wg(blockIdx.x);
+    const int si = kSingle ? 0 : plan.segment_of_wg(blockIdx.x);
     const Segment& sg = plan.seg[si];
-    const ModelDev& m = plan.model[sg.model];
+    const ModelDev& m = plan.model[kSingle ? 0 : sg.model];
     // XCD-aware order: workgroup g runs on XCD g % 8; each XCD sweeps its own contiguous
     // tile range and runs all samples of a tile back to back (shared table rows in L2)
     const int g = blockIdx.x - sg.tile_begin;
@@ -156,6 +183,17 @@ __global__ void __launch_bounds__(kWaves * kWave)
     const bool valid = lane < sg.tile_w && nu < Nnu;
     const int nu_c = valid ? nu : min(tile * sg.tile_w, Nnu - 1);
 
+    // Table rows: row (species i, temperature k, layer l) of this lane's column sits at
+    // tab + i s_stride + k t_stride + l l_stride. The tile-major copy (when built for this
+    // tile width) holds the tile's rows as one contiguous block of 64-column rows, the
+    // row-major tables as pieces of Nnu-long rows.
+    const bool tiled = m.sigma_tiles != nullptr && m.tile_w == sg.tile_w;
+    const T* __restrict__ tab = tiled ? static_cast<const T*>(m.sigma_tiles) + (size_t)tile * L * kTileNu + lane
+                                      : static_cast<const T*>(m.sigma) + nu_c;
+    const size_t l_stride = tiled ? (size_t)kTileNu : (size_t)Nnu;
+    const size_t t_stride = tiled ? (size_t)sg.tiles * L * kTileNu : (size_t)L * Nnu;
+    const size_t s_stride = (size_t)m.NT * t_stride;
+
     T* es = reinterpret_cast<T*>(smem + lay.es);
     double* part = reinterpret_cast<double*>(smem + lay.part);
     double* dsh = reinterpret_cast<double*>(smem + lay.bins);
@@ -168,23 +206,13 @@ __global__ void __launch_bounds__(kWaves * kWave)
     const T sray = m.rayleigh ? (T)rayleigh_h2_xsec(m.nu_start + m.dnu * nu_c) : T(0);
     double dval = __builtin_nan("");  // this lane's depth (wave 0)
 
-    if (!(flags & BM_FLAG_RADIUS)) {
-        if constexpr (kStageA && sizeof(T) == 4) {
-            // chord-weight fragments record -> LDS without passing through registers
-            // (global_load_lds: lane i of a wave writes 16 bytes at dst + 16 i). Every wave
-            // issues the same fixed number of copies, so the compiler's memory-counter waits
-            // stay exact; copies past the sample's fragments reread chunk 0 into a dummy
-            // LDS row. They overlap the prologue's loads and are complete at its barrier.
-            const int n_chunks = mfma_total_ksteps(L) * kWave / (4 * kWave);  // <= StageSize::chunks
-#pragma unroll
-            for (int i = 0; i < StageSize<kMode>::chunks_per_wave; ++i) {
-                const int q = wave + kWaves * i;
-                const bool real = q < n_chunks;
-                const float* src = rec.wb + (real ? q : 0) * 4 * kWave + 4 * lane;
-                float* dst = real ? wa_s + q * 4 * kWave : wa_dummy;
-                __builtin_amdgcn_global_load_lds((const void*)src, (lds_void_ptr)dst, 16, 0, 0);
-            }
-        }
+    // The pipelined path does not wait for the header before its loads: a flagged sample
+    // runs the same in-bounds loads and gets NaN depths at the end. Its record fields, on
+    // which the first table addresses depend, are issued before the fragment copies (loads
+    // return in issue order, so waiting for them does not wait for the copies).
+    if (kPipe || !(flags & BM_FLAG_RADIUS)) {
+        PipeFields<T, kS, kCia> pf;
+        if constexpr (kPipe) pf.load(rec, L, kPipeMaxLayers, wave, lane, m.NT, m.NTc);
         // impact-parameter weights (read per optical depth in phase 2) and this tile's
         // columns of every CIA temperature row (read by many layers) go to LDS; all their
         // loads are issued before the first store
@@ -209,6 +237,31 @@ __global__ void __launch_bounds__(kWaves * kWave)
                 if (i < n) cia_s[i] = cv[q];
             }
         };
+        // pipelined path: these loads go before the fragment copies too, so that their LDS
+        // stores (before the first barrier) do not wait for the copies
+        double cwv = 0.0;
+        if constexpr (kPipe) {
+            static_assert(kPipeMaxLayers <= kWaves * kWave, "one impact-parameter weight per thread");
+            cwv = rec.cw[min((int)threadIdx.x, L - 1)];
+            if constexpr (kCia) cia_load();
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (kStageA && sizeof(T) == 4) {
+            // chord-weight fragments record -> LDS without passing through registers
+            // (global_load_lds: lane i of a wave writes 16 bytes at dst + 16 i). Every wave
+            // issues the same fixed number of copies, so the compiler's memory-counter waits
+            // stay exact; copies past the sample's fragments reread chunk 0 into a dummy
+            // LDS row. They overlap the prologue's loads and are complete at its barrier.
+            const int n_chunks = mfma_total_ksteps(L) * kWave / (4 * kWave);  // <= StageSize::chunks
+#pragma unroll
+            for (int i = 0; i < StageSize<kMode>::chunks_per_wave; ++i) {
+                const int q = wave + kWaves * i;
+                const bool real = q < n_chunks;
+                const float* src = rec.wb + (real ? q : 0) * 4 * kWave + 4 * lane;
+                float* dst = real ? wa_s + q * 4 * kWave : wa_dummy;
+                __builtin_amdgcn_global_load_lds((const void*)src, (lds_void_ptr)dst, 16, 0, 0);
+            }
+        }
         if constexpr (!kPipe) {
             for (int i = threadIdx.x; i < L; i += kWaves * kWave) cw_s[i] = rec.cw[i];
             if constexpr (kCia) {
@@ -227,9 +280,6 @@ __global__ void __launch_bounds__(kWaves * kWave)
             // of the two following stages are in flight, then runs the matrix-core chunks of its
             // (row block, column group) items; the stages' layers are disjoint, so one barrier
             // per stage orders the extinction rows before their use.
-            const T* __restrict__ sig = static_cast<const T*>(m.sigma);
-            const size_t t_stride = (size_t)L * Nnu;
-            const size_t s_stride = (size_t)m.NT * t_stride;
             // a fixed number of stages (layers up to kPipeMaxLayers), so that the stage loop
             // unrolls into straight-line code and the memory-counter waits stay exact; stages
             // above the model's top rows (Lk = 16 ceil(L/16)) only reissue valid table loads
@@ -237,27 +287,11 @@ __global__ void __launch_bounds__(kWaves * kWave)
             constexpr int Ltop = kPipeMaxLayers;
             const int Lk = kMfmaM * ((L + kMfmaM - 1) / kMfmaM);
             const int nJ = mfma_row_blocks(L);
-            // the prologue's own loads first (see below)
-            static_assert(kPipeMaxLayers <= kWaves * kWave, "one impact-parameter weight per thread");
-            const double cwv = rec.cw[min((int)threadIdx.x, L - 1)];
-            if constexpr (kCia) cia_load();
-            __builtin_amdgcn_sched_barrier(0);
-            // record fields of this wave's layers, one per lane: lane i <-> stage i / 2,
-            // layer lo + 2 wave + i % 2 (clamped; only lanes below 2S are used)
-            const int my_l = max(0, min(Ltop - kMfmaM * (lane / 2 + 1) + 2 * wave + (lane & 1), L - 1));
-            const int r_k = rec.kidx[my_l];
-            const T r_w = rec.w[my_l];
-            const T r_rf = rec.rfac[my_l];
-            T r_a[kS];
-#pragma unroll
-            for (int i = 0; i < kS; ++i) r_a[i] = rec.afac[i * L + my_l];
-            int r_kc = 0;
-            double r_wc = 0.0, r_b = 0.0;
-            if constexpr (kCia) {
-                r_kc = rec.kcidx[my_l];
-                r_wc = rec.wc[my_l];
-                r_b = rec.bfac[my_l];
-            }
+            // record fields of this wave's layers (loaded above; only lanes below 2S are used)
+            const int r_k = pf.k, r_kc = pf.kc;
+            const T r_w = pf.w, r_rf = pf.rf;
+            const T(&r_a)[kS] = pf.a;
+            const double r_wc = pf.wc, r_b = pf.b;
             // this wave's items: the q-th is item q * 8 + (q odd ? 7 - wave : wave) of the
             // (J, column group) list, as in the unpipelined snake order
             int koff[4];
@@ -277,7 +311,7 @@ __global__ void __launch_bounds__(kWaves * kWave)
 #pragma unroll
                 for (int u = 0; u < 2; ++u) {
                     const int l = min(Ltop - kMfmaM * (st + 1) + 2 * wave + u, L - 1);
-                    const T* p = sig + (size_t)lane_get(r_k, 2 * st + u) * t_stride + (size_t)l * Nnu + nu_c;
+                    const T* p = tab + (size_t)lane_get(r_k, 2 * st + u) * t_stride + (size_t)l * l_stride;
 #pragma unroll
                     for (int i = 0; i < kS; ++i) {
                         v0[u][i] = ld_table<T, kNonTemporal>(p + i * s_stride);
@@ -379,16 +413,13 @@ __global__ void __launch_bounds__(kWaves * kWave)
                 double sum = rec.hdr->base;
                 if (jcl >= L - 1) sum += cw_s[L - 1];  // the top chord lies in the deck
                 for (int J = 0; J < nJ; ++J) sum += part[J * kTileNu + lane];
-                dval = sum / rec.hdr->rs2;
+                dval = (flags & BM_FLAG_RADIUS) ? __builtin_nan("") : sum / rec.hdr->rs2;
             }
         } else {
         // ---- phase 1: extinction into LDS --------------------------------------------
         // wave w owns layers [w*per, (w+1)*per). Their record fields are loaded once, one
         // layer per lane, and broadcast with v_readlane, so the table loads of a group of
         // four layers are issued back to back without waiting on memory for addresses.
-        const T* __restrict__ sig = static_cast<const T*>(m.sigma);
-        const size_t t_stride = (size_t)L * Nnu;
-        const size_t s_stride = (size_t)m.NT * t_stride;
         const int per = (L + kWaves - 1) / kWaves;
         const int lb = wave * per;
         const int le = min(L, lb + per);
@@ -412,7 +443,7 @@ __global__ void __launch_bounds__(kWaves * kWave)
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int uu = min(l0 + u, le - 1) - lb;
-                const T* p = sig + (size_t)lane_get(r_k, uu) * t_stride + (size_t)(lb + uu) * Nnu + nu_c;
+                const T* p = tab + (size_t)lane_get(r_k, uu) * t_stride + (size_t)(lb + uu) * l_stride;
 #pragma unroll
                 for (int i = 0; i < kS; ++i) {
                     s0[u][i] = ld_table<T, kNonTemporal>(p + i * s_stride);
@@ -594,12 +625,30 @@ int launch_k_forward(const HostPlan& hp, const LaunchPlan& lp, size_t lds, char*
                             hipEvent_t ev1) {
     const dim3 grid(lp.total_wgs), block(kW * kWave);
     int code = BM_OK;
+    // one run of samples (pipelined modes): its model moves to slot 0
+    constexpr bool kHasSingle = kMode == kModePipelined;
+    const bool single = kHasSingle && lp.n_seg == 1;
+    LaunchPlan lp1 = lp;
+    if (single) {
+        lp1.model[0] = lp.model[lp.seg[0].model];
+        lp1.seg[0].model = 0;
+    }
     switch (hp.n_species) {
-#define BM_FWD_LAUNCH(NS, CIA)                                                                     \
-    code = ensure_dynamic_lds((const void*)k_forward<T, kW, NS, CIA, kNT, kMode>, lds);            \
+#define BM_FWD_GO(NS, CIA, SINGLE, PLAN)                                                          \
+    code = ensure_dynamic_lds((const void*)k_forward<T, kW, NS, CIA, kNT, kMode, SINGLE>, lds);    \
     if (code != BM_OK) return code;                                                                \
-    hipExtLaunchKernelGGL((k_forward<T, kW, NS, CIA, kNT, kMode>), grid, block, lds, st, ev0, ev1, 0, lp, ws, act, \
-                          depth, binned, c2);
+    hipExtLaunchKernelGGL((k_forward<T, kW, NS, CIA, kNT, kMode, SINGLE>), grid, block, lds, st, ev0, ev1, 0, PLAN, \
+                          ws, act, depth, binned, c2);
+#define BM_FWD_LAUNCH(NS, CIA)                 \
+    if constexpr (kHasSingle) {                \
+        if (single) {                          \
+            BM_FWD_GO(NS, CIA, kHasSingle, lp1) \
+        } else {                               \
+            BM_FWD_GO(NS, CIA, false, lp)      \
+        }                                      \
+    } else {                                   \
+        BM_FWD_GO(NS, CIA, false, lp)          \
+    }
 #define BM_FWD_CASE(NS)              \
     case NS:                         \
         if (hp.cia) {                \
@@ -612,6 +661,7 @@ int launch_k_forward(const HostPlan& hp, const LaunchPlan& lp, size_t lds, char*
         BM_FWD_CASE(5) BM_FWD_CASE(6) BM_FWD_CASE(7) BM_FWD_CASE(8)
 #undef BM_FWD_CASE
 #undef BM_FWD_LAUNCH
+#undef BM_FWD_GO
         default: return BM_ESHAPE;
     }
     BM_CHECK_HIP(hipGetLastError());

@@ -24,7 +24,7 @@ def config1_table(n_nu=1000, seed=12):
     return s, sigma
 
 
-def gpu_model(setup, sigma, cia=None, data=None, err=None, device="cuda", cia_he=None):
+def gpu_model(setup, sigma, cia=None, data=None, err=None, device="cuda", cia_he=None, tiles=True):
     import torch
     import paper_2104_12522_amd as bm
     return bm.Model(torch.as_tensor(sigma), setup.temps, setup.p_bar, setup.mass_amu,
@@ -35,7 +35,7 @@ def gpu_model(setup, sigma, cia=None, data=None, err=None, device="cuda", cia_he
                     tau_max=setup.tau_max, nu_start=float(setup.nu[0]),
                     dnu=float(setup.nu[1] - setup.nu[0]) if setup.nu.size > 1 else 1.0,
                     rayleigh=setup.rayleigh, cloud=setup.cloud, geometry=setup.geometry,
-                    cia_he=None if cia_he is None else torch.as_tensor(cia_he))
+                    cia_he=None if cia_he is None else torch.as_tensor(cia_he), tiles=tiles)
 
 
 def prior_for(setup):

@@ -93,3 +93,27 @@ def test_binding_struct_layouts_match_the_library(lib):
     for which, cls in enumerate((_abi.BmPlanet, _abi.BmModel, _abi.BmDemcz, _abi.BmMlp, _abi.BmVoigtGrid)):
         assert lib.bm_struct_size(which) == C.sizeof(cls), cls.__name__
     assert lib.bm_struct_size(99) == 0
+
+
+def test_sigma_tiles_size_and_argument_errors(lib):
+    # host logic only: the size of the tile-major copy and the checks made before any launch
+    from paper_2104_12522_amd import _abi
+    lib.bm_sigma_tiles_bytes.restype = C.c_size_t
+    lib.bm_sigma_tiles_bytes.argtypes = [C.POINTER(_abi.BmModel), C.c_int]
+    lib.bm_sigma_tiles.argtypes = [C.POINTER(_abi.BmModel), C.c_int, C.c_void_p, C.c_size_t, C.c_void_p]
+    m = _abi.BmModel()
+    m.dtype, m.n_species, m.n_temp, m.n_layers, m.n_nu = _abi.BM_F32, 4, 20, 100, 995
+    m.tp_mode = 1
+    m.sigma = m.temp = m.p_bar = 16          # never dereferenced by these calls
+    for tw, n_tiles in ((60, 17), (64, 16), (1, 995), (7, 143)):
+        assert lib.bm_sigma_tiles_bytes(C.byref(m), tw) == 4 * 20 * n_tiles * 100 * 64 * 4
+    assert lib.bm_sigma_tiles_bytes(C.byref(m), 0) == 0
+    assert lib.bm_sigma_tiles_bytes(C.byref(m), 65) == 0
+    need = lib.bm_sigma_tiles_bytes(C.byref(m), 60)
+    assert lib.bm_sigma_tiles(C.byref(m), 60, C.c_void_p(16), need - 1, None) == -4   # BM_ENOSPACE
+    assert lib.bm_sigma_tiles(C.byref(m), 65, C.c_void_p(16), need, None) == -1       # BM_EINVAL
+    assert lib.bm_sigma_tiles(C.byref(m), 60, None, need, None) == -1
+    m.dtype = _abi.BM_F64
+    assert lib.bm_sigma_tiles_bytes(C.byref(m), 60) == 2 * need
+    m.n_layers = 1
+    assert lib.bm_sigma_tiles_bytes(C.byref(m), 60) == 0                             # bad model

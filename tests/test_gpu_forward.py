@@ -487,3 +487,84 @@ def test_emission_rejects_transit_only_options():
     model = gpu_model(s, sigma)
     with pytest.raises(bm.BartmiError):
         bm.forward_batch(model, torch.as_tensor(np.array([[1200.0, -4.0, 1.14]]), device="cuda"))
+
+
+# ------------------------------------------------------------------------- tile-major tables
+@pytest.mark.parametrize("n_nu,tw", [(130, 60), (130, 64), (129, 7), (61, 1), (995, 60)])
+def test_sigma_tiles_copy_is_exact(n_nu, tw):
+    # out[s][k][t][l][c] = sigma[s][k][l][min(t tw + c, Nnu - 1)], element for element
+    s, sigma, cia = small_config2(n_nu=n_nu, n_layers=17, seed=50)
+    model = gpu_model(s, sigma, cia, tiles=False)
+    model.build_tiles(tw)
+    torch.cuda.synchronize()
+    S, NT, L, N = sigma.shape
+    n_tiles = -(-N // tw)
+    nu = np.minimum(np.arange(n_tiles)[:, None] * tw + np.arange(64)[None, :], N - 1)   # [t][c]
+    want = sigma[:, :, :, nu].transpose(0, 1, 3, 2, 4)                                  # [s][k][t][l][c]
+    got = _np(model.sigma_tiles).reshape(S, NT, n_tiles, L, 64)
+    assert np.array_equal(got, want)
+    assert model.struct.tile_w == tw
+
+
+def _all_configs(model, params, binned, chi2):
+    f = bm.Forward(model, params.shape[0], binned=binned, chi2=chi2)
+    outs = []
+    for c in range(len(bm.forward_configs())):
+        f.set_config(c)
+        f(params)
+        outs.append([t.clone() for t in (f.depth, f.binned, f.chi2, f.flags) if t is not None])
+    f.set_config(-1)
+    torch.cuda.synchronize()
+    return outs
+
+
+@pytest.mark.parametrize("n_nu,L,B", [(995, 100, 1), (995, 100, 3), (900, 70, 2), (130, 130, 2), (61, 17, 1)])
+def test_tiled_tables_give_identical_results(n_nu, L, B):
+    # the tile-major copy holds the same values, so every launch configuration gives the
+    # same depth, channels, chi^2 and flags bit for bit with and without it (binned calls
+    # use the copy; unbinned calls have tile width 64 and read the row-major tables)
+    s, sigma, cia = small_config2(n_nu=n_nu, n_layers=L, seed=60 + L)
+    nb = s.nu.size // s.bin_width
+    data, err = np.full(nb, 0.02), np.full(nb, 6e-5)
+    params = torch.as_tensor(prior_for(s).draw(B, seed=61), device="cuda")
+    plain = gpu_model(s, sigma, cia, data=data, err=err, tiles=False)
+    tiled = gpu_model(s, sigma, cia, data=data, err=err)
+    assert tiled.sigma_tiles is not None and tiled.struct.tile_w == 60
+    for binned in (True, False):
+        a = _all_configs(plain, params, binned, binned)
+        b = _all_configs(tiled, params, binned, binned)
+        for c, (x, y) in enumerate(zip(a, b)):
+            for u, v in zip(x, y):
+                assert torch.equal(u, v), (binned, c)
+    # and against the oracle (binned call, default configuration)
+    f = bm.Forward(tiled, B, binned=True, chi2=True)
+    f(params)
+    for b_ in range(B):
+        ref = ort.forward(_np(params[b_]), s, sigma.astype(np.float64), cia, data=data, err=err)
+        sl = slice(int(f.depth_off[b_]), int(f.depth_off[b_ + 1]))
+        np.testing.assert_allclose(_np(f.depth[sl]), ref["depth"], rtol=1e-4)
+
+
+def test_tiled_tables_fp64_and_mixed_instances():
+    # FP64 (config 1 shapes, no channels: tile width 64) and a mixed batch of two
+    # instances, each with its own copy, against the row-major tables
+    s, sigma = config1_table(n_nu=1000)
+    params = torch.as_tensor(np.array([wl.config1_params(), [1500.0, -3.0, 1.25]]), device="cuda")
+    outs = []
+    for tiles in (False, True):
+        model = gpu_model(s, sigma, None, tiles=tiles)
+        f = bm.forward_batch(model, params, binned=False, chi2=False)
+        torch.cuda.synchronize()
+        outs.append(f.depth.clone())
+    assert torch.equal(outs[0], outs[1])
+    inst = [(60, 800), (100, 995)]
+    setups = [small_config2(n_nu=n, n_layers=L, seed=70 + L) for L, n in inst]
+    params_np = wl.line2013_prior(4).draw(4, seed=71)
+    res = []
+    for tiles in (False, True):
+        models = [gpu_model(st, sg, ci, tiles=tiles) for st, sg, ci in setups]
+        f = bm.Forward(models, 4, instance=[0, 1, 1, 0], binned=True)
+        f(torch.as_tensor(params_np, device="cuda"))
+        torch.cuda.synchronize()
+        res.append((f.depth.clone(), f.binned.clone()))
+    assert torch.equal(res[0][0], res[1][0]) and torch.equal(res[0][1], res[1][1])

@@ -161,11 +161,16 @@ class Prior:
         return self.lo + (self.hi - self.lo) * g.random((n, self.lo.size))
 
 
-def line2013_prior(n_species: int) -> Prior:
+def line2013_prior(n_species: int, alpha_max: float = 1.0) -> Prior:
     """Parameters: log10 kappa, log10 gamma1, log10 gamma2, alpha, beta,
-    log10 x_i (n_species), R_ref / R_J."""
+    log10 x_i (n_species), R_ref / R_J.
+
+    The profile is unchanged by exchanging the two visible streams, (gamma1, gamma2, alpha)
+    -> (gamma2, gamma1, 1 - alpha), and gamma1 and gamma2 share one range, so with
+    alpha in [0, 1] every posterior has a mirror mode. alpha_max = 0.5 labels the streams
+    (the one with weight 1 - alpha >= alpha is stream 1) and keeps every profile."""
     lo = np.array([-3.0, -1.5, -1.5, 0.0, 0.6] + [-8.0] * n_species + [1.0])
-    hi = np.array([0.0, 1.0, 1.0, 1.0, 1.2] + [-2.0] * n_species + [1.3])
+    hi = np.array([0.0, 1.0, 1.0, alpha_max, 1.2] + [-2.0] * n_species + [1.3])
     return Prior(lo, hi)
 
 
