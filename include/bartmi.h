@@ -235,11 +235,12 @@ size_t bm_workspace_size(const bm_model* models, int n_models, const int32_t* in
                          int B);
 /* Tile-major copy of a model's opacity tables (the same values as sigma, rearranged).
  * bm_forward_batch's fused kernel reads the tables in tiles of tile_w consecutive
- * wavenumbers, one 64-wide column block per tile; in the row-major [S][NT][L][Nnu] layout
- * each (species, temperature, layer) row piece of a tile is a separate short read, which
- * the copy turns into one contiguous block per tile:
+ * wavenumbers; in the row-major [S][NT][L][Nnu] layout each (species, temperature, layer)
+ * row piece of a tile is a separate short read, which the copy turns into one contiguous
+ * block per tile:
  *   out[s][k][t][l][c] = sigma[s][k][l][min(t tile_w + c, Nnu - 1)],
- *   t < n_tiles = ceil(Nnu / tile_w), c < 64, element type model->dtype.
+ *   t < n_tiles = ceil(Nnu / tile_w), c < tile_w, element type model->dtype
+ * (the size of sigma, plus the ragged tail's padding).
  * bm_sigma_tiles_bytes gives the size (0 on invalid arguments); bm_sigma_tiles writes
  * `out` (device, caller-owned, out_bytes >= that size) on `stream` from model->sigma.
  * Set model->sigma_tiles = out and model->tile_w = tile_w to use it; the fused kernel

@@ -90,8 +90,8 @@ class Model:
                  tiles: bool = True):
         """cia_he: an H2-He CIA table on the CIA temperature grid; it is folded into the
         H2-H2 table once here (bm_cia_combine), since n_He / n_H2 is fixed by the filler
-        split. tiles: also keep a tile-major copy of the tables (bm_sigma_tiles, 64/60 of the
-        table size for 30-point channels) for the tile width of binned calls,
+        split. tiles: also keep a tile-major copy of the tables (bm_sigma_tiles, the table's
+        size) for the tile width of binned calls,
         floor(64 / bin_width) bin_width (64 without channels); the fused kernel reads it
         for calls with that tile width (transit geometry)."""
         if sigma.dim() != 4:

@@ -219,16 +219,16 @@ ModelDev to_device_view(const bm_model& m) {
 }
 
 // ---- tile-major copy of the opacity tables ---------------------------------------------
-// out[s][k][t][l][c] = sigma[s][k][l][min(t tw + c, Nnu - 1)]: one element per thread,
-// consecutive threads write consecutive elements.
+// out[s][k][t][l][c] = sigma[s][k][l][min(t tw + c, Nnu - 1)], c < tw: one element per
+// thread, consecutive threads write consecutive elements.
 template <typename T>
 __global__ void __launch_bounds__(256)
     k_sigma_tiles(const T* __restrict__ sigma, int L, int Nnu, int tw, int n_tiles, size_t n_rows,
                   T* __restrict__ out) {
-    const size_t total = n_rows * (size_t)n_tiles * L * kTileNu;
+    const size_t total = n_rows * (size_t)n_tiles * L * tw;
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (size_t)gridDim.x * 256) {
-        const int c = (int)(i % kTileNu);
-        size_t q = i / kTileNu;
+        const int c = (int)(i % tw);
+        size_t q = i / tw;
         const int l = (int)(q % L);
         q /= L;
         const int t = (int)(q % n_tiles);
@@ -240,7 +240,7 @@ __global__ void __launch_bounds__(256)
 
 static size_t sigma_tiles_bytes(const bm_model& m, int tile_w) {
     const size_t n_tiles = (size_t)(m.n_nu + tile_w - 1) / tile_w;
-    return (size_t)m.n_species * m.n_temp * n_tiles * m.n_layers * kTileNu *
+    return (size_t)m.n_species * m.n_temp * n_tiles * m.n_layers * tile_w *
            (m.dtype == BM_F32 ? sizeof(float) : sizeof(double));
 }
 
@@ -728,7 +728,7 @@ extern "C" int bm_sigma_tiles(const bm_model* model, int tile_w, void* out, size
     if (out_bytes < need) return BM_ENOSPACE;
     const int n_tiles = (model->n_nu + tile_w - 1) / tile_w;
     const size_t n_rows = (size_t)model->n_species * model->n_temp;
-    const size_t total = n_rows * (size_t)n_tiles * model->n_layers * kTileNu;
+    const size_t total = n_rows * (size_t)n_tiles * model->n_layers * tile_w;
     const unsigned grid = (unsigned)std::min<size_t>((total + 255) / 256, 1u << 16);
     hipStream_t st = (hipStream_t)stream;
     if (model->dtype == BM_F32)

@@ -185,13 +185,15 @@ __global__ void __launch_bounds__(kWaves * kWave)
 
     // Table rows: row (species i, temperature k, layer l) of this lane's column sits at
     // tab + i s_stride + k t_stride + l l_stride. The tile-major copy (when built for this
-    // tile width) holds the tile's rows as one contiguous block of 64-column rows, the
-    // row-major tables as pieces of Nnu-long rows.
-    const bool tiled = m.sigma_tiles != nullptr && m.tile_w == sg.tile_w;
-    const T* __restrict__ tab = tiled ? static_cast<const T*>(m.sigma_tiles) + (size_t)tile * L * kTileNu + lane
+    // tile width) holds the tile's rows as one contiguous block of tile_w-column rows, the
+    // row-major tables as pieces of Nnu-long rows. Lanes past the tile reread its last
+    // column (no extra lines fetched).
+    const int tw = sg.tile_w;
+    const bool tiled = m.sigma_tiles != nullptr && m.tile_w == tw;
+    const T* __restrict__ tab = tiled ? static_cast<const T*>(m.sigma_tiles) + (size_t)tile * L * tw + min(lane, tw - 1)
                                       : static_cast<const T*>(m.sigma) + nu_c;
-    const size_t l_stride = tiled ? (size_t)kTileNu : (size_t)Nnu;
-    const size_t t_stride = tiled ? (size_t)sg.tiles * L * kTileNu : (size_t)L * Nnu;
+    const size_t l_stride = tiled ? (size_t)tw : (size_t)Nnu;
+    const size_t t_stride = tiled ? (size_t)sg.tiles * L * tw : (size_t)L * Nnu;
     const size_t s_stride = (size_t)m.NT * t_stride;
 
     T* es = reinterpret_cast<T*>(smem + lay.es);

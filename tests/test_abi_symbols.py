@@ -106,7 +106,7 @@ def test_sigma_tiles_size_and_argument_errors(lib):
     m.tp_mode = 1
     m.sigma = m.temp = m.p_bar = 16          # never dereferenced by these calls
     for tw, n_tiles in ((60, 17), (64, 16), (1, 995), (7, 143)):
-        assert lib.bm_sigma_tiles_bytes(C.byref(m), tw) == 4 * 20 * n_tiles * 100 * 64 * 4
+        assert lib.bm_sigma_tiles_bytes(C.byref(m), tw) == 4 * 20 * n_tiles * 100 * tw * 4
     assert lib.bm_sigma_tiles_bytes(C.byref(m), 0) == 0
     assert lib.bm_sigma_tiles_bytes(C.byref(m), 65) == 0
     need = lib.bm_sigma_tiles_bytes(C.byref(m), 60)

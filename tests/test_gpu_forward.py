@@ -492,16 +492,16 @@ def test_emission_rejects_transit_only_options():
 # ------------------------------------------------------------------------- tile-major tables
 @pytest.mark.parametrize("n_nu,tw", [(130, 60), (130, 64), (129, 7), (61, 1), (995, 60)])
 def test_sigma_tiles_copy_is_exact(n_nu, tw):
-    # out[s][k][t][l][c] = sigma[s][k][l][min(t tw + c, Nnu - 1)], element for element
+    # out[s][k][t][l][c] = sigma[s][k][l][min(t tw + c, Nnu - 1)], c < tw, element for element
     s, sigma, cia = small_config2(n_nu=n_nu, n_layers=17, seed=50)
     model = gpu_model(s, sigma, cia, tiles=False)
     model.build_tiles(tw)
     torch.cuda.synchronize()
     S, NT, L, N = sigma.shape
     n_tiles = -(-N // tw)
-    nu = np.minimum(np.arange(n_tiles)[:, None] * tw + np.arange(64)[None, :], N - 1)   # [t][c]
+    nu = np.minimum(np.arange(n_tiles)[:, None] * tw + np.arange(tw)[None, :], N - 1)   # [t][c]
     want = sigma[:, :, :, nu].transpose(0, 1, 3, 2, 4)                                  # [s][k][t][l][c]
-    got = _np(model.sigma_tiles).reshape(S, NT, n_tiles, L, 64)
+    got = _np(model.sigma_tiles).reshape(S, NT, n_tiles, L, tw)
     assert np.array_equal(got, want)
     assert model.struct.tile_w == tw
 
