@@ -202,6 +202,7 @@ struct HostPlan {
     std::vector<int> first_sample;   // first sample of each plan
     std::vector<int> n_samples;      // samples of each plan
     size_t ws_bytes = 0;
+    size_t list_off = 0;      // workspace offset of the requested-sample list (B + 1 int32)
     int max_L = 0;
     int n_species = 0;
     bool cia = false;

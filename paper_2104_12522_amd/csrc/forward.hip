@@ -17,6 +17,7 @@ namespace bm {
 #define BM_FWD_EXTERN(T, W, NT, MODE)                                                                  \
     extern template int launch_k_forward<T, W, NT, MODE>(const HostPlan&, const LaunchPlan&, size_t, char*, \
                                                           const int32_t*, double*, double*, double*,      \
+                                                          const int32_t*, const int32_t*, int,            \
                                                           hipStream_t, hipEvent_t, hipEvent_t);
 BM_FWD_EXTERN(float, 8, true, 1)
 BM_FWD_EXTERN(float, 8, true, 0)
@@ -324,9 +325,43 @@ static int build_plans(const bm_model* models, int n_models, const int32_t* inst
         hp.first_sample.push_back(first_of_plan);
         hp.n_samples.push_back(b - first_of_plan);
     }
-    hp.ws_bytes = ws;
+    // the list of requested samples of a masked call (k_active_list), then its count
+    hp.list_off = align_up(ws, 256);
+    hp.ws_bytes = hp.list_off + sizeof(int32_t) * ((size_t)B + 1);
     hp.total_samples = B;
     return BM_OK;
+}
+
+// Masked calls of one run of samples: the requested samples' indices in ascending order,
+// list[0 .. n), and n = list[B], written by one workgroup (a ballot scan per block of
+// 1024 samples), so that the forward kernel's grid can cover a few sample slots per tile
+// instead of every sample. Graph-safe: it writes every entry it later reads.
+constexpr int kCompactSlots = 16;
+__global__ void __launch_bounds__(1024)
+    k_active_list(const int32_t* __restrict__ active, int B, int32_t* __restrict__ list) {
+    __shared__ int wsum[1024 / kWave];
+    __shared__ int base;
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    if (threadIdx.x == 0) base = 0;
+    __syncthreads();
+    for (int b0 = 0; b0 < B; b0 += 1024) {
+        const int b = b0 + threadIdx.x;
+        const bool on = b < B && active[b] != 0;
+        const unsigned long long bal = __ballot(on);
+        if (lane == 0) wsum[w] = __popcll(bal);
+        __syncthreads();
+        int off = base;
+        for (int q = 0; q < w; ++q) off += wsum[q];
+        if (on) list[off + __popcll(bal & ((1ull << lane) - 1))] = b;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int t = 0;
+            for (int q = 0; q < 1024 / kWave; ++q) t += wsum[q];
+            base += t;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) list[B] = base;
 }
 
 // Launch configurations of the fused forward kernel that the autotuner chooses from:
@@ -440,6 +475,18 @@ static int launch_forward(const HostPlan& hp, int cfg, const double* params, int
     if (!fits(cfg)) cfg = config_with_mode(cfg, kModeStreamed);
     if (!fits(cfg)) return BM_ESHAPE;
     const size_t lds = forward_lds_bytes<T>(hp.max_L, kFwdConfigs[cfg].waves, hp.max_ntc, kFwdConfigs[cfg].mode);
+    // a masked transit call of one run of samples launches the forward kernel over the list
+    // of requested samples (kCompactSlots slots per tile) instead of every sample
+    const int B = hp.total_samples;
+    const bool compact = active && hp.geometry == BM_GEOM_TRANSIT && hp.plans.size() == 1 &&
+                         hp.plans[0].n_seg == 1 && B > kCompactSlots;
+    int32_t* list = compact ? reinterpret_cast<int32_t*>(ws + hp.list_off) : nullptr;
+    if (compact) {
+        hipLaunchKernelGGL(k_active_list, dim3(1), dim3(1024), 0, st, active, B, list);
+        BM_CHECK_HIP(hipGetLastError());
+    }
+    const int32_t* list_n = compact ? list + B : nullptr;
+    const int slots = compact ? kCompactSlots : 0;
     for (size_t p = 0; p < hp.plans.size(); ++p) {
         const LaunchPlan& lp = hp.plans[p];
         const int b0 = hp.first_sample[p];
@@ -478,9 +525,11 @@ static int launch_forward(const HostPlan& hp, int cfg, const double* params, int
         hipEvent_t e0, e1;
         timing_slot(st, &e0, &e1);
         if constexpr (sizeof(T) == 8) {
-            code = launch_k_forward<T, 8, true, kModeStreamed>(hp, lp, lds, ws, act, depth, binned, c2, st, e0, e1);
+            code = launch_k_forward<T, 8, true, kModeStreamed>(hp, lp, lds, ws, act, depth, binned, c2, list, list_n,
+                                                              slots, st, e0, e1);
         } else {
-#define BM_CFG(NT, MODE) launch_k_forward<T, 8, NT, MODE>(hp, lp, lds, ws, act, depth, binned, c2, st, e0, e1)
+#define BM_CFG(NT, MODE) \
+    launch_k_forward<T, 8, NT, MODE>(hp, lp, lds, ws, act, depth, binned, c2, list, list_n, slots, st, e0, e1)
             switch (cfg) {
                 case 1: code = BM_CFG(false, kModeStaged); break;
                 case 2: code = BM_CFG(true, kModeStreamed); break;

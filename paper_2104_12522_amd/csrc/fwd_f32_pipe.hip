@@ -4,9 +4,11 @@
 
 namespace bm {
 template int launch_k_forward<float, 8, true, 2>(const HostPlan&, const LaunchPlan&, size_t, char*,
-                                                   const int32_t*, double*, double*, double*, hipStream_t,
+                                                   const int32_t*, double*, double*, double*, const int32_t*,
+                                                   const int32_t*, int, hipStream_t,
                                                    hipEvent_t, hipEvent_t);
 template int launch_k_forward<float, 8, false, 2>(const HostPlan&, const LaunchPlan&, size_t, char*,
-                                                   const int32_t*, double*, double*, double*, hipStream_t,
+                                                   const int32_t*, double*, double*, double*, const int32_t*,
+                                                   const int32_t*, int, hipStream_t,
                                                    hipEvent_t, hipEvent_t);
 }  // namespace bm

@@ -150,7 +150,8 @@ struct PipeFields {
 template <typename T, int kWaves, int kS, bool kCia, bool kNonTemporal, int kMode, bool kSingle = false>
 __global__ void __launch_bounds__(kWaves * kWave)
     k_forward(LaunchPlan plan, char* __restrict__ ws, const int32_t* __restrict__ active,
-              double* __restrict__ depth, double* __restrict__ binned, double* __restrict__ chi2) {
+              double* __restrict__ depth, double* __restrict__ binned, double* __restrict__ chi2,
+              const int32_t* __restrict__ compact, const int32_t* __restrict__ compact_count, int compact_slots) {
     constexpr bool kStageA = kMode != kModeStreamed;
     constexpr bool kPipe = kMode == kModePipelined;
     extern __shared__ __align__(16) char smem[];
@@ -163,469 +164,482 @@ __global__ void __launch_bounds__(kWaves * kWave)
     const Segment& sg = plan.seg[si];
     const ModelDev& m = plan.model[kSingle ? 0 : sg.model];
     // XCD-aware order: workgroup g runs on XCD g % 8; each XCD sweeps its own contiguous
-    // tile range and runs all samples of a tile back to back (shared table rows in L2)
+    // tile range and runs all samples of a tile back to back (shared table rows in L2).
+    // A compacted launch (a masked call of one run of samples: compact lists the requested
+    // samples, compact_count[0] of them) has compact_slots sample slots per tile, and
+    // workgroup (tile, slot k) takes list entries k, k + slots, ... in turn, so that a call
+    // that requests few samples launches few workgroups.
+    const int slots = compact ? compact_slots : sg.count;
     const int g = blockIdx.x - sg.tile_begin;
     const int kx = g / kXcds;
-    const int tile = (g % kXcds) * sg.tiles_per_xcd + kx / sg.count;
-    const int s_in = kx % sg.count;
+    const int tile = (g % kXcds) * sg.tiles_per_xcd + kx / slots;
+    const int slot = kx % slots;
     if (tile >= sg.tiles) return;  // padding workgroup of the XCD split
-    const int b = sg.first + s_in;
-    if (active && !active[b]) return;  // sample not requested in this call
-    const int L = m.L, Nnu = m.Nnu;
-    const RecordView<T> rec(ws + sg.ws_off + (size_t)s_in * sg.rec_bytes, kS, L);
-    const FwdLds<T> lay(L, kWaves, plan.max_ntc, kPipe);
+    const int n_items = compact ? *compact_count : slot + 1;
+    for (int q = slot; q < n_items; q += slots) {
+        if (q != slot) __syncthreads();  // the previous sample's LDS reads are done
+        const int s_in = compact ? compact[q] - sg.first : q;
+        const int b = sg.first + s_in;
+        if (active && !active[b]) continue;  // sample not requested in this call
+        const int L = m.L, Nnu = m.Nnu;
+        const RecordView<T> rec(ws + sg.ws_off + (size_t)s_in * sg.rec_bytes, kS, L);
+        const FwdLds<T> lay(L, kWaves, plan.max_ntc, kPipe);
 
-    const int lane = threadIdx.x & (kWave - 1);
-    // the wave index is uniform across a wave; readfirstlane lets the compiler keep the
-    // layer loops and every per-layer record load on the scalar unit
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    const int nu = tile * sg.tile_w + lane;
-    const bool valid = lane < sg.tile_w && nu < Nnu;
-    const int nu_c = valid ? nu : min(tile * sg.tile_w, Nnu - 1);
+        const int lane = threadIdx.x & (kWave - 1);
+        // the wave index is uniform across a wave; readfirstlane lets the compiler keep the
+        // layer loops and every per-layer record load on the scalar unit
+        const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+        const int nu = tile * sg.tile_w + lane;
+        const bool valid = lane < sg.tile_w && nu < Nnu;
+        const int nu_c = valid ? nu : min(tile * sg.tile_w, Nnu - 1);
 
-    // Table rows: row (species i, temperature k, layer l) of this lane's column sits at
-    // tab + i s_stride + k t_stride + l l_stride. The tile-major copy (when built for this
-    // tile width) holds the tile's rows as one contiguous block of tile_w-column rows, the
-    // row-major tables as pieces of Nnu-long rows. Lanes past the tile reread its last
-    // column (no extra lines fetched).
-    const int tw = sg.tile_w;
-    const bool tiled = m.sigma_tiles != nullptr && m.tile_w == tw;
-    const T* __restrict__ tab = tiled ? static_cast<const T*>(m.sigma_tiles) + (size_t)tile * L * tw + min(lane, tw - 1)
-                                      : static_cast<const T*>(m.sigma) + nu_c;
-    const size_t l_stride = tiled ? (size_t)tw : (size_t)Nnu;
-    const size_t t_stride = tiled ? (size_t)sg.tiles * L * tw : (size_t)L * Nnu;
-    const size_t s_stride = (size_t)m.NT * t_stride;
+        // Table rows: row (species i, temperature k, layer l) of this lane's column sits at
+        // tab + i s_stride + k t_stride + l l_stride. The tile-major copy (when built for this
+        // tile width) holds the tile's rows as one contiguous block of tile_w-column rows, the
+        // row-major tables as pieces of Nnu-long rows. Lanes past the tile reread its last
+        // column (no extra lines fetched).
+        const int tw = sg.tile_w;
+        const bool tiled = m.sigma_tiles != nullptr && m.tile_w == tw;
+        const T* __restrict__ tab = tiled ? static_cast<const T*>(m.sigma_tiles) + (size_t)tile * L * tw + min(lane, tw - 1)
+                                          : static_cast<const T*>(m.sigma) + nu_c;
+        const size_t l_stride = tiled ? (size_t)tw : (size_t)Nnu;
+        const size_t t_stride = tiled ? (size_t)sg.tiles * L * tw : (size_t)L * Nnu;
+        const size_t s_stride = (size_t)m.NT * t_stride;
 
-    T* es = reinterpret_cast<T*>(smem + lay.es);
-    double* part = reinterpret_cast<double*>(smem + lay.part);
-    double* dsh = reinterpret_cast<double*>(smem + lay.bins);
-    double* dout = depth + sg.depth_off + (size_t)s_in * Nnu;
-    const int flags = rec.hdr->flags;
-    const int jcl = m.cloud ? rec.hdr->jcloud : -1;  // chords j <= jcl are opaque (cloud deck)
-    // this lane's H2 Rayleigh cross section (the record holds n_H2 per layer); zero without
-    // Rayleigh scattering, so that the per-layer term needs no branch (a branch in the
-    // extinction loop cost 16 % at 256 samples per launch)
-    const T sray = m.rayleigh ? (T)rayleigh_h2_xsec(m.nu_start + m.dnu * nu_c) : T(0);
-    double dval = __builtin_nan("");  // this lane's depth (wave 0)
+        T* es = reinterpret_cast<T*>(smem + lay.es);
+        double* part = reinterpret_cast<double*>(smem + lay.part);
+        double* dsh = reinterpret_cast<double*>(smem + lay.bins);
+        double* dout = depth + sg.depth_off + (size_t)s_in * Nnu;
+        const int flags = rec.hdr->flags;
+        const int jcl = m.cloud ? rec.hdr->jcloud : -1;  // chords j <= jcl are opaque (cloud deck)
+        // this lane's H2 Rayleigh cross section (the record holds n_H2 per layer); zero without
+        // Rayleigh scattering, so that the per-layer term needs no branch (a branch in the
+        // extinction loop cost 16 % at 256 samples per launch)
+        const T sray = m.rayleigh ? (T)rayleigh_h2_xsec(m.nu_start + m.dnu * nu_c) : T(0);
+        double dval = __builtin_nan("");  // this lane's depth (wave 0)
 
-    // The pipelined path does not wait for the header before its loads: a flagged sample
-    // runs the same in-bounds loads and gets NaN depths at the end. Its record fields, on
-    // which the first table addresses depend, are issued before the fragment copies (loads
-    // return in issue order, so waiting for them does not wait for the copies).
-    if (kPipe || !(flags & BM_FLAG_RADIUS)) {
-        PipeFields<T, kS, kCia> pf;
-        if constexpr (kPipe) pf.load(rec, L, kPipeMaxLayers, wave, lane, m.NT, m.NTc);
-        // impact-parameter weights (read per optical depth in phase 2) and this tile's
-        // columns of every CIA temperature row (read by many layers) go to LDS; all their
-        // loads are issued before the first store
-        double* cw_s = reinterpret_cast<double*>(smem + lay.cw);
-        double* cia_s = reinterpret_cast<double*>(smem + lay.ciat);
-        constexpr int kMaxPer = BM_MAX_TEMPS * kTileNu / (kWaves * kWave);
-        double cv[kMaxPer];
-        auto cia_load = [&]() {
-            const int n = m.NTc * kTileNu;
-#pragma unroll
-            for (int q = 0; q < kMaxPer; ++q) {
-                const int i = min((int)threadIdx.x + q * kWaves * kWave, n - 1);
-                const int col = min(tile * sg.tile_w + (i % kTileNu), Nnu - 1);
-                cv[q] = m.cia[(size_t)(i / kTileNu) * Nnu + col];
-            }
-        };
-        auto cia_store = [&]() {
-            const int n = m.NTc * kTileNu;
-#pragma unroll
-            for (int q = 0; q < kMaxPer; ++q) {
-                const int i = threadIdx.x + q * kWaves * kWave;
-                if (i < n) cia_s[i] = cv[q];
-            }
-        };
-        // pipelined path: these loads go before the fragment copies too, so that their LDS
-        // stores (before the first barrier) do not wait for the copies
-        double cwv = 0.0;
-        if constexpr (kPipe) {
-            static_assert(kPipeMaxLayers <= kWaves * kWave, "one impact-parameter weight per thread");
-            cwv = rec.cw[min((int)threadIdx.x, L - 1)];
-            if constexpr (kCia) cia_load();
-        }
-        __builtin_amdgcn_sched_barrier(0);
-        if constexpr (kStageA && sizeof(T) == 4) {
-            // chord-weight fragments record -> LDS without passing through registers
-            // (global_load_lds: lane i of a wave writes 16 bytes at dst + 16 i). Every wave
-            // issues the same fixed number of copies, so the compiler's memory-counter waits
-            // stay exact; copies past the sample's fragments reread chunk 0 into a dummy
-            // LDS row. They overlap the prologue's loads and are complete at its barrier.
-            const int n_chunks = mfma_total_ksteps(L) * kWave / (4 * kWave);  // <= StageSize::chunks
-#pragma unroll
-            for (int i = 0; i < StageSize<kMode>::chunks_per_wave; ++i) {
-                const int q = wave + kWaves * i;
-                const bool real = q < n_chunks;
-                const float* src = rec.wb + (real ? q : 0) * 4 * kWave + 4 * lane;
-                float* dst = real ? wa_s + q * 4 * kWave : wa_dummy;
-                __builtin_amdgcn_global_load_lds((const void*)src, (lds_void_ptr)dst, 16, 0, 0);
-            }
-        }
-        if constexpr (!kPipe) {
-            for (int i = threadIdx.x; i < L; i += kWaves * kWave) cw_s[i] = rec.cw[i];
-            if constexpr (kCia) {
-                cia_load();
-                cia_store();
-            }
-            __syncthreads();
-        }
-
-        if constexpr (kPipe) {
-            // ---- phases 1 and 2 interleaved over stages of 16 layers, from the top ----------
-            // Stage s holds layers [lo_s, lo_s + 16), lo_s = Ltop - 16 (s + 1).
-            // Every row block J with 16 J <= lo_s takes one chunk (4 k-steps, the stage's
-            // layers) from it, and is complete after the stage with lo_s = 16 J. Wave w
-            // computes the extinction of layers lo_s + 2w and lo_s + 2w + 1 while the table rows
-            // of the two following stages are in flight, then runs the matrix-core chunks of its
-            // (row block, column group) items; the stages' layers are disjoint, so one barrier
-            // per stage orders the extinction rows before their use.
-            // a fixed number of stages (layers up to kPipeMaxLayers), so that the stage loop
-            // unrolls into straight-line code and the memory-counter waits stay exact; stages
-            // above the model's top rows (Lk = 16 ceil(L/16)) only reissue valid table loads
-            constexpr int kStages = kPipeMaxLayers / kMfmaM;
-            constexpr int Ltop = kPipeMaxLayers;
-            const int Lk = kMfmaM * ((L + kMfmaM - 1) / kMfmaM);
-            const int nJ = mfma_row_blocks(L);
-            // record fields of this wave's layers (loaded above; only lanes below 2S are used)
-            const int r_k = pf.k, r_kc = pf.kc;
-            const T r_w = pf.w, r_rf = pf.rf;
-            const T(&r_a)[kS] = pf.a;
-            const double r_wc = pf.wc, r_b = pf.b;
-            // this wave's items: the q-th is item q * 8 + (q odd ? 7 - wave : wave) of the
-            // (J, column group) list, as in the unpipelined snake order
-            int koff[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int it = q * kWaves + ((q & 1) ? (kWaves - 1 - wave) : wave);
-                koff[q] = (it < 4 * nJ) ? mfma_kstep_offset(L, it >> 2) : 0;
-            }
-            floatx4 acc[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) acc[q] = floatx4{0.f, 0.f, 0.f, 0.f};
-            T va0[2][kS], va1[2][kS], vb0[2][kS], vb1[2][kS];
-
-            // table rows of stage s for this wave's two layers (padding layers reread the last
-            // layer's rows, so every wave issues the same loads and the counters stay exact)
-            auto issue = [&](int st, T (&v0)[2][kS], T (&v1)[2][kS]) {
-#pragma unroll
-                for (int u = 0; u < 2; ++u) {
-                    const int l = min(Ltop - kMfmaM * (st + 1) + 2 * wave + u, L - 1);
-                    const T* p = tab + (size_t)lane_get(r_k, 2 * st + u) * t_stride + (size_t)l * l_stride;
-#pragma unroll
-                    for (int i = 0; i < kS; ++i) {
-                        v0[u][i] = ld_table<T, kNonTemporal>(p + i * s_stride);
-                        v1[u][i] = ld_table<T, kNonTemporal>(p + i * s_stride + t_stride);
-                    }
+        // The pipelined path does not wait for the header before its loads: a flagged sample
+        // runs the same in-bounds loads and gets NaN depths at the end. Its record fields, on
+        // which the first table addresses depend, are issued before the fragment copies (loads
+        // return in issue order, so waiting for them does not wait for the copies).
+        if (kPipe || !(flags & BM_FLAG_RADIUS)) {
+            PipeFields<T, kS, kCia> pf;
+            if constexpr (kPipe) pf.load(rec, L, kPipeMaxLayers, wave, lane, m.NT, m.NTc);
+            // impact-parameter weights (read per optical depth in phase 2) and this tile's
+            // columns of every CIA temperature row (read by many layers) go to LDS; all their
+            // loads are issued before the first store
+            double* cw_s = reinterpret_cast<double*>(smem + lay.cw);
+            double* cia_s = reinterpret_cast<double*>(smem + lay.ciat);
+            constexpr int kMaxPer = BM_MAX_TEMPS * kTileNu / (kWaves * kWave);
+            double cv[kMaxPer];
+            auto cia_load = [&]() {
+                const int n = m.NTc * kTileNu;
+    #pragma unroll
+                for (int q = 0; q < kMaxPer; ++q) {
+                    const int i = min((int)threadIdx.x + q * kWaves * kWave, n - 1);
+                    const int col = min(tile * sg.tile_w + (i % kTileNu), Nnu - 1);
+                    cv[q] = m.cia[(size_t)(i / kTileNu) * Nnu + col];
                 }
             };
-            auto extinction = [&](int st, const T (&v0)[2][kS], const T (&v1)[2][kS]) {
-#pragma unroll
-                for (int u = 0; u < 2; ++u) {
-                    const int l = Ltop - kMfmaM * (st + 1) + 2 * wave + u;
-                    if (l < L) {
-                        const int i = 2 * st + u;
-                        const T w = lane_get(r_w, i);
-                        T e = T(0);
-#pragma unroll
-                        for (int sp = 0; sp < kS; ++sp)
-                            e = fma(lane_get(r_a[sp], i), fma(w, v1[u][sp] - v0[u][sp], v0[u][sp]), e);
-                        if constexpr (kCia) {
-                            const double* c = cia_s + lane_get(r_kc, i) * kTileNu + lane;
-                            e += (T)(lane_get(r_b, i) * fma(lane_get(r_wc, i), c[kTileNu] - c[0], c[0]));
+            auto cia_store = [&]() {
+                const int n = m.NTc * kTileNu;
+    #pragma unroll
+                for (int q = 0; q < kMaxPer; ++q) {
+                    const int i = threadIdx.x + q * kWaves * kWave;
+                    if (i < n) cia_s[i] = cv[q];
+                }
+            };
+            // pipelined path: these loads go before the fragment copies too, so that their LDS
+            // stores (before the first barrier) do not wait for the copies
+            double cwv = 0.0;
+            if constexpr (kPipe) {
+                static_assert(kPipeMaxLayers <= kWaves * kWave, "one impact-parameter weight per thread");
+                cwv = rec.cw[min((int)threadIdx.x, L - 1)];
+                if constexpr (kCia) cia_load();
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            if constexpr (kStageA && sizeof(T) == 4) {
+                // chord-weight fragments record -> LDS without passing through registers
+                // (global_load_lds: lane i of a wave writes 16 bytes at dst + 16 i). Every wave
+                // issues the same fixed number of copies, so the compiler's memory-counter waits
+                // stay exact; copies past the sample's fragments reread chunk 0 into a dummy
+                // LDS row. They overlap the prologue's loads and are complete at its barrier.
+                const int n_chunks = mfma_total_ksteps(L) * kWave / (4 * kWave);  // <= StageSize::chunks
+    #pragma unroll
+                for (int i = 0; i < StageSize<kMode>::chunks_per_wave; ++i) {
+                    const int q = wave + kWaves * i;
+                    const bool real = q < n_chunks;
+                    const float* src = rec.wb + (real ? q : 0) * 4 * kWave + 4 * lane;
+                    float* dst = real ? wa_s + q * 4 * kWave : wa_dummy;
+                    __builtin_amdgcn_global_load_lds((const void*)src, (lds_void_ptr)dst, 16, 0, 0);
+                }
+            }
+            if constexpr (!kPipe) {
+                for (int i = threadIdx.x; i < L; i += kWaves * kWave) cw_s[i] = rec.cw[i];
+                if constexpr (kCia) {
+                    cia_load();
+                    cia_store();
+                }
+                __syncthreads();
+            }
+
+            if constexpr (kPipe) {
+                // ---- phases 1 and 2 interleaved over stages of 16 layers, from the top ----------
+                // Stage s holds layers [lo_s, lo_s + 16), lo_s = Ltop - 16 (s + 1).
+                // Every row block J with 16 J <= lo_s takes one chunk (4 k-steps, the stage's
+                // layers) from it, and is complete after the stage with lo_s = 16 J. Wave w
+                // computes the extinction of layers lo_s + 2w and lo_s + 2w + 1 while the table rows
+                // of the two following stages are in flight, then runs the matrix-core chunks of its
+                // (row block, column group) items; the stages' layers are disjoint, so one barrier
+                // per stage orders the extinction rows before their use.
+                // a fixed number of stages (layers up to kPipeMaxLayers), so that the stage loop
+                // unrolls into straight-line code and the memory-counter waits stay exact; stages
+                // above the model's top rows (Lk = 16 ceil(L/16)) only reissue valid table loads
+                constexpr int kStages = kPipeMaxLayers / kMfmaM;
+                constexpr int Ltop = kPipeMaxLayers;
+                const int Lk = kMfmaM * ((L + kMfmaM - 1) / kMfmaM);
+                const int nJ = mfma_row_blocks(L);
+                // record fields of this wave's layers (loaded above; only lanes below 2S are used)
+                const int r_k = pf.k, r_kc = pf.kc;
+                const T r_w = pf.w, r_rf = pf.rf;
+                const T(&r_a)[kS] = pf.a;
+                const double r_wc = pf.wc, r_b = pf.b;
+                // this wave's items: the q-th is item q * 8 + (q odd ? 7 - wave : wave) of the
+                // (J, column group) list, as in the unpipelined snake order
+                int koff[4];
+    #pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int it = q * kWaves + ((q & 1) ? (kWaves - 1 - wave) : wave);
+                    koff[q] = (it < 4 * nJ) ? mfma_kstep_offset(L, it >> 2) : 0;
+                }
+                floatx4 acc[4];
+    #pragma unroll
+                for (int q = 0; q < 4; ++q) acc[q] = floatx4{0.f, 0.f, 0.f, 0.f};
+                T va0[2][kS], va1[2][kS], vb0[2][kS], vb1[2][kS];
+
+                // table rows of stage s for this wave's two layers (padding layers reread the last
+                // layer's rows, so every wave issues the same loads and the counters stay exact)
+                auto issue = [&](int st, T (&v0)[2][kS], T (&v1)[2][kS]) {
+    #pragma unroll
+                    for (int u = 0; u < 2; ++u) {
+                        const int l = min(Ltop - kMfmaM * (st + 1) + 2 * wave + u, L - 1);
+                        const T* p = tab + (size_t)lane_get(r_k, 2 * st + u) * t_stride + (size_t)l * l_stride;
+    #pragma unroll
+                        for (int i = 0; i < kS; ++i) {
+                            v0[u][i] = ld_table<T, kNonTemporal>(p + i * s_stride);
+                            v1[u][i] = ld_table<T, kNonTemporal>(p + i * s_stride + t_stride);
                         }
-                        e = fma(lane_get(r_rf, i), sray, e);  // sray = 0 without Rayleigh
+                    }
+                };
+                auto extinction = [&](int st, const T (&v0)[2][kS], const T (&v1)[2][kS]) {
+    #pragma unroll
+                    for (int u = 0; u < 2; ++u) {
+                        const int l = Ltop - kMfmaM * (st + 1) + 2 * wave + u;
+                        if (l < L) {
+                            const int i = 2 * st + u;
+                            const T w = lane_get(r_w, i);
+                            T e = T(0);
+    #pragma unroll
+                            for (int sp = 0; sp < kS; ++sp)
+                                e = fma(lane_get(r_a[sp], i), fma(w, v1[u][sp] - v0[u][sp], v0[u][sp]), e);
+                            if constexpr (kCia) {
+                                const double* c = cia_s + lane_get(r_kc, i) * kTileNu + lane;
+                                e += (T)(lane_get(r_b, i) * fma(lane_get(r_wc, i), c[kTileNu] - c[0], c[0]));
+                            }
+                            e = fma(lane_get(r_rf, i), sray, e);  // sray = 0 without Rayleigh
+                            es[es_index<T>(l, lane)] = e;
+                        }
+                    }
+                };
+                auto chunks = [&](int st) {
+                    const int lo = Ltop - kMfmaM * (st + 1);
+                    float a[4][kMfmaChunk], bv[4][kMfmaChunk];
+    #pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int it = q * kWaves + ((q & 1) ? (kWaves - 1 - wave) : wave);
+                        const int J = it >> 2, col = it & 3;
+                        if (it < 4 * nJ && kMfmaM * J <= lo && lo < Lk) {
+                            const float* wa = wa_s + (size_t)(koff[q] + (lo - kMfmaM * J) / kMfmaK) * kWave + lane;
+    #pragma unroll
+                            for (int u = 0; u < kMfmaChunk; ++u) {
+                                a[q][u] = wa[u * kWave];
+                                bv[q][u] = es[es_index<T>(lo + kMfmaK * u + (lane >> 4), col * 16 + (lane & 15))];
+                            }
+                        }
+                    }
+    #pragma unroll
+                    for (int u = 0; u < kMfmaChunk; ++u)
+    #pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const int it = q * kWaves + ((q & 1) ? (kWaves - 1 - wave) : wave);
+                            if (it < 4 * nJ && kMfmaM * (it >> 2) <= lo && lo < Lk)
+                                acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[q][u], bv[q][u], acc[q], 0, 0, 0);
+                        }
+                    // row blocks completed by this stage: 1 - exp(-tau), impact-parameter weights
+    #pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int it = q * kWaves + ((q & 1) ? (kWaves - 1 - wave) : wave);
+                        const int J = it >> 2, col = it & 3;
+                        if (it < 4 * nJ && kMfmaM * J == lo) {
+                            double pp = 0.0;
+    #pragma unroll
+                            for (int r = 0; r < 4; ++r) {
+                                const int j = kMfmaM * J + 4 * (lane >> 4) + r;
+                                if (j <= L - 2) pp += cw_s[j] * chord_fraction(j, jcl, acc[q][r], m.tau_max);
+                            }
+                            pp += __shfl_xor(pp, 16);
+                            pp += __shfl_xor(pp, 32);
+                            if (lane < 16) part[J * kTileNu + col * 16 + (lane & 15)] = pp;
+                        }
+                    }
+                };
+
+                // prologue: the fragment copies (issued first), the impact-parameter weights, the
+                // CIA columns, the record fields and the first two stages' table rows are all in
+                // flight before the first wait. Vector-memory loads return in issue order, so once
+                // a wave has waited for its stage-0 rows its fragment copies have landed too.
+                issue(0, va0, va1);
+                issue(1, vb0, vb1);
+                // keep the stage loads ahead of the waits that the LDS stores below need
+                __builtin_amdgcn_sched_barrier(0);
+                if ((int)threadIdx.x < L) cw_s[threadIdx.x] = cwv;
+                if constexpr (kCia) cia_store();
+                // zero rows past the last layer (read by the top stages against zero weights)
+                for (int i = threadIdx.x; i < (lay.es_rows - L) * kTileNu; i += kWaves * kWave) es[L * kTileNu + i] = T(0);
+                __syncthreads();
+    #pragma unroll
+                for (int st = 0; st < kStages; st += 2) {
+                    extinction(st, va0, va1);
+                    if (st + 2 < kStages) issue(st + 2, va0, va1);
+                    __syncthreads();
+                    chunks(st);
+                    if (st + 1 < kStages) {
+                        extinction(st + 1, vb0, vb1);
+                        if (st + 3 < kStages) issue(st + 3, vb0, vb1);
+                        __syncthreads();
+                        chunks(st + 1);
+                    }
+                }
+                __syncthreads();
+                if (wave == 0) {
+                    double sum = rec.hdr->base;
+                    if (jcl >= L - 1) sum += cw_s[L - 1];  // the top chord lies in the deck
+                    for (int J = 0; J < nJ; ++J) sum += part[J * kTileNu + lane];
+                    dval = (flags & BM_FLAG_RADIUS) ? __builtin_nan("") : sum / rec.hdr->rs2;
+                }
+            } else {
+            // ---- phase 1: extinction into LDS --------------------------------------------
+            // wave w owns layers [w*per, (w+1)*per). Their record fields are loaded once, one
+            // layer per lane, and broadcast with v_readlane, so the table loads of a group of
+            // four layers are issued back to back without waiting on memory for addresses.
+            const int per = (L + kWaves - 1) / kWaves;
+            const int lb = wave * per;
+            const int le = min(L, lb + per);
+            const int mine = min(lb + lane, L - 1);
+            const int r_k = rec.kidx[mine];
+            const T r_w = rec.w[mine];
+            const T r_rf = rec.rfac[mine];
+            T r_a[kS];
+    #pragma unroll
+            for (int i = 0; i < kS; ++i) r_a[i] = rec.afac[i * L + mine];
+            int r_kc = 0;
+            double r_wc = 0.0, r_b = 0.0;
+            if constexpr (kCia) {
+                r_kc = rec.kcidx[mine];
+                r_wc = rec.wc[mine];
+                r_b = rec.bfac[mine];
+            }
+            for (int l0 = lb; l0 < le; l0 += 4) {
+                T s0[4][kS], s1[4][kS];
+                double c0[4], c1[4];
+    #pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int uu = min(l0 + u, le - 1) - lb;
+                    const T* p = tab + (size_t)lane_get(r_k, uu) * t_stride + (size_t)(lb + uu) * l_stride;
+    #pragma unroll
+                    for (int i = 0; i < kS; ++i) {
+                        s0[u][i] = ld_table<T, kNonTemporal>(p + i * s_stride);
+                        s1[u][i] = ld_table<T, kNonTemporal>(p + i * s_stride + t_stride);
+                    }
+                    if constexpr (kCia) {
+                        const double* c = cia_s + lane_get(r_kc, uu) * kTileNu + lane;
+                        c0[u] = c[0];
+                        c1[u] = c[kTileNu];
+                    }
+                }
+    #pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int l = l0 + u;
+                    if (l < le) {
+                        const int uu = l - lb;
+                        const T w = lane_get(r_w, uu);
+                        T e = T(0);
+    #pragma unroll
+                        for (int i = 0; i < kS; ++i)
+                            e = fma(lane_get(r_a[i], uu), fma(w, s1[u][i] - s0[u][i], s0[u][i]), e);
+                        if constexpr (kCia)
+                            e += (T)(lane_get(r_b, uu) * fma(lane_get(r_wc, uu), c1[u] - c0[u], c0[u]));
+                        e = fma(lane_get(r_rf, uu), sray, e);  // sray = 0 without Rayleigh
                         es[es_index<T>(l, lane)] = e;
                     }
                 }
-            };
-            auto chunks = [&](int st) {
-                const int lo = Ltop - kMfmaM * (st + 1);
-                float a[4][kMfmaChunk], bv[4][kMfmaChunk];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int it = q * kWaves + ((q & 1) ? (kWaves - 1 - wave) : wave);
-                    const int J = it >> 2, col = it & 3;
-                    if (it < 4 * nJ && kMfmaM * J <= lo && lo < Lk) {
-                        const float* wa = wa_s + (size_t)(koff[q] + (lo - kMfmaM * J) / kMfmaK) * kWave + lane;
-#pragma unroll
-                        for (int u = 0; u < kMfmaChunk; ++u) {
-                            a[q][u] = wa[u * kWave];
-                            bv[q][u] = es[es_index<T>(lo + kMfmaK * u + (lane >> 4), col * 16 + (lane & 15))];
-                        }
-                    }
-                }
-#pragma unroll
-                for (int u = 0; u < kMfmaChunk; ++u)
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int it = q * kWaves + ((q & 1) ? (kWaves - 1 - wave) : wave);
-                        if (it < 4 * nJ && kMfmaM * (it >> 2) <= lo && lo < Lk)
-                            acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[q][u], bv[q][u], acc[q], 0, 0, 0);
-                    }
-                // row blocks completed by this stage: 1 - exp(-tau), impact-parameter weights
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int it = q * kWaves + ((q & 1) ? (kWaves - 1 - wave) : wave);
-                    const int J = it >> 2, col = it & 3;
-                    if (it < 4 * nJ && kMfmaM * J == lo) {
-                        double pp = 0.0;
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) {
-                            const int j = kMfmaM * J + 4 * (lane >> 4) + r;
-                            if (j <= L - 2) pp += cw_s[j] * chord_fraction(j, jcl, acc[q][r], m.tau_max);
-                        }
-                        pp += __shfl_xor(pp, 16);
-                        pp += __shfl_xor(pp, 32);
-                        if (lane < 16) part[J * kTileNu + col * 16 + (lane & 15)] = pp;
-                    }
-                }
-            };
-
-            // prologue: the fragment copies (issued first), the impact-parameter weights, the
-            // CIA columns, the record fields and the first two stages' table rows are all in
-            // flight before the first wait. Vector-memory loads return in issue order, so once
-            // a wave has waited for its stage-0 rows its fragment copies have landed too.
-            issue(0, va0, va1);
-            issue(1, vb0, vb1);
-            // keep the stage loads ahead of the waits that the LDS stores below need
-            __builtin_amdgcn_sched_barrier(0);
-            if ((int)threadIdx.x < L) cw_s[threadIdx.x] = cwv;
-            if constexpr (kCia) cia_store();
-            // zero rows past the last layer (read by the top stages against zero weights)
-            for (int i = threadIdx.x; i < (lay.es_rows - L) * kTileNu; i += kWaves * kWave) es[L * kTileNu + i] = T(0);
+            }
+            if constexpr (sizeof(T) == 4) {
+                // zero rows past the last layer (read, against zero weights, by padded k-steps)
+                for (int i = threadIdx.x; i < (lay.es_rows - L) * kTileNu; i += kWaves * kWave) es[L * kTileNu + i] = T(0);
+            }
+            if constexpr (kStageA) __builtin_amdgcn_s_waitcnt(0);  // this wave's LDS copies are done
             __syncthreads();
-#pragma unroll
-            for (int st = 0; st < kStages; st += 2) {
-                extinction(st, va0, va1);
-                if (st + 2 < kStages) issue(st + 2, va0, va1);
+
+            // ---- phase 2: chord optical depth, 1 - exp(-tau), impact-parameter sum -------
+            if constexpr (sizeof(T) == 4) {
+                // items (row block J, 16-column group) in decreasing cost, dealt in snake order
+                const int nJ = mfma_row_blocks(L);
+                const int n_items = nJ * 4;
+                for (int it = 0; it < n_items; ++it) {
+                    const int round = it / kWaves, pos = it - round * kWaves;
+                    const int owner = (round & 1) ? (kWaves - 1 - pos) : pos;
+                    if (owner != wave) continue;
+                    const int J = it >> 2, col = it & 3;
+                    const int K = mfma_ksteps(L, J);  // a multiple of kMfmaChunk
+                    const int brow = kMfmaM * J + (lane >> 4);
+                    const int bcol = col * 16 + (lane & 15);
+                    floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+                    floatx4 acc2 = {0.f, 0.f, 0.f, 0.f};
+                    if constexpr (kStageA) {
+                        // A fragments and B from LDS
+                        const float* wa = wa_s + (size_t)mfma_kstep_offset(L, J) * kWave + lane;
+                        for (int ks = 0; ks < K; ks += kMfmaChunk) {
+                            float ac[kMfmaChunk], bv[kMfmaChunk];
+    #pragma unroll
+                            for (int u = 0; u < kMfmaChunk; ++u) {
+                                ac[u] = wa[(ks + u) * kWave];
+                                bv[u] = es[es_index<T>(brow + kMfmaK * (ks + u), bcol)];
+                            }
+    #pragma unroll
+                            for (int u = 0; u < kMfmaChunk; u += 2) {
+                                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ac[u], bv[u], acc, 0, 0, 0);
+                                acc2 = __builtin_amdgcn_mfma_f32_16x16x4f32(ac[u + 1], bv[u + 1], acc2, 0, 0, 0);
+                            }
+                        }
+                    } else {
+                        // A fragments stream from L2 (coalesced, one chunk ahead), B from LDS
+                        const float* ag = rec.wb + (size_t)mfma_kstep_offset(L, J) * kWave + lane;
+                        float an[kMfmaChunk];
+    #pragma unroll
+                        for (int u = 0; u < kMfmaChunk; ++u) an[u] = ag[u * kWave];
+                        for (int ks = 0; ks < K; ks += kMfmaChunk) {
+                            float ac[kMfmaChunk], bv[kMfmaChunk];
+    #pragma unroll
+                            for (int u = 0; u < kMfmaChunk; ++u) {
+                                ac[u] = an[u];
+                                an[u] = ag[min(ks + kMfmaChunk + u, K - 1) * kWave];
+                                bv[u] = es[es_index<T>(brow + kMfmaK * (ks + u), bcol)];
+                            }
+    #pragma unroll
+                            for (int u = 0; u < kMfmaChunk; u += 2) {
+                                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ac[u], bv[u], acc, 0, 0, 0);
+                                acc2 = __builtin_amdgcn_mfma_f32_16x16x4f32(ac[u + 1], bv[u + 1], acc2, 0, 0, 0);
+                            }
+                        }
+                    }
+                    acc += acc2;
+                    // this lane holds rows 16J + 4(lane/16) + r of column bcol
+                    double pp = 0.0;
+    #pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int j = kMfmaM * J + 4 * (lane >> 4) + r;
+                        if (j <= L - 2) pp += cw_s[j] * chord_fraction(j, jcl, acc[r], m.tau_max);
+                    }
+                    pp += __shfl_xor(pp, 16);
+                    pp += __shfl_xor(pp, 32);
+                    if (lane < 16) part[J * kTileNu + bcol] = pp;
+                }
                 __syncthreads();
-                chunks(st);
-                if (st + 1 < kStages) {
-                    extinction(st + 1, vb0, vb1);
-                    if (st + 3 < kStages) issue(st + 3, vb0, vb1);
-                    __syncthreads();
-                    chunks(st + 1);
+                if (wave == 0) {
+                    double s = rec.hdr->base;
+                    if (jcl >= L - 1) s += cw_s[L - 1];
+                    for (int J = 0; J < nJ; ++J) s += part[J * kTileNu + lane];
+                    dval = s / rec.hdr->rs2;
+                }
+            } else {
+                // FP64: vector ALU, 8-row register blocks, chord weights as uniform loads
+                double acc = 0.0;
+                const int nbu = (L - 1 + kRows - 1) / kRows;
+                for (int blk = 0; blk < nbu; ++blk) {
+                    const int round = blk / kWaves, pos = blk - round * kWaves;
+                    const int owner = (round & 1) ? (kWaves - 1 - pos) : pos;
+                    if (owner != wave) continue;
+                    const int j0 = blk * kRows;
+                    T t[kRows];
+    #pragma unroll
+                    for (int r = 0; r < kRows; ++r) t[r] = T(0);
+                    const T* __restrict__ wcol = rec.wb + (size_t)blk * L * kRows;
+                    for (int l = j0; l < L; ++l) {
+                        const T e = es[es_index<T>(l, lane)];
+    #pragma unroll
+                        for (int r = 0; r < kRows; ++r) t[r] = fma(wcol[l * kRows + r], e, t[r]);
+                    }
+    #pragma unroll
+                    for (int r = 0; r < kRows; ++r) {
+                        const int j = j0 + r;
+                        if (j <= L - 2) acc += cw_s[j] * chord_fraction(j, jcl, t[r], m.tau_max);
+                    }
+                }
+                part[wave * kTileNu + lane] = acc;
+                __syncthreads();
+                if (wave == 0) {
+                    double s = rec.hdr->base;
+                    if (jcl >= L - 1) s += cw_s[L - 1];
+                    for (int w2 = 0; w2 < kWaves; ++w2) s += part[w2 * kTileNu + lane];
+                    dval = s / rec.hdr->rs2;
                 }
             }
-            __syncthreads();
-            if (wave == 0) {
-                double sum = rec.hdr->base;
-                if (jcl >= L - 1) sum += cw_s[L - 1];  // the top chord lies in the deck
-                for (int J = 0; J < nJ; ++J) sum += part[J * kTileNu + lane];
-                dval = (flags & BM_FLAG_RADIUS) ? __builtin_nan("") : sum / rec.hdr->rs2;
-            }
-        } else {
-        // ---- phase 1: extinction into LDS --------------------------------------------
-        // wave w owns layers [w*per, (w+1)*per). Their record fields are loaded once, one
-        // layer per lane, and broadcast with v_readlane, so the table loads of a group of
-        // four layers are issued back to back without waiting on memory for addresses.
-        const int per = (L + kWaves - 1) / kWaves;
-        const int lb = wave * per;
-        const int le = min(L, lb + per);
-        const int mine = min(lb + lane, L - 1);
-        const int r_k = rec.kidx[mine];
-        const T r_w = rec.w[mine];
-        const T r_rf = rec.rfac[mine];
-        T r_a[kS];
-#pragma unroll
-        for (int i = 0; i < kS; ++i) r_a[i] = rec.afac[i * L + mine];
-        int r_kc = 0;
-        double r_wc = 0.0, r_b = 0.0;
-        if constexpr (kCia) {
-            r_kc = rec.kcidx[mine];
-            r_wc = rec.wc[mine];
-            r_b = rec.bfac[mine];
+            }  // unpipelined
         }
-        for (int l0 = lb; l0 < le; l0 += 4) {
-            T s0[4][kS], s1[4][kS];
-            double c0[4], c1[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int uu = min(l0 + u, le - 1) - lb;
-                const T* p = tab + (size_t)lane_get(r_k, uu) * t_stride + (size_t)(lb + uu) * l_stride;
-#pragma unroll
-                for (int i = 0; i < kS; ++i) {
-                    s0[u][i] = ld_table<T, kNonTemporal>(p + i * s_stride);
-                    s1[u][i] = ld_table<T, kNonTemporal>(p + i * s_stride + t_stride);
-                }
-                if constexpr (kCia) {
-                    const double* c = cia_s + lane_get(r_kc, uu) * kTileNu + lane;
-                    c0[u] = c[0];
-                    c1[u] = c[kTileNu];
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int l = l0 + u;
-                if (l < le) {
-                    const int uu = l - lb;
-                    const T w = lane_get(r_w, uu);
-                    T e = T(0);
-#pragma unroll
-                    for (int i = 0; i < kS; ++i)
-                        e = fma(lane_get(r_a[i], uu), fma(w, s1[u][i] - s0[u][i], s0[u][i]), e);
-                    if constexpr (kCia)
-                        e += (T)(lane_get(r_b, uu) * fma(lane_get(r_wc, uu), c1[u] - c0[u], c0[u]));
-                    e = fma(lane_get(r_rf, uu), sray, e);  // sray = 0 without Rayleigh
-                    es[es_index<T>(l, lane)] = e;
-                }
-            }
+        if (wave == 0) {
+            if (valid) dout[nu] = dval;
+            dsh[lane] = dval;
         }
-        if constexpr (sizeof(T) == 4) {
-            // zero rows past the last layer (read, against zero weights, by padded k-steps)
-            for (int i = threadIdx.x; i < (lay.es_rows - L) * kTileNu; i += kWaves * kWave) es[L * kTileNu + i] = T(0);
-        }
-        if constexpr (kStageA) __builtin_amdgcn_s_waitcnt(0);  // this wave's LDS copies are done
+
+        // ---- phase 3: channels of this tile; chi^2 partial; last tile sums the partials ----
+        if (binned == nullptr || !sg.fused_bins) continue;
         __syncthreads();
-
-        // ---- phase 2: chord optical depth, 1 - exp(-tau), impact-parameter sum -------
-        if constexpr (sizeof(T) == 4) {
-            // items (row block J, 16-column group) in decreasing cost, dealt in snake order
-            const int nJ = mfma_row_blocks(L);
-            const int n_items = nJ * 4;
-            for (int it = 0; it < n_items; ++it) {
-                const int round = it / kWaves, pos = it - round * kWaves;
-                const int owner = (round & 1) ? (kWaves - 1 - pos) : pos;
-                if (owner != wave) continue;
-                const int J = it >> 2, col = it & 3;
-                const int K = mfma_ksteps(L, J);  // a multiple of kMfmaChunk
-                const int brow = kMfmaM * J + (lane >> 4);
-                const int bcol = col * 16 + (lane & 15);
-                floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-                floatx4 acc2 = {0.f, 0.f, 0.f, 0.f};
-                if constexpr (kStageA) {
-                    // A fragments and B from LDS
-                    const float* wa = wa_s + (size_t)mfma_kstep_offset(L, J) * kWave + lane;
-                    for (int ks = 0; ks < K; ks += kMfmaChunk) {
-                        float ac[kMfmaChunk], bv[kMfmaChunk];
-#pragma unroll
-                        for (int u = 0; u < kMfmaChunk; ++u) {
-                            ac[u] = wa[(ks + u) * kWave];
-                            bv[u] = es[es_index<T>(brow + kMfmaK * (ks + u), bcol)];
-                        }
-#pragma unroll
-                        for (int u = 0; u < kMfmaChunk; u += 2) {
-                            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ac[u], bv[u], acc, 0, 0, 0);
-                            acc2 = __builtin_amdgcn_mfma_f32_16x16x4f32(ac[u + 1], bv[u + 1], acc2, 0, 0, 0);
-                        }
-                    }
-                } else {
-                    // A fragments stream from L2 (coalesced, one chunk ahead), B from LDS
-                    const float* ag = rec.wb + (size_t)mfma_kstep_offset(L, J) * kWave + lane;
-                    float an[kMfmaChunk];
-#pragma unroll
-                    for (int u = 0; u < kMfmaChunk; ++u) an[u] = ag[u * kWave];
-                    for (int ks = 0; ks < K; ks += kMfmaChunk) {
-                        float ac[kMfmaChunk], bv[kMfmaChunk];
-#pragma unroll
-                        for (int u = 0; u < kMfmaChunk; ++u) {
-                            ac[u] = an[u];
-                            an[u] = ag[min(ks + kMfmaChunk + u, K - 1) * kWave];
-                            bv[u] = es[es_index<T>(brow + kMfmaK * (ks + u), bcol)];
-                        }
-#pragma unroll
-                        for (int u = 0; u < kMfmaChunk; u += 2) {
-                            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ac[u], bv[u], acc, 0, 0, 0);
-                            acc2 = __builtin_amdgcn_mfma_f32_16x16x4f32(ac[u + 1], bv[u + 1], acc2, 0, 0, 0);
-                        }
-                    }
-                }
-                acc += acc2;
-                // this lane holds rows 16J + 4(lane/16) + r of column bcol
-                double pp = 0.0;
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int j = kMfmaM * J + 4 * (lane >> 4) + r;
-                    if (j <= L - 2) pp += cw_s[j] * chord_fraction(j, jcl, acc[r], m.tau_max);
-                }
-                pp += __shfl_xor(pp, 16);
-                pp += __shfl_xor(pp, 32);
-                if (lane < 16) part[J * kTileNu + bcol] = pp;
-            }
-            __syncthreads();
-            if (wave == 0) {
-                double s = rec.hdr->base;
-                if (jcl >= L - 1) s += cw_s[L - 1];
-                for (int J = 0; J < nJ; ++J) s += part[J * kTileNu + lane];
-                dval = s / rec.hdr->rs2;
-            }
-        } else {
-            // FP64: vector ALU, 8-row register blocks, chord weights as uniform loads
-            double acc = 0.0;
-            const int nbu = (L - 1 + kRows - 1) / kRows;
-            for (int blk = 0; blk < nbu; ++blk) {
-                const int round = blk / kWaves, pos = blk - round * kWaves;
-                const int owner = (round & 1) ? (kWaves - 1 - pos) : pos;
-                if (owner != wave) continue;
-                const int j0 = blk * kRows;
-                T t[kRows];
-#pragma unroll
-                for (int r = 0; r < kRows; ++r) t[r] = T(0);
-                const T* __restrict__ wcol = rec.wb + (size_t)blk * L * kRows;
-                for (int l = j0; l < L; ++l) {
-                    const T e = es[es_index<T>(l, lane)];
-#pragma unroll
-                    for (int r = 0; r < kRows; ++r) t[r] = fma(wcol[l * kRows + r], e, t[r]);
-                }
-#pragma unroll
-                for (int r = 0; r < kRows; ++r) {
-                    const int j = j0 + r;
-                    if (j <= L - 2) acc += cw_s[j] * chord_fraction(j, jcl, t[r], m.tau_max);
+        const int bw = m.bin_width;
+        const int nbt = sg.tile_w / bw;   // whole channels per tile
+        const int nbins = Nnu / bw;
+        const bool want_chi2 = (chi2 != nullptr) && m.data && m.err;
+        double* bout = binned + sg.bin_off + (size_t)s_in * nbins;
+        if (wave == 0) {
+            double term = 0.0;
+            const int cg = tile * nbt + lane;
+            if (lane < nbt && cg < nbins) {
+                double acc = 0.0;
+                for (int q = 0; q < bw; ++q) acc += dsh[lane * bw + q];
+                const double mean = acc / bw;
+                bout[cg] = mean;
+                if (want_chi2) {
+                    const double d = (mean - m.data[cg]) / m.err[cg];
+                    term = d * d;
                 }
             }
-            part[wave * kTileNu + lane] = acc;
-            __syncthreads();
-            if (wave == 0) {
-                double s = rec.hdr->base;
-                if (jcl >= L - 1) s += cw_s[L - 1];
-                for (int w2 = 0; w2 < kWaves; ++w2) s += part[w2 * kTileNu + lane];
-                dval = s / rec.hdr->rs2;
-            }
-        }
-        }  // unpipelined
-    }
-    if (wave == 0) {
-        if (valid) dout[nu] = dval;
-        dsh[lane] = dval;
-    }
-
-    // ---- phase 3: channels of this tile; chi^2 partial; last tile sums the partials ----
-    if (binned == nullptr || !sg.fused_bins) return;
-    __syncthreads();
-    const int bw = m.bin_width;
-    const int nbt = sg.tile_w / bw;   // whole channels per tile
-    const int nbins = Nnu / bw;
-    const bool want_chi2 = (chi2 != nullptr) && m.data && m.err;
-    double* bout = binned + sg.bin_off + (size_t)s_in * nbins;
-    if (wave == 0) {
-        double term = 0.0;
-        const int cg = tile * nbt + lane;
-        if (lane < nbt && cg < nbins) {
-            double acc = 0.0;
-            for (int q = 0; q < bw; ++q) acc += dsh[lane * bw + q];
-            const double mean = acc / bw;
-            bout[cg] = mean;
             if (want_chi2) {
-                const double d = (mean - m.data[cg]) / m.err[cg];
-                term = d * d;
+                // fixed-order butterfly over the wave
+                for (int o = 32; o > 0; o >>= 1) term += __shfl_xor(term, o);
+                if (lane == 0) rec.chi2part[tile] = term;
             }
         }
-        if (want_chi2) {
-            // fixed-order butterfly over the wave
-            for (int o = 32; o > 0; o >>= 1) term += __shfl_xor(term, o);
-            if (lane == 0) rec.chi2part[tile] = term;
-        }
-    }
+    }  // samples of this workgroup
 }
 
 template <typename T, int kW, bool kNT, int kMode>
 int launch_k_forward(const HostPlan& hp, const LaunchPlan& lp, size_t lds, char* ws, const int32_t* act,
-                            double* depth, double* binned, double* c2, hipStream_t st, hipEvent_t ev0,
-                            hipEvent_t ev1) {
-    const dim3 grid(lp.total_wgs), block(kW * kWave);
+                     double* depth, double* binned, double* c2, const int32_t* compact,
+                     const int32_t* compact_count, int compact_slots, hipStream_t st, hipEvent_t ev0,
+                     hipEvent_t ev1) {
+    // a compacted launch has compact_slots sample slots per tile of its one run of samples
+    if (compact && (lp.n_seg != 1 || compact_slots < 1)) return BM_EINVAL;
+    const dim3 grid(compact ? segment_wgs(compact_slots, lp.seg[0].tiles) : lp.total_wgs), block(kW * kWave);
     int code = BM_OK;
     // one run of samples (pipelined modes): its model moves to slot 0
     constexpr bool kHasSingle = kMode == kModePipelined;
@@ -640,7 +654,7 @@ int launch_k_forward(const HostPlan& hp, const LaunchPlan& lp, size_t lds, char*
     code = ensure_dynamic_lds((const void*)k_forward<T, kW, NS, CIA, kNT, kMode, SINGLE>, lds);    \
     if (code != BM_OK) return code;                                                                \
     hipExtLaunchKernelGGL((k_forward<T, kW, NS, CIA, kNT, kMode, SINGLE>), grid, block, lds, st, ev0, ev1, 0, PLAN, \
-                          ws, act, depth, binned, c2);
+                          ws, act, depth, binned, c2, compact, compact_count, compact_slots);
 #define BM_FWD_LAUNCH(NS, CIA)                 \
     if constexpr (kHasSingle) {                \
         if (single) {                          \

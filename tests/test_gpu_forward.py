@@ -568,3 +568,40 @@ def test_tiled_tables_fp64_and_mixed_instances():
         torch.cuda.synchronize()
         res.append((f.depth.clone(), f.binned.clone()))
     assert torch.equal(res[0][0], res[1][0]) and torch.equal(res[0][1], res[1][1])
+
+
+@pytest.mark.parametrize("n_on", [0, 1, 5, 16, 17, 40])
+def test_masked_calls_match_unmasked(n_on):
+    # a masked call of one run of samples launches the forward kernel over the list of
+    # requested samples (a few slots per tile; more than 16 requested samples make slots
+    # take several in turn): requested samples get exactly the unmasked call's depth,
+    # channels, chi^2 and flags, the others' outputs are left as they were
+    s, sigma, cia = small_config2(n_nu=995, n_layers=70, seed=90)
+    nb = s.nu.size // s.bin_width
+    data, err = np.full(nb, 0.02), np.full(nb, 6e-5)
+    model = gpu_model(s, sigma, cia, data=data, err=err)
+    B = 40
+    params = torch.as_tensor(prior_for(s).draw(B, seed=91), device="cuda")
+    on = np.zeros(B, dtype=np.int32)
+    on[np.random.default_rng(92).choice(B, n_on, replace=False)] = 1
+    act = torch.as_tensor(on, device="cuda")
+    f = bm.Forward(model, B, binned=True, chi2=True)
+    for c in range(len(bm.forward_configs())):
+        f.set_config(c)
+        f(params)
+        ref = [t.clone() for t in (f.depth, f.binned, f.chi2, f.flags)]
+        for t in (f.depth, f.binned, f.chi2):
+            t.fill_(-7.0)
+        f.flags.fill_(-7)
+        f(params, active=act)
+        torch.cuda.synchronize()
+        for b in range(B):
+            d = slice(int(f.depth_off[b]), int(f.depth_off[b + 1]))
+            k = slice(int(f.bin_off[b]), int(f.bin_off[b + 1]))
+            if on[b]:
+                assert torch.equal(f.depth[d], ref[0][d]) and torch.equal(f.binned[k], ref[1][k]), (c, b)
+                assert torch.equal(f.chi2[b], ref[2][b]) and int(f.flags[b]) == int(ref[3][b]), (c, b)
+            else:
+                assert bool((f.depth[d] == -7.0).all()) and bool((f.binned[k] == -7.0).all()), (c, b)
+                assert float(f.chi2[b]) == -7.0 and int(f.flags[b]) == -7, (c, b)
+    f.set_config(-1)
