@@ -78,9 +78,12 @@ def test_model_validation(lib):
     assert lib.bm_workspace_size(C.byref(m), 1, None, 4) == 0        # no tables: rejected
     m.sigma = C.c_void_p(64)
     m.temp = C.c_void_p(64)
+    # B records (each a multiple of 256 bytes), then the masked calls' list of requested
+    # samples and its count (B + 1 int32)
     one = lib.bm_workspace_size(C.byref(m), 1, None, 1)
-    assert one > 100 * 101 // 2 * 4                                # holds the chord-weight triangle
-    assert lib.bm_workspace_size(C.byref(m), 1, None, 7) == 7 * one
+    rec = one - 4 * 2
+    assert rec % 256 == 0 and rec > 100 * 101 // 2 * 4               # holds the chord-weight triangle
+    assert lib.bm_workspace_size(C.byref(m), 1, None, 7) == 7 * rec + 4 * 8
     m.n_species = 9
     assert lib.bm_workspace_size(C.byref(m), 1, None, 1) == 0
 
