@@ -226,10 +226,13 @@ int bm_bin_chi2(const double* depth, int B, int n_nu, int bin_width, const doubl
  * (device int32 [B]).
  * `active` (device int32 [B], or NULL = all) skips samples whose entry is 0: their
  * depth, binned, chi2 and flags entries are left untouched (delayed acceptance runs the
- * exact model only for the proposals its first stage passed, with static shapes).
+ * exact model only for the proposals its first stage passed, with static shapes). A
+ * masked transit call of one model over more than 16 samples builds the list of
+ * requested samples on the device and launches the fused kernel over that list, so its
+ * cost follows the number of requested samples.
  * The workspace (device, `workspace_bytes` >= bm_workspace_size(...)) holds per-sample
- * records; it needs no initialisation. Calls sharing one workspace must be ordered on
- * one stream. Only kernels are enqueued (no memset or copy), so a call can be captured
+ * records and the list of requested samples; it needs no initialisation. Calls sharing
+ * one workspace must be ordered on one stream. Only kernels are enqueued (no memset or copy), so a call can be captured
  * in a HIP graph. */
 size_t bm_workspace_size(const bm_model* models, int n_models, const int32_t* instance,
                          int B);
