@@ -37,11 +37,14 @@ __device__ __forceinline__ float silu_grad(float z) {
 // ---- GEMM: C[M][N] = sum_k A(m, k) B(k, n) -------------------------------------------------
 // A(m, k) = A[m * lda + k] (trans_a = 0) or A[k * lda + m] (trans_a = 1); B(k, n) =
 // B[n * ldb + k] (trans_b = 0: B holds rows of length K, as W[out][in]) or B[k * ldb + n].
-// Block tile BM x BN x 32 with 4 waves in a 2 x 2 layout, each wave (BM/2) x (BN/2) of
+// Block tile BM x BN x TK with 4 waves in a 2 x 2 layout, each wave (BM/2) x (BN/2) of
 // 16 x 16 MFMA tiles. Operand tiles are double-buffered in LDS: the next tile's global
 // loads are in flight while the matrix cores work on the current one. Each thread moves
-// 8 consecutive elements of an operand row (one 16-byte load when the layout allows it).
-constexpr int kTK = 32, kPad = 8;
+// groups of 8 consecutive elements of an operand row (one 16-byte load each when the
+// layout allows it). The k loop is latency-bound for small products (one load round
+// trip per TK slice), so the small tiles take TK = 128; the matrix cores step through a
+// slice 32 k at a time, in the same k order for every TK.
+constexpr int kPad = 8;
 
 struct GemmArgs {
     int M, N, K;
@@ -63,63 +66,76 @@ struct GemmArgs {
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-// 8 elements of one operand for tile rows [r0, r0 + R) x k-slice [k0, k0 + 32): chunk t of
-// the tile. Non-transposed: row r = t / 4, k = 8 (t % 4) .. +7 (contiguous in memory).
-// Transposed: k = t / (R / 8), rows 8 (t % (R / 8)) .. +7 (contiguous in memory).
-template <int R>
+// 8 elements of one operand for tile rows [r0, r0 + R) x k-slice [k0, k0 + TK): chunk t of
+// the tile. Non-transposed: row r = t / (TK / 8), k = 8 (t % (TK / 8)) .. +7 (contiguous in
+// memory). Transposed: k = t / (R / 8), rows 8 (t % (R / 8)) .. +7 (contiguous in memory).
+// Thread t of the 256 holds chunks t, t + 256, ...
+template <int R, int TK>
 struct TileChunk {
-    u32x4 v;
-    __device__ __forceinline__ void load(const uint16_t* __restrict__ X, int ld, int trans, int vec, int rows,
-                                         int K, int r0, int k0, int t) {
-        v = u32x4{0u, 0u, 0u, 0u};
-        if (t >= R * kTK / 8) return;
+    static constexpr int kChunks = R * TK / 8;
+    static constexpr int kPer = (kChunks + 255) / 256;
+    u32x4 v[kPer];
+    __device__ __forceinline__ static u32x4 load_one(const uint16_t* __restrict__ X, int ld, int trans, int vec,
+                                                    int rows, int K, int r0, int k0, int t) {
+        u32x4 out = u32x4{0u, 0u, 0u, 0u};
+        if (t >= kChunks) return out;
         uint16_t e[8];
         if (!trans) {
-            const int r = r0 + t / (kTK / 8), k = k0 + 8 * (t % (kTK / 8));
-            if (r >= rows) return;
+            const int r = r0 + t / (TK / 8), k = k0 + 8 * (t % (TK / 8));
+            if (r >= rows) return out;
             const uint16_t* p = X + (size_t)r * ld + k;
             if (vec) {
-                if (k < K) v = *reinterpret_cast<const u32x4*>(p);  // K % 8 == 0: all 8 or none
-                return;
+                if (k < K) out = *reinterpret_cast<const u32x4*>(p);  // K % 8 == 0: all 8 or none
+                return out;
             }
 #pragma unroll
             for (int i = 0; i < 8; ++i) e[i] = (k + i < K) ? p[i] : (uint16_t)0;
         } else {
             const int k = k0 + t / (R / 8), r = r0 + 8 * (t % (R / 8));
-            if (k >= K) return;
+            if (k >= K) return out;
             const uint16_t* p = X + (size_t)k * ld + r;
             if (vec) {
-                if (r < rows) v = *reinterpret_cast<const u32x4*>(p);  // rows % 8 == 0
-                return;
+                if (r < rows) out = *reinterpret_cast<const u32x4*>(p);  // rows % 8 == 0
+                return out;
             }
 #pragma unroll
             for (int i = 0; i < 8; ++i) e[i] = (r + i < rows) ? p[i] : (uint16_t)0;
         }
-        v = u32x4{(uint32_t)e[0] | ((uint32_t)e[1] << 16), (uint32_t)e[2] | ((uint32_t)e[3] << 16),
-                  (uint32_t)e[4] | ((uint32_t)e[5] << 16), (uint32_t)e[6] | ((uint32_t)e[7] << 16)};
+        return u32x4{(uint32_t)e[0] | ((uint32_t)e[1] << 16), (uint32_t)e[2] | ((uint32_t)e[3] << 16),
+                     (uint32_t)e[4] | ((uint32_t)e[5] << 16), (uint32_t)e[6] | ((uint32_t)e[7] << 16)};
     }
-    // into the LDS tile [R][kTK + kPad] (row-major in k)
-    __device__ __forceinline__ void store(uint16_t (*S)[kTK + kPad], int trans, int t) const {
-        if (t >= R * kTK / 8) return;
-        if (!trans) {
-            *reinterpret_cast<u32x4*>(&S[t / (kTK / 8)][8 * (t % (kTK / 8))]) = v;
-        } else {
-            const int k = t / (R / 8), r = 8 * (t % (R / 8));
+    __device__ __forceinline__ void load(const uint16_t* __restrict__ X, int ld, int trans, int vec, int rows,
+                                         int K, int r0, int k0, int t) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                S[r + 2 * i][k] = (uint16_t)(v[i] & 0xffffu);
-                S[r + 2 * i + 1][k] = (uint16_t)(v[i] >> 16);
+        for (int u = 0; u < kPer; ++u) v[u] = load_one(X, ld, trans, vec, rows, K, r0, k0, t + 256 * u);
+    }
+    // into the LDS tile [R][TK + kPad] (row-major in k)
+    __device__ __forceinline__ void store(uint16_t (*S)[TK + kPad], int trans, int t0) const {
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int t = t0 + 256 * u;
+            if (t >= kChunks) continue;
+            if (!trans) {
+                *reinterpret_cast<u32x4*>(&S[t / (TK / 8)][8 * (t % (TK / 8))]) = v[u];
+            } else {
+                const int k = t / (R / 8), r = 8 * (t % (R / 8));
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    S[r + 2 * i][k] = (uint16_t)(v[u][i] & 0xffffu);
+                    S[r + 2 * i + 1][k] = (uint16_t)(v[u][i] >> 16);
+                }
             }
         }
     }
 };
 
-template <int BM, int BN>
+template <int BM, int BN, int TK>
 __global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
     constexpr int WM = BM / 2, WN = BN / 2;          // wave tile
     constexpr int TI = WM / 16, TJ = WN / 16;        // MFMA tiles per wave
-    __shared__ __align__(16) uint16_t As[2][BM][kTK + kPad];
-    __shared__ __align__(16) uint16_t Bs[2][BN][kTK + kPad];
+    static_assert(TK % 32 == 0, "k slices of whole MFMA steps");
+    __shared__ __align__(16) uint16_t As[2][BM][TK + kPad];
+    __shared__ __align__(16) uint16_t Bs[2][BN][TK + kPad];
     const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = (wave >> 1) * WM, wn = (wave & 1) * WN;
@@ -128,9 +144,9 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
     for (int i = 0; i < TI; ++i)
 #pragma unroll
         for (int j = 0; j < TJ; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const int nk = (g.K + kTK - 1) / kTK;
-    TileChunk<BM> ca;
-    TileChunk<BN> cb;
+    const int nk = (g.K + TK - 1) / TK;
+    TileChunk<BM, TK> ca;
+    TileChunk<BN, TK> cb;
     ca.load(g.A, g.lda, g.trans_a, g.vec_a, g.M, g.K, m0, 0, tid);
     cb.load(g.B, g.ldb, g.trans_b, g.vec_b, g.N, g.K, n0, 0, tid);
     ca.store(As[0], g.trans_a, tid);
@@ -139,21 +155,26 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
     for (int kt = 0; kt < nk; ++kt) {
         const int cur = kt & 1;
         if (kt + 1 < nk) {
-            ca.load(g.A, g.lda, g.trans_a, g.vec_a, g.M, g.K, m0, (kt + 1) * kTK, tid);
-            cb.load(g.B, g.ldb, g.trans_b, g.vec_b, g.N, g.K, n0, (kt + 1) * kTK, tid);
+            ca.load(g.A, g.lda, g.trans_a, g.vec_a, g.M, g.K, m0, (kt + 1) * TK, tid);
+            cb.load(g.B, g.ldb, g.trans_b, g.vec_b, g.N, g.K, n0, (kt + 1) * TK, tid);
         }
         // operands: lane holds 8 consecutive k of row (lane % 16); k offset 8 (lane / 16)
-        const int kq = 8 * (lane >> 4);
-        bf16x8 a[TI], b[TJ];
 #pragma unroll
-        for (int i = 0; i < TI; ++i) a[i] = *reinterpret_cast<const bf16x8*>(&As[cur][wm + 16 * i + (lane & 15)][kq]);
+        for (int kk = 0; kk < TK; kk += 32) {
+            const int kq = kk + 8 * (lane >> 4);
+            bf16x8 a[TI], b[TJ];
 #pragma unroll
-        for (int j = 0; j < TJ; ++j) b[j] = *reinterpret_cast<const bf16x8*>(&Bs[cur][wn + 16 * j + (lane & 15)][kq]);
-#pragma unroll
-        for (int i = 0; i < TI; ++i)
+            for (int i = 0; i < TI; ++i)
+                a[i] = *reinterpret_cast<const bf16x8*>(&As[cur][wm + 16 * i + (lane & 15)][kq]);
 #pragma unroll
             for (int j = 0; j < TJ; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+                b[j] = *reinterpret_cast<const bf16x8*>(&Bs[cur][wn + 16 * j + (lane & 15)][kq]);
+#pragma unroll
+            for (int i = 0; i < TI; ++i)
+#pragma unroll
+                for (int j = 0; j < TJ; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
         if (kt + 1 < nk) {
             ca.store(As[cur ^ 1], g.trans_a, tid);
             cb.store(Bs[cur ^ 1], g.trans_b, tid);
@@ -305,10 +326,14 @@ static int launch_gemm(GemmArgs a, hipStream_t st) {
     const long tiles64 = (long)((a.N + 63) / 64) * ((a.M + 63) / 64);
     if (tiles64 >= 256) {
         dim3 grid((a.N + 63) / 64, (a.M + 63) / 64);
-        hipLaunchKernelGGL((k_gemm_bf16<64, 64>), grid, dim3(256), 0, st, a);
+        hipLaunchKernelGGL((k_gemm_bf16<64, 64, 32>), grid, dim3(256), 0, st, a);
     } else {
+        // small products: few workgroups, so each takes 128-deep k slices (fewer round trips)
         dim3 grid((a.N + 31) / 32, (a.M + 31) / 32);
-        hipLaunchKernelGGL((k_gemm_bf16<32, 32>), grid, dim3(256), 0, st, a);
+        if (a.K > 64)
+            hipLaunchKernelGGL((k_gemm_bf16<32, 32, 128>), grid, dim3(256), 0, st, a);
+        else
+            hipLaunchKernelGGL((k_gemm_bf16<32, 32, 32>), grid, dim3(256), 0, st, a);
     }
     BM_CHECK_HIP(hipGetLastError());
     return BM_OK;
