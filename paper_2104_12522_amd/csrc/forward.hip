@@ -392,6 +392,12 @@ static int config_with_mode(int cfg, int mode) {
         if (kFwdConfigs[c].nontemporal == kFwdConfigs[cfg].nontemporal && kFwdConfigs[c].mode == mode) return c;
     return cfg;
 }
+// the configuration with the same phase-2 mode and cached table loads
+static int config_cached(int cfg) {
+    for (int c = 0; c < kNumFwdConfigs; ++c)
+        if (!kFwdConfigs[c].nontemporal && kFwdConfigs[c].mode == kFwdConfigs[cfg].mode) return c;
+    return cfg;
+}
 
 // dynamic LDS of a launch; the staged modes add their static staging arrays
 template <typename T>
@@ -474,12 +480,14 @@ static int launch_forward(const HostPlan& hp, int cfg, const double* params, int
     if (!fits(cfg) && kFwdConfigs[cfg].mode == kModePipelined) cfg = config_with_mode(cfg, kModeStaged);
     if (!fits(cfg)) cfg = config_with_mode(cfg, kModeStreamed);
     if (!fits(cfg)) return BM_ESHAPE;
-    const size_t lds = forward_lds_bytes<T>(hp.max_L, kFwdConfigs[cfg].waves, hp.max_ntc, kFwdConfigs[cfg].mode);
-    // a masked transit call of one run of samples launches the forward kernel over the list
-    // of requested samples (kCompactSlots slots per tile) instead of every sample
+    // a masked FP32 transit call of one run of samples launches the forward kernel over the
+    // list of requested samples (kCompactSlots slots per tile) instead of every sample, with
+    // cached table loads (the compacted kernels exist for those)
     const int B = hp.total_samples;
-    const bool compact = active && hp.geometry == BM_GEOM_TRANSIT && hp.plans.size() == 1 &&
+    const bool compact = sizeof(T) == 4 && active && hp.geometry == BM_GEOM_TRANSIT && hp.plans.size() == 1 &&
                          hp.plans[0].n_seg == 1 && B > kCompactSlots;
+    if (compact) cfg = config_cached(cfg);
+    const size_t lds = forward_lds_bytes<T>(hp.max_L, kFwdConfigs[cfg].waves, hp.max_ntc, kFwdConfigs[cfg].mode);
     int32_t* list = compact ? reinterpret_cast<int32_t*>(ws + hp.list_off) : nullptr;
     if (compact) {
         hipLaunchKernelGGL(k_active_list, dim3(1), dim3(1024), 0, st, active, B, list);

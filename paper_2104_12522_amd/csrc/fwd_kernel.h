@@ -147,7 +147,8 @@ struct PipeFields {
 
 // kSingle: the launch holds one run of samples whose model is in slot 0, so the segment and
 // model fields sit at fixed argument offsets and are read without a dependent lookup
-template <typename T, int kWaves, int kS, bool kCia, bool kNonTemporal, int kMode, bool kSingle = false>
+template <typename T, int kWaves, int kS, bool kCia, bool kNonTemporal, int kMode, bool kSingle = false,
+          bool kCompact = false>
 __global__ void __launch_bounds__(kWaves * kWave)
     k_forward(LaunchPlan plan, char* __restrict__ ws, const int32_t* __restrict__ active,
               double* __restrict__ depth, double* __restrict__ binned, double* __restrict__ chi2,
@@ -169,18 +170,17 @@ __global__ void __launch_bounds__(kWaves * kWave)
     // samples, compact_count[0] of them) has compact_slots sample slots per tile, and
     // workgroup (tile, slot k) takes list entries k, k + slots, ... in turn, so that a call
     // that requests few samples launches few workgroups.
-    const int slots = compact ? compact_slots : sg.count;
+    const int slots = kCompact ? compact_slots : sg.count;
     const int g = blockIdx.x - sg.tile_begin;
     const int kx = g / kXcds;
     const int tile = (g % kXcds) * sg.tiles_per_xcd + kx / slots;
     const int slot = kx % slots;
     if (tile >= sg.tiles) return;  // padding workgroup of the XCD split
-    const int n_items = compact ? *compact_count : slot + 1;
-    for (int q = slot; q < n_items; q += slots) {
-        if (q != slot) __syncthreads();  // the previous sample's LDS reads are done
-        const int s_in = compact ? compact[q] - sg.first : q;
+    // one sample of this workgroup's tile (the compacted variant runs it for each of its
+    // list entries; the loop stays out of the other variants' code)
+    auto run = [&](const int s_in) {
         const int b = sg.first + s_in;
-        if (active && !active[b]) continue;  // sample not requested in this call
+        if (active && !active[b]) return;  // sample not requested in this call
         const int L = m.L, Nnu = m.Nnu;
         const RecordView<T> rec(ws + sg.ws_off + (size_t)s_in * sg.rec_bytes, kS, L);
         const FwdLds<T> lay(L, kWaves, plan.max_ntc, kPipe);
@@ -603,7 +603,7 @@ __global__ void __launch_bounds__(kWaves * kWave)
         }
 
         // ---- phase 3: channels of this tile; chi^2 partial; last tile sums the partials ----
-        if (binned == nullptr || !sg.fused_bins) continue;
+        if (binned == nullptr || !sg.fused_bins) return;
         __syncthreads();
         const int bw = m.bin_width;
         const int nbt = sg.tile_w / bw;   // whole channels per tile
@@ -629,7 +629,16 @@ __global__ void __launch_bounds__(kWaves * kWave)
                 if (lane == 0) rec.chi2part[tile] = term;
             }
         }
-    }  // samples of this workgroup
+    };
+    if constexpr (kCompact) {
+        const int n_items = *compact_count;
+        for (int q = slot; q < n_items; q += slots) {
+            if (q != slot) __syncthreads();  // the previous sample's LDS reads are done
+            run(compact[q] - sg.first);
+        }
+    } else {
+        run(slot);
+    }
 }
 
 template <typename T, int kW, bool kNT, int kMode>
@@ -638,7 +647,8 @@ int launch_k_forward(const HostPlan& hp, const LaunchPlan& lp, size_t lds, char*
                      const int32_t* compact_count, int compact_slots, hipStream_t st, hipEvent_t ev0,
                      hipEvent_t ev1) {
     // a compacted launch has compact_slots sample slots per tile of its one run of samples
-    if (compact && (lp.n_seg != 1 || compact_slots < 1)) return BM_EINVAL;
+    // (FP32 with cached table loads)
+    if (compact && (lp.n_seg != 1 || compact_slots < 1 || kNT || sizeof(T) != 4)) return BM_EINVAL;
     const dim3 grid(compact ? segment_wgs(compact_slots, lp.seg[0].tiles) : lp.total_wgs), block(kW * kWave);
     int code = BM_OK;
     // one run of samples (pipelined modes): its model moves to slot 0
@@ -650,20 +660,30 @@ int launch_k_forward(const HostPlan& hp, const LaunchPlan& lp, size_t lds, char*
         lp1.seg[0].model = 0;
     }
     switch (hp.n_species) {
-#define BM_FWD_GO(NS, CIA, SINGLE, PLAN)                                                          \
-    code = ensure_dynamic_lds((const void*)k_forward<T, kW, NS, CIA, kNT, kMode, SINGLE>, lds);    \
-    if (code != BM_OK) return code;                                                                \
-    hipExtLaunchKernelGGL((k_forward<T, kW, NS, CIA, kNT, kMode, SINGLE>), grid, block, lds, st, ev0, ev1, 0, PLAN, \
-                          ws, act, depth, binned, c2, compact, compact_count, compact_slots);
+#define BM_FWD_GO(NS, CIA, SINGLE, COMPACT, PLAN)                                                          \
+    code = ensure_dynamic_lds((const void*)k_forward<T, kW, NS, CIA, kNT, kMode, SINGLE, COMPACT>, lds);    \
+    if (code != BM_OK) return code;                                                                         \
+    hipExtLaunchKernelGGL((k_forward<T, kW, NS, CIA, kNT, kMode, SINGLE, COMPACT>), grid, block, lds, st, ev0, \
+                          ev1, 0, PLAN, ws, act, depth, binned, c2, compact, compact_count, compact_slots);
+#define BM_FWD_GO2(NS, CIA, SINGLE, PLAN)                        \
+    if constexpr (!kNT && sizeof(T) == 4) {                      \
+        if (compact) {                                           \
+            BM_FWD_GO(NS, CIA, SINGLE, true, PLAN)               \
+        } else {                                                 \
+            BM_FWD_GO(NS, CIA, SINGLE, false, PLAN)              \
+        }                                                        \
+    } else {                                                     \
+        BM_FWD_GO(NS, CIA, SINGLE, false, PLAN)                  \
+    }
 #define BM_FWD_LAUNCH(NS, CIA)                 \
     if constexpr (kHasSingle) {                \
         if (single) {                          \
-            BM_FWD_GO(NS, CIA, kHasSingle, lp1) \
+            BM_FWD_GO2(NS, CIA, true, lp1)     \
         } else {                               \
-            BM_FWD_GO(NS, CIA, false, lp)      \
+            BM_FWD_GO2(NS, CIA, false, lp)     \
         }                                      \
     } else {                                   \
-        BM_FWD_GO(NS, CIA, false, lp)          \
+        BM_FWD_GO2(NS, CIA, false, lp)         \
     }
 #define BM_FWD_CASE(NS)              \
     case NS:                         \
@@ -677,6 +697,7 @@ int launch_k_forward(const HostPlan& hp, const LaunchPlan& lp, size_t lds, char*
         BM_FWD_CASE(5) BM_FWD_CASE(6) BM_FWD_CASE(7) BM_FWD_CASE(8)
 #undef BM_FWD_CASE
 #undef BM_FWD_LAUNCH
+#undef BM_FWD_GO2
 #undef BM_FWD_GO
         default: return BM_ESHAPE;
     }
