@@ -9,8 +9,10 @@
 //            (T bracket, weights, densities) sit one layer per lane and are broadcast
 //            with v_readlane, so the two bracketing temperature rows of every species
 //            table are streamed for four layers at a time (coalesced along
-//            wavenumber, non-temporal) with no memory wait for addresses. CIA rows of
-//            the tile are staged in LDS once. e[l][nu] is left in LDS.
+//            wavenumber, non-temporal or cached) with no memory wait for addresses, from
+//            the tile-major copy of the tables when one exists for the tile width. CIA
+//            rows of the tile are staged in LDS once. e[l][nu] is left in LDS.
+//   (pipelined mode: phases 1 and 2 interleaved over 16-layer stages, see below)
 //   phase 2  chord optical depth on the matrix cores (FP32): v_mfma_f32_16x16x4f32 over
 //            16-row blocks of the triangular chord-weight matrix (A, staged in LDS) and
 //            4-layer slices of e (B); items (row block, 16-column group) are dealt to
@@ -20,7 +22,9 @@
 //   phase 3  the tile bins its own channels and writes its chi^2 partial; a small
 //            kernel sums the partials per sample in a fixed tree.
 // Workgroups are ordered XCD-aware and tile-major (see Segment) so that, in a batch,
-// all samples of one tile read the same table rows from the same L2.
+// all samples of one tile read the same table rows from the same L2. A masked call of one
+// run of samples can launch over the device-built list of its requested samples instead
+// (the compacted variant).
 #pragma once
 #include <hip/hip_ext.h>
 
