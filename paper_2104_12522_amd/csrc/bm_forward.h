@@ -218,11 +218,15 @@ int launch_k_emission(const LaunchPlan& lp, int seg, char* ws, const int32_t* ac
 
 // launch of the fused kernel for one plan with kW waves per workgroup, non-temporal (kNT)
 // or cached table loads, and phase-2 mode kMode (chord weights streamed from L2, staged in
-// LDS, or staged with phases 1 and 2 interleaved; fwd_kernel.h); ev0/ev1 (or null) are
-// timing events that the dispatch itself records at the kernel's start and end
+// LDS, or staged with phases 1 and 2 interleaved; fwd_kernel.h); compact (or null) is the
+// list of requested samples of a masked call and compact_count its length, run in
+// compact_slots sample slots per tile; ev0/ev1 (or null) are timing events that the
+// dispatch itself records at the kernel's start and end
 template <typename T, int kW, bool kNT, int kMode>
 int launch_k_forward(const HostPlan& hp, const LaunchPlan& lp, size_t lds, char* ws, const int32_t* act,
-                     double* depth, double* binned, double* c2, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1);
+                     double* depth, double* binned, double* c2, const int32_t* compact,
+                     const int32_t* compact_count, int compact_slots, hipStream_t st, hipEvent_t ev0,
+                     hipEvent_t ev1);
 
 // record preparation; kSingle: a single-segment plan whose model is in slot 0;
 // kMasked: `active` is not null
