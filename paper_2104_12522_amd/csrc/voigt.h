@@ -45,38 +45,40 @@ inline WeidemanCoef weideman_coefficients() {
     return c;
 }
 
+// Re w(x + i y) far from the origin (|z| >= 8): the Laplace continued fraction of w(z),
+// 1/(z - (1/2)/(z - (2/2)/(z - ...))), through its convergents P_m / Q_m with
+// h_m = z h_{m-1} - ((m-1)/2) h_{m-2} (P_0 = 0, P_1 = 1; Q_0 = 1, Q_1 = z), N levels; then
+// w = (i / sqrt(pi)) P / Q, Re w = -Im(P / Q) / sqrt(pi). N is a compile-time depth, so the
+// recurrence unrolls into straight-line code with no register rotation.
+template <int N>
+__device__ __forceinline__ double faddeeva_re_cf(double x, double y) {
+    double pr0 = 0.0, pi0 = 0.0, pr1 = 1.0, pi1 = 0.0;
+    double qr0 = 1.0, qi0 = 0.0, qr1 = x, qi1 = y;
+#pragma unroll
+    for (int m = 2; m <= N + 1; ++m) {
+        const double am = -0.5 * (m - 1);
+        const double prn = x * pr1 - y * pi1 + am * pr0;
+        const double pin = x * pi1 + y * pr1 + am * pi0;
+        const double qrn = x * qr1 - y * qi1 + am * qr0;
+        const double qin = x * qi1 + y * qr1 + am * qi0;
+        pr0 = pr1; pi0 = pi1; pr1 = prn; pi1 = pin;
+        qr0 = qr1; qi0 = qi1; qr1 = qrn; qi1 = qin;
+    }
+    const double den = qr1 * qr1 + qi1 * qi1;
+    const double im_ratio = (pi1 * qr1 - pr1 * qi1) / den;
+    return -im_ratio * 0.56418958354775628695;  // 1/sqrt(pi)
+}
+
 // Re w(x + i y), y > 0.
 __device__ __forceinline__ double faddeeva_re(double x, double y, const WeidemanCoef& wc) {
     x = fabs(x);
     const double r2 = x * x + y * y;
-    if (r2 >= 64.0) {
-        int n;
-        if (r2 >= 1600.0)
-            n = 4;
-        else if (r2 >= 225.0)
-            n = 6;
-        else if (r2 >= 100.0)
-            n = 8;
-        else
-            n = 10;
-        // convergents of 1/(z - (1/2)/(z - (2/2)/(z - ...))): h_m = z h_{m-1} - ((m-1)/2) h_{m-2}
-        // start: P_0 = 0, P_1 = 1; Q_0 = 1, Q_1 = z
-        double pr0 = 0.0, pi0 = 0.0, pr1 = 1.0, pi1 = 0.0;
-        double qr0 = 1.0, qi0 = 0.0, qr1 = x, qi1 = y;
-        for (int m = 2; m <= n + 1; ++m) {
-            const double am = -0.5 * (m - 1);
-            const double prn = x * pr1 - y * pi1 + am * pr0;
-            const double pin = x * pi1 + y * pr1 + am * pi0;
-            const double qrn = x * qr1 - y * qi1 + am * qr0;
-            const double qin = x * qi1 + y * qr1 + am * qi0;
-            pr0 = pr1; pi0 = pi1; pr1 = prn; pi1 = pin;
-            qr0 = qr1; qi0 = qi1; qr1 = qrn; qi1 = qin;
-        }
-        // w = (i / sqrt(pi)) P / Q ;  Re w = -Im(P / Q) / sqrt(pi)
-        const double den = qr1 * qr1 + qi1 * qi1;
-        const double im_ratio = (pi1 * qr1 - pr1 * qi1) / den;
-        return -im_ratio * 0.56418958354775628695;  // 1/sqrt(pi)
-    }
+    // depth by |z|: 4 levels for |z| >= 40 (every evaluation of strongly pressure-broadened
+    // lines), 6 from 15, 8 from 10, 10 from 8
+    if (r2 >= 1600.0) return faddeeva_re_cf<4>(x, y);
+    if (r2 >= 225.0) return faddeeva_re_cf<6>(x, y);
+    if (r2 >= 100.0) return faddeeva_re_cf<8>(x, y);
+    if (r2 >= 64.0) return faddeeva_re_cf<10>(x, y);
     // Weideman: Z = (L + iz)/(L - iz), w = (2 p(Z) / (L - iz) + 1/sqrt(pi)) / (L - iz)
     const double L = wc.L;
     const double dr = L + y, di = -x;            // L - iz
