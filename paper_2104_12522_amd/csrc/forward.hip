@@ -13,7 +13,7 @@
 namespace bm {
 
 // the fused kernel's launchers are instantiated in fwd_f32_nt.hip, fwd_f32_t.hip,
-// fwd_f32_pipe.hip and fwd_f64.hip (compiled in parallel)
+// fwd_f32_pipe_nt.hip, fwd_f32_pipe_t.hip and fwd_f64.hip (compiled in parallel)
 #define BM_FWD_EXTERN(T, W, NT, MODE)                                                                  \
     extern template int launch_k_forward<T, W, NT, MODE>(const HostPlan&, const LaunchPlan&, size_t, char*, \
                                                           const int32_t*, double*, double*, double*,      \
