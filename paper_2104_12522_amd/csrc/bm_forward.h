@@ -8,7 +8,6 @@
 namespace bm {
 
 constexpr int kAtmThreads = BM_MAX_LAYERS;  // threads for one-sample atmosphere work (>= L)
-constexpr int kPrepThreads = 1024;          // record-preparation workgroup
 constexpr int kRows = 8;                    // chord-weight rows per register block (FP64 path)
 constexpr int kTileNu = kWave;              // wavenumbers per forward workgroup (one per lane)
 constexpr int kMaxModels = 4;               // distinct models in one fused launch
