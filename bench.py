@@ -80,10 +80,14 @@ def make_model(setup, sigma, seed: int, truth=None):
     prior = wl.line2013_prior(setup.n_species)
     if truth is None:
         truth = prior.draw(1, seed=seed + 2)[0]
-    f = bm.Forward(model, 1, binned=True)
-    f(torch.as_tensor(np.asarray(truth, np.float64)[None], device="cuda"))
+    # two copies of the truth: no section tunes a two-spectrum call, so the observation
+    # takes the default launch configuration whichever sections ran before (the pipelined
+    # configuration that a tuned one-spectrum call may use sums the chord depths in another
+    # order, which moves the observation in its last bits and with it every chain)
+    f = bm.Forward(model, 2, binned=True)
+    f(torch.as_tensor(np.repeat(np.asarray(truth, np.float64)[None], 2, axis=0), device="cuda"))
     noise = wl.rng(seed + 3).normal(0.0, 60e-6, nb)
-    model.set_observation(f.binned.cpu().numpy() + noise, np.full(nb, 60e-6))
+    model.set_observation(f.binned_spectrum(0).cpu().numpy() + noise, np.full(nb, 60e-6))
     return model, cia
 
 
@@ -471,8 +475,8 @@ def section_mcmc(args, setup, prior):
         del Xl, Yl
 
     # 4. production runs from the same burned-in state and random stream
-    def production(surrogate=None, per_sample=0, n_gen=G):
-        r = Retrieval(model, C, prior.lo, prior.hi, seed=args.seed + 70, thin=10, hist_cap=n_gen,
+    def production(surrogate=None, per_sample=0, n_gen=G, stream=70):
+        r = Retrieval(model, C, prior.lo, prior.hi, seed=args.seed + stream, thin=10, hist_cap=n_gen,
                       surrogate=surrogate, per_sample_workers=per_sample,
                       z_cap=z0.shape[0] + C * (n_gen // 10 + 1))
         r.resume(x0, z0)
@@ -507,6 +511,14 @@ def section_mcmc(args, setup, prior):
     log(f"mcmc: delayed-acceptance production, {G} generations")
     _, h_d, w_d, acc_d = production(surrogate=sur)
     da, mu_d, sd_d = stats(h_d, w_d, acc_d, G, stage1_pass_rate=float(acc_d[0]))
+    del h_d
+    # a second delayed-acceptance run from the same state with another random stream: the
+    # spread between runs of G generations, the yardstick for the plain-vs-DA difference
+    log(f"mcmc: delayed-acceptance replicate (another random stream), {G} generations")
+    _, h_r, w_r, acc_r = production(surrogate=sur, stream=71)
+    da_rep, mu_r, sd_r = stats(h_r, w_r, acc_r, G)
+    del h_r
+    diff_rep = (mu_r - mu_d) / sd_b2
     log(f"mcmc: plain per-sample, {args.per_sample_gens} generations timed")
     _, h_p, w_p, _ = production(per_sample=1, n_gen=args.per_sample_gens)
     identical = bool(torch.equal(h_p, h_b[:args.per_sample_gens]))
@@ -526,7 +538,7 @@ def section_mcmc(args, setup, prior):
     e2e = (da["ess"] / (w_d + t_local)) / (plain_b["ess"] / ps_wall)
     log(f"mcmc: ESS/s per-sample {plain_ps['ess_per_s']:.2f}, batched {plain_b['ess_per_s']:.2f}, "
         f"delayed acceptance {da['ess_per_s']:.2f} -> {ratio:.1f}x; max |mean diff| "
-        f"{np.abs(diff).max():.3f} sd")
+        f"{np.abs(diff).max():.3f} sd (two delayed-acceptance runs: {np.abs(diff_rep).max():.3f} sd)")
     return {
         "chains": C, "burn_in": BURN, "da_burn_in": args.da_burn, "truth": truth.tolist(),
         "prior": {"lo": prior.lo.tolist(), "hi": prior.hi.tolist()},
@@ -549,7 +561,12 @@ def section_mcmc(args, setup, prior):
         "max_abs_mean_diff_sd": float(np.abs(diff).max()),
         "marginal_mean_diff_in_standard_errors": diff_z.tolist(),
         "max_abs_mean_diff_in_standard_errors": float(np.abs(diff_z).max()),
-        "marginal_mean": {"plain": mu_b2.tolist(), "delayed_acceptance": mu_d.tolist()},
+        "delayed_acceptance_replicate": {
+            "ess": da_rep["ess"], "gelman_rubin_max": da_rep["gelman_rubin_max"],
+            "marginal_mean_diff_sd_vs_delayed_acceptance": diff_rep.tolist(),
+            "max_abs_mean_diff_sd_vs_delayed_acceptance": float(np.abs(diff_rep).max())},
+        "marginal_mean": {"plain": mu_b2.tolist(), "delayed_acceptance": mu_d.tolist(),
+                          "delayed_acceptance_replicate": mu_r.tolist()},
         "marginal_sd": {"plain": sd_b2.tolist(), "delayed_acceptance": sd_d.tolist()},
     }
 
