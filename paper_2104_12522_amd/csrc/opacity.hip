@@ -55,12 +55,71 @@ __global__ void k_line_extremes(LineArrays ln, double* out) {
     }
 }
 
+// the cell's widest window plus one grid step: every line's window is at most wmax - dnu
+// wide (the Doppler and Lorentz widths of the widest line bound every line's; the factor
+// covers their rounding)
+__device__ __forceinline__ double cell_wmax(const double* __restrict__ extremes, double T_, double pfac,
+                                            double cutoff, double dnu) {
+    const double gmax = extremes[0] * pfac;
+    const double smax = extremes[1] / kLight * sqrt(kBoltz * T_ / kAmu);
+    return cutoff * voigt_hwhm(smax, gmax) * (1.0 + 1e-12) + dnu;
+}
+
+// Cells of narrow lines take the line-major kernel: every window, widened by two grid points
+// on each side for rounding, spans at most kNarrowPts points.
+constexpr int kNarrowPts = 48;
+constexpr int kNarrowLines = 64;  // lines evaluated per pass, four threads each
+__device__ __forceinline__ bool narrow_cell(double wmax, double dnu) {
+    return 2.0 * wmax / dnu + 3.0 <= (double)kNarrowPts;
+}
+
+// first line with nu0 >= lo_v and first line with nu0 > hi_v (centres sorted ascending)
+__device__ inline void line_range(const LineArrays& ln, double lo_v, double hi_v, int64_t* range) {
+    int64_t a = 0, b = ln.n;
+    while (a < b) {
+        int64_t mid = (a + b) >> 1;
+        if (ln.nu0[mid] < lo_v) a = mid + 1; else b = mid;
+    }
+    range[0] = a;
+    b = ln.n;
+    while (a < b) {
+        int64_t mid = (a + b) >> 1;
+        if (ln.nu0[mid] <= hi_v) a = mid + 1; else b = mid;
+    }
+    range[1] = a;
+}
+
+// Lines staged in LDS: centre, window half-width, S(T) / (sigma sqrt(2 pi)), 1 / (sigma sqrt 2)
+// and the Faddeeva argument's imaginary part y = gamma / (sigma sqrt 2).
+struct StagedLines {
+    double nu0[kOpThreads], half[kOpThreads], amp[kOpThreads], inv[kOpThreads], y[kOpThreads];
+};
+
+// line i at temperature T_ into slot t (Sec. 3: strength at T, Doppler and Lorentz widths)
+__device__ __forceinline__ void stage_line(const LineArrays& ln, int64_t i, int t, double T_, double pfac,
+                                           double cutoff, double qratio, StagedLines& sl) {
+    const double boltz_ref = 1.0 / kTRef;
+    const double nu0 = ln.nu0[i];
+    const double el = ln.elow[i];
+    const double s_t = ln.s296[i] * qratio * exp(-kC2 * el / T_) / exp(-kC2 * el * boltz_ref) *
+                       ((1.0 - exp(-kC2 * nu0 / T_)) / (1.0 - exp(-kC2 * nu0 * boltz_ref)));
+    const double sig = nu0 / kLight * sqrt(kBoltz * T_ / (ln.mass[i] * kAmu));
+    const double gam = ln.gamma296[i] * pfac;
+    const double inv = 1.0 / (sig * 1.41421356237309504880);
+    sl.nu0[t] = nu0;
+    sl.half[t] = cutoff * voigt_hwhm(sig, gam);
+    sl.amp[t] = s_t / (sig * 2.50662827463100050242);  // sigma sqrt(2 pi)
+    sl.inv[t] = inv;
+    sl.y[t] = gam * inv;
+}
+
+// Wavenumber-major build (cells of wide lines): every lane sums, in line order, the profiles
+// of the staged lines whose window contains its wavenumber.
 template <typename T>
 __global__ void __launch_bounds__(kOpThreads)
     k_opacity_gather(LineArrays ln, CellGrid cg, double nu_start, double dnu, int n_nu, double cutoff,
                      const double* __restrict__ extremes, WeidemanCoef wc, T* __restrict__ out) {
-    __shared__ double s_nu0[kOpThreads], s_half[kOpThreads], s_amp[kOpThreads], s_inv[kOpThreads],
-        s_y[kOpThreads];
+    __shared__ StagedLines sl;
     __shared__ int64_t range[2];
     const int cell = blockIdx.y;
     const double T_ = cg.temp[cell / cg.n_p];
@@ -71,55 +130,104 @@ __global__ void __launch_bounds__(kOpThreads)
     const double t_hi = nu_start + dnu * (double)min(blockIdx.x * kOpThreads + kOpThreads - 1, n_nu - 1);
 
     const double pfac = (p / kAtmBar) * sqrt(kTRef / T_);
-    if (threadIdx.x == 0) {
-        const double gmax = extremes[0] * pfac;
-        const double smax = extremes[1] / kLight * sqrt(kBoltz * T_ / kAmu);
-        const double wmax = cutoff * voigt_hwhm(smax, gmax) * (1.0 + 1e-12) + dnu;
-        // first line with nu0 >= t_lo - wmax, first line with nu0 > t_hi + wmax
-        const double lo_v = t_lo - wmax, hi_v = t_hi + wmax;
-        int64_t a = 0, b = ln.n;
-        while (a < b) {
-            int64_t mid = (a + b) >> 1;
-            if (ln.nu0[mid] < lo_v) a = mid + 1; else b = mid;
-        }
-        range[0] = a;
-        b = ln.n;
-        while (a < b) {
-            int64_t mid = (a + b) >> 1;
-            if (ln.nu0[mid] <= hi_v) a = mid + 1; else b = mid;
-        }
-        range[1] = a;
-    }
+    const double wmax = cell_wmax(extremes, T_, pfac, cutoff, dnu);
+    if (narrow_cell(wmax, dnu)) return;  // the line-major kernel builds this cell
+    if (threadIdx.x == 0) line_range(ln, t_lo - wmax, t_hi + wmax, range);
     __syncthreads();
     const int64_t first = range[0], last = range[1];
-    const double boltz_ref = 1.0 / kTRef;
     const double qratio = pow(kTRef / T_, 1.5);
     double acc = 0.0;
     for (int64_t c0 = first; c0 < last; c0 += kOpThreads) {
         const int64_t i = c0 + threadIdx.x;
-        if (i < last) {
-            const double nu0 = ln.nu0[i];
-            const double el = ln.elow[i];
-            const double s_t = ln.s296[i] * qratio * exp(-kC2 * el / T_) / exp(-kC2 * el * boltz_ref) *
-                               ((1.0 - exp(-kC2 * nu0 / T_)) / (1.0 - exp(-kC2 * nu0 * boltz_ref)));
-            const double sig = nu0 / kLight * sqrt(kBoltz * T_ / (ln.mass[i] * kAmu));
-            const double gam = ln.gamma296[i] * pfac;
-            const double inv = 1.0 / (sig * 1.41421356237309504880);
-            s_nu0[threadIdx.x] = nu0;
-            s_half[threadIdx.x] = cutoff * voigt_hwhm(sig, gam);
-            s_amp[threadIdx.x] = s_t / (sig * 2.50662827463100050242);  // sigma sqrt(2 pi)
-            s_inv[threadIdx.x] = inv;
-            s_y[threadIdx.x] = gam * inv;
-        }
+        if (i < last) stage_line(ln, i, threadIdx.x, T_, pfac, cutoff, qratio, sl);
         __syncthreads();
         const int cnt = (int)min((int64_t)kOpThreads, last - c0);
         if (k < n_nu) {
             for (int q = 0; q < cnt; ++q) {
-                const double d = nu - s_nu0[q];
-                if (fabs(d) <= s_half[q]) acc += s_amp[q] * faddeeva_re(d * s_inv[q], s_y[q], wc);
+                const double d = nu - sl.nu0[q];
+                if (fabs(d) <= sl.half[q]) acc += sl.amp[q] * faddeeva_re(d * sl.inv[q], sl.y[q], wc);
             }
         }
         __syncthreads();
+    }
+    if (k < n_nu) out[(size_t)cell * n_nu + k] = (T)acc;
+}
+
+// Line-major build (cells of narrow lines, whose windows span a few grid points: in the
+// wavenumber-major loop most of a wave would idle through each line's profile). Per pass
+// of 64 staged lines, four threads per line evaluate the profile at the line's window
+// points inside the tile into LDS, marking each evaluated point; then every lane adds, in
+// line order, the marked values at its own wavenumber. Same terms, same order and the same
+// per-term arithmetic as the wavenumber-major kernel.
+template <typename T>
+__global__ void __launch_bounds__(kOpThreads)
+    k_opacity_narrow(LineArrays ln, CellGrid cg, double nu_start, double dnu, int n_nu, double cutoff,
+                     const double* __restrict__ extremes, WeidemanCoef wc, T* __restrict__ out) {
+    __shared__ StagedLines sl;
+    __shared__ double s_f[kNarrowLines][kNarrowPts];        // profile values, point j of the line's span
+    __shared__ unsigned long long s_mask[kNarrowLines][4];  // bit j of mask[j % 4]: value j was evaluated
+    __shared__ int s_k0[kNarrowLines], s_n[kNarrowLines];   // first grid point and length of the span
+    __shared__ int64_t range[2];
+    static_assert(kNarrowPts <= 64 && kNarrowLines * 4 == kOpThreads, "pass layout");
+    const int cell = blockIdx.y;
+    const double T_ = cg.temp[cell / cg.n_p];
+    const double p = cg.p_bar[cell % cg.n_p];
+    const int tile0 = blockIdx.x * kOpThreads;
+    const int tile1 = min(tile0 + kOpThreads - 1, n_nu - 1);
+    const int k = tile0 + threadIdx.x;
+    const double nu = nu_start + dnu * (double)k;
+    const double t_lo = nu_start + dnu * (double)(blockIdx.x * kOpThreads);
+    const double t_hi = nu_start + dnu * (double)min(blockIdx.x * kOpThreads + kOpThreads - 1, n_nu - 1);
+
+    const double pfac = (p / kAtmBar) * sqrt(kTRef / T_);
+    const double wmax = cell_wmax(extremes, T_, pfac, cutoff, dnu);
+    if (!narrow_cell(wmax, dnu)) return;  // the wavenumber-major kernel builds this cell
+    if (threadIdx.x == 0) line_range(ln, t_lo - wmax, t_hi + wmax, range);
+    __syncthreads();
+    const int64_t first = range[0], last = range[1];
+    const double qratio = pow(kTRef / T_, 1.5);
+    const int ql = threadIdx.x >> 2, r = threadIdx.x & 3;
+    double acc = 0.0;
+    for (int64_t c0 = first; c0 < last; c0 += kOpThreads) {
+        const int64_t i = c0 + threadIdx.x;
+        if (i < last) stage_line(ln, i, threadIdx.x, T_, pfac, cutoff, qratio, sl);
+        __syncthreads();
+        const int cnt = (int)min((int64_t)kOpThreads, last - c0);
+        for (int sub = 0; sub < cnt; sub += kNarrowLines) {
+            const int q = sub + ql;
+            unsigned long long mask = 0;
+            if (q < cnt) {
+                // grid points that can lie in the window, one point of margin on each side
+                // (kb - ka + 1 <= 2 half / dnu + 5 <= 2 wmax / dnu + 3 <= kNarrowPts),
+                // clipped to the tile
+                const double nu0 = sl.nu0[q], half = sl.half[q];
+                const int ka = max((int)floor((nu0 - half - nu_start) / dnu) - 1, tile0);
+                const int kb = min((int)ceil((nu0 + half - nu_start) / dnu) + 1, tile1);
+                const int n = min(kb - ka + 1, kNarrowPts);
+                if (r == 0) {
+                    s_k0[ql] = ka;
+                    s_n[ql] = n;
+                }
+                for (int j = r; j < n; j += 4) {
+                    const double d = (nu_start + dnu * (double)(ka + j)) - nu0;
+                    if (fabs(d) <= half) {
+                        s_f[ql][j] = faddeeva_re(d * sl.inv[q], sl.y[q], wc);
+                        mask |= 1ull << j;
+                    }
+                }
+            }
+            s_mask[ql][r] = mask;
+            __syncthreads();
+            if (k < n_nu) {
+                const int qn = min(kNarrowLines, cnt - sub);
+                for (int l = 0; l < qn; ++l) {
+                    const int j = k - s_k0[l];
+                    if (j >= 0 && j < s_n[l] && ((s_mask[l][j & 3] >> j) & 1ull))
+                        acc += sl.amp[sub + l] * s_f[l][j];
+                }
+            }
+            __syncthreads();
+        }
     }
     if (k < n_nu) out[(size_t)cell * n_nu + k] = (T)acc;
 }
@@ -190,12 +298,20 @@ extern "C" int bm_opacity_table_build(const double* nu0, const double* s296, con
     if (n_lines > 0) hipLaunchKernelGGL(k_line_extremes, dim3(1), dim3(256), 0, st, ln, d_ext);
     BM_CHECK_HIP(hipGetLastError());
     dim3 grid((n_nu + kOpThreads - 1) / kOpThreads, n_temp * n_p);
-    if (dtype == BM_F32)
+    // every cell is built by exactly one of the two kernels (the other's workgroups exit)
+    if (dtype == BM_F32) {
         hipLaunchKernelGGL(k_opacity_gather<float>, grid, dim3(kOpThreads), 0, st, ln, cg, nu_start, dnu, n_nu,
                            cutoff_hwhm, d_ext, weideman(), (float*)sigma_out);
-    else
+        BM_CHECK_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_opacity_narrow<float>, grid, dim3(kOpThreads), 0, st, ln, cg, nu_start, dnu, n_nu,
+                           cutoff_hwhm, d_ext, weideman(), (float*)sigma_out);
+    } else {
         hipLaunchKernelGGL(k_opacity_gather<double>, grid, dim3(kOpThreads), 0, st, ln, cg, nu_start, dnu,
                            n_nu, cutoff_hwhm, d_ext, weideman(), (double*)sigma_out);
+        BM_CHECK_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_opacity_narrow<double>, grid, dim3(kOpThreads), 0, st, ln, cg, nu_start, dnu,
+                           n_nu, cutoff_hwhm, d_ext, weideman(), (double*)sigma_out);
+    }
     BM_CHECK_HIP(hipGetLastError());
     return BM_OK;
 }
