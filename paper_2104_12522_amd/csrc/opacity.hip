@@ -1,14 +1,17 @@
 // Secondary path: line-by-line opacity table (Sec. 3 and Sec. 4, first pass; Sec. 6.1.1,
 // Voigt profile Eqs. 4-11; Sec. 4, point sampling at the output wavenumbers).
 //
-// Kernel k_opacity_gather: one workgroup owns 256 consecutive output wavenumbers of one
-// (T, p) cell. The lines are sorted by centre, so the lines that can reach the tile form
-// one index range, found by binary search with the widest possible window of the cell.
-// The range is staged through LDS 256 lines at a time (per-line strength, Doppler and
-// Lorentz widths and window computed once per workgroup), and every lane sums the
-// profiles of the staged lines whose window contains its wavenumber, in double, in line
-// order. No atomics: each output element is written once, so results are deterministic.
-// The Faddeeva function is in voigt.h.
+// Kernels k_opacity_gather and k_opacity_narrow: one workgroup owns 256 consecutive output
+// wavenumbers of one (T, p) cell. The lines are sorted by centre, so the lines that can
+// reach the tile form one index range, found by binary search with the widest possible
+// window of the cell. The range is staged through LDS 256 lines at a time (per-line
+// strength, Doppler and Lorentz widths and window computed once per workgroup). Each cell
+// is built by one of the two kernels, chosen by its widest window: wavenumber-major (every
+// lane sums the profiles of the staged lines whose window contains its wavenumber) or, for
+// windows of a few grid points, line-major (threads evaluate each line's window points,
+// then every lane sums its own). Both sum in double, in line order, with no atomics: each
+// output element is written once, so results are deterministic. The Faddeeva function is
+// in voigt.h.
 #include "voigt.h"
 
 namespace bm {
