@@ -77,6 +77,31 @@ def test_opacity_build_config4_subset():
                    torch.float32, rtol=2e-6)
 
 
+
+def _window_span(lines, temp, p_bar, dnu, cutoff=25.0):
+    """Grid points (plus rounding margin) of the widest window of a cell, by the rule that
+    sends a cell to the line-major kernel when it is at most 48: the widest line's Doppler
+    and Lorentz widths, 2 wmax / dnu + 3 with wmax = cutoff HWHM + dnu."""
+    kb, amu, c = 1.380649e-16, 1.66053906660e-24, 2.99792458e10
+    gm = lines.gamma296.max() * (p_bar / 1.01325) * np.sqrt(296.0 / temp)
+    sm = (lines.nu0 / np.sqrt(lines.mass_amu)).max() / c * np.sqrt(kb * temp / amu)
+    w = cutoff * oop.voigt_hwhm(sm, gm) + dnu
+    return 2.0 * w / dnu + 3.0
+
+
+def test_opacity_build_dense_narrow_lines():
+    """Cells on both sides of the split between the line-major and wavenumber-major
+    kernels, one close to the 48-point limit; ~450 lines reach each 256-point tile (two
+    staging rounds, several 64-line passes); lines centred beyond both ends of the grid and
+    a ragged last tile."""
+    lines = wl.line_list(6000, seed=7, nu_min=1995.0, nu_max=2035.0)
+    temps, p_bar, dnu = [300.0, 2350.0, 2600.0], [1e-6, 1e-2, 0.3], 0.01
+    spans = np.array([[_window_span(lines, t, p, dnu) for p in p_bar] for t in temps])
+    assert np.any((spans > 44) & (spans <= 48)) and np.any((spans > 48) & (spans < 52))
+    assert np.any(spans <= 48) and np.any(spans > 60)
+    _compare_table(lines, temps, p_bar, 2000.0, dnu, 3100, torch.float64, rtol=1e-9)
+    _compare_table(lines, temps[1:], p_bar[:2], 2000.0, dnu, 3100, torch.float32, rtol=2e-6)
+
 # ---- profile-table mode (Sec. 4 items 4-6) ---------------------------------------------
 def _node_grid(lines, temps, p_bar, n_sigma, n_gamma):
     """Nodes log-spaced over the widths the lines take in these cells (the paper's
