@@ -134,10 +134,31 @@ def section_forward(args, setup, model, prior):
     params = torch.as_tensor(prior.draw(n_draw, seed=args.seed + 1), device="cuda").contiguous()
     rows = [params[i:i + 1] for i in range(n_draw)]
     f = bm.Forward(model, 1, binned=True, chi2=True)
-    chosen, times = f.tune(rows[0], reps=50)
+    tuned, times = f.tune(rows[0], reps=50)
     cfg_names = bm.forward_configs()
-    log(f"forward: autotuned one-spectrum call -> config {chosen} ({cfg_names[chosen]}); us per call "
+    log(f"forward: autotuned one-spectrum call -> config {tuned} ({cfg_names[tuned]}); us per call "
         f"{[round(t * 1e3, 1) for t in times]}")
+    # The tuner repeats one parameter set, so every repetition reads the same table rows;
+    # the timed loop draws new parameters for each call, which read rows that the 256 MB
+    # Infinity Cache holds only in part (the tables are 960 MB). Its two best candidates
+    # are timed again that way (300 calls each, two interleaved rounds) and the faster kept.
+    cands = [c for _, c in sorted((t, c) for c, t in enumerate(times) if t > 0)[:2]]
+    steady = {c: 0.0 for c in cands}
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for _ in range(2):
+        for c in cands:
+            f.set_config(c)
+            f(rows[0])
+            e0.record()
+            for i in range(300):
+                f(rows[i % n_draw])
+            e1.record()
+            torch.cuda.synchronize()
+            steady[c] += e0.elapsed_time(e1) / 600
+    chosen = min(steady, key=steady.get)
+    f.set_config(chosen)
+    log(f"forward: varied-parameter check of configs {cands}: us per call "
+        f"{[round(steady[c] * 1e3, 2) for c in cands]} -> config {chosen} ({cfg_names[chosen]})")
     for i in range(args.warmup):
         f(rows[i])
     torch.cuda.synchronize()
@@ -173,7 +194,8 @@ def section_forward(args, setup, model, prior):
                      "call_us": ms * 1e3,
                      "call_frac": bytes_spec / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "last_flags": int(f.flags[0]),
-        "autotune": {"chosen": chosen, "configs": cfg_names, "ms_per_call": times},
+        "autotune": {"chosen": chosen, "tuner_choice": tuned, "configs": cfg_names, "ms_per_call": times,
+                     "varied_check_ms_per_call": {str(c): steady[c] for c in cands}},
     }
     if args.workers > 1:
         out["multi_worker"] = multi_worker(args, model, rows)
