@@ -729,6 +729,40 @@ def cpu_baseline(setup, sigma_np, cia_np, params, budget_s: float):
                       f"float64 numpy, single thread, {dt:.1f} s"}
 
 
+def cpu_baseline_opacity(seed: int):
+    """The oracle's line-by-line build beside the library's on the same bounded sample of
+    the opacity-build workload: its first 1e4 lines on its 1e5-point grid, at 1442.58 K and
+    1e-8, 0.33516 and 100 bar (Doppler, intermediate and pressure-broadened cells)."""
+    import torch
+    import workloads as wl
+    import paper_2104_12522_amd as bm
+    from oracle import opacity as oop
+    nu, _, _ = wl.config4_grid()
+    lines = wl.config4_lines(10_000, seed=seed)
+    temps, p_bar = [1442.58], [1e-8, 0.33516, 100.0]
+    dnu = float(nu[1] - nu[0])
+    evals = window_evaluations(lines, nu, temps, p_bar, sample=10_000, seed=seed)
+    t0 = time.perf_counter()
+    for p in p_bar:
+        oop.cell_cross_section(lines, temps[0], p, float(nu[0]), dnu, nu.size)
+    t_cpu = time.perf_counter() - t0
+    out = torch.empty(1, len(p_bar), nu.size, dtype=torch.float32, device="cuda")
+    bm.opacity_table_build(lines, temps, p_bar, float(nu[0]), dnu, nu.size, out=out)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    bm.opacity_table_build(lines, temps, p_bar, float(nu[0]), dnu, nu.size, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    t_gpu = e0.elapsed_time(e1) * 1e-3
+    return {"kind": "oracle", "cores": 1, "profile_evaluations": evals,
+            "oracle_s": t_cpu, "oracle_evaluations_per_s": evals / t_cpu,
+            "gpu_s": t_gpu, "gpu_evaluations_per_s": evals / t_gpu,
+            "sample": "first 1e4 lines of the opacity-build workload, 1e5 nu, T 1442.58 K, "
+                      "p 1e-8 / 0.33516 / 100 bar; oracle float64 numpy (scipy wofz), single "
+                      "thread; GPU float32 table, FP64 arithmetic"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -800,6 +834,8 @@ def main():
         setup_cpu.bin_width = 0
         out["cpu_baseline"] = cpu_baseline(setup_cpu, sig_np, cia_np, params_np, args.cpu_seconds)
         del sig_np
+        log("timing the CPU oracle's opacity build on a line subset")
+        out["cpu_baseline"]["opacity_subset"] = cpu_baseline_opacity(wl.SEED_BASE + 4)
     if "batched" in sections:
         out["batched"] = section_batched(args, setup, model, prior)
     if "mcmc" in sections:
