@@ -12,6 +12,8 @@
 // then every lane sums its own). Both sum in double, in line order, with no atomics: each
 // output element is written once, so results are deterministic. The Faddeeva function is
 // in voigt.h.
+#include <type_traits>
+
 #include "voigt.h"
 
 namespace bm {
@@ -167,7 +169,11 @@ __global__ void __launch_bounds__(kOpThreads)
     k_opacity_narrow(LineArrays ln, CellGrid cg, double nu_start, double dnu, int n_nu, double cutoff,
                      const double* __restrict__ extremes, WeidemanCoef wc, T* __restrict__ out) {
     __shared__ StagedLines sl;
-    __shared__ double s_f[kNarrowLines][kNarrowPts];        // profile values, point j of the line's span
+    // profile values, point j of the line's span: float for a float table (each term then
+    // carries a relative error of 6e-8, the table's own resolution; the sum stays in
+    // double), which halves the buffer and raises the workgroups per CU from 4 to 6
+    using FVal = typename std::conditional<sizeof(T) == 4, float, double>::type;
+    __shared__ FVal s_f[kNarrowLines][kNarrowPts];
     __shared__ unsigned long long s_mask[kNarrowLines][4];  // bit j of mask[j % 4]: value j was evaluated
     __shared__ int s_k0[kNarrowLines], s_n[kNarrowLines];   // first grid point and length of the span
     __shared__ int64_t range[2];
@@ -214,7 +220,7 @@ __global__ void __launch_bounds__(kOpThreads)
                 for (int j = r; j < n; j += 4) {
                     const double d = (nu_start + dnu * (double)(ka + j)) - nu0;
                     if (fabs(d) <= half) {
-                        s_f[ql][j] = faddeeva_re(d * sl.inv[q], sl.y[q], wc);
+                        s_f[ql][j] = (FVal)faddeeva_re(d * sl.inv[q], sl.y[q], wc);
                         mask |= 1ull << j;
                     }
                 }
@@ -226,7 +232,7 @@ __global__ void __launch_bounds__(kOpThreads)
                 for (int l = 0; l < qn; ++l) {
                     const int j = k - s_k0[l];
                     if (j >= 0 && j < s_n[l] && ((s_mask[l][j & 3] >> j) & 1ull))
-                        acc += sl.amp[sub + l] * s_f[l][j];
+                        acc += sl.amp[sub + l] * (double)s_f[l][j];
                 }
             }
             __syncthreads();
