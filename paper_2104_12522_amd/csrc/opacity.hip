@@ -162,8 +162,9 @@ __global__ void __launch_bounds__(kOpThreads)
 // wavenumber-major loop most of a wave would idle through each line's profile). Per pass
 // of 64 staged lines, four threads per line evaluate the profile at the line's window
 // points inside the tile into LDS, marking each evaluated point; then every lane adds, in
-// line order, the marked values at its own wavenumber. Same terms, same order and the same
-// per-term arithmetic as the wavenumber-major kernel.
+// line order, the marked values at its own wavenumber. Same terms and order as the
+// wavenumber-major kernel; each value is the same double, kept as a float for a float
+// table.
 template <typename T>
 __global__ void __launch_bounds__(kOpThreads)
     k_opacity_narrow(LineArrays ln, CellGrid cg, double nu_start, double dnu, int n_nu, double cutoff,
