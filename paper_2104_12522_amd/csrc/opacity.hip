@@ -12,6 +12,7 @@
 // then every lane sums its own). Both sum in double, in line order, with no atomics: each
 // output element is written once, so results are deterministic. The Faddeeva function is
 // in voigt.h.
+#include <algorithm>
 #include <type_traits>
 
 #include "voigt.h"
@@ -36,14 +37,12 @@ struct CellGrid {
     int n_p;
 };
 
-// widest window inputs over all lines: [0] max gamma296, [1] max nu0 / sqrt(mass)
-__global__ void k_line_extremes(LineArrays ln, double* out) {
-    __shared__ double s0[256], s1[256];
-    double g = 0.0, d = 0.0;
-    for (int64_t i = threadIdx.x; i < ln.n; i += blockDim.x) {
-        g = fmax(g, ln.gamma296[i]);
-        d = fmax(d, ln.nu0[i] / sqrt(ln.mass[i]));
-    }
+// widest window inputs over all lines, max gamma296 and max nu0 / sqrt(mass), in two
+// stages: up to kExtBlocks workgroups each reduce a grid-strided share of the lines into
+// out[2 + 2 b], out[3 + 2 b]; one workgroup then reduces those into out[0], out[1] (maxima
+// are exact in any order)
+constexpr int kExtBlocks = 256;
+__device__ __forceinline__ void block_max2(double& g, double& d, double* s0, double* s1) {
     s0[threadIdx.x] = g;
     s1[threadIdx.x] = d;
     __syncthreads();
@@ -54,9 +53,35 @@ __global__ void k_line_extremes(LineArrays ln, double* out) {
         }
         __syncthreads();
     }
+    g = s0[0];
+    d = s1[0];
+}
+
+__global__ void __launch_bounds__(256) k_line_extremes(LineArrays ln, double* out) {
+    __shared__ double s0[256], s1[256];
+    double g = 0.0, d = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ln.n; i += (int64_t)gridDim.x * blockDim.x) {
+        g = fmax(g, ln.gamma296[i]);
+        d = fmax(d, ln.nu0[i] / sqrt(ln.mass[i]));
+    }
+    block_max2(g, d, s0, s1);
     if (threadIdx.x == 0) {
-        out[0] = s0[0];
-        out[1] = s1[0];
+        out[2 + 2 * blockIdx.x] = g;
+        out[3 + 2 * blockIdx.x] = d;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_line_extremes_final(double* out, int n_blocks) {
+    __shared__ double s0[256], s1[256];
+    double g = 0.0, d = 0.0;
+    for (int b = threadIdx.x; b < n_blocks; b += blockDim.x) {
+        g = fmax(g, out[2 + 2 * b]);
+        d = fmax(d, out[3 + 2 * b]);
+    }
+    block_max2(g, d, s0, s1);
+    if (threadIdx.x == 0) {
+        out[0] = g;
+        out[1] = d;
     }
 }
 
@@ -266,15 +291,16 @@ extern "C" int bm_voigt(const double* x, int64_t n, double sigma, double gamma, 
     return BM_OK;
 }
 
-// The widest-window inputs (two doubles) live in a 256-byte buffer per device, allocated
-// on the first call on that device and held until the process ends.
+// The widest-window inputs (two doubles, then the per-workgroup partials) live in a
+// buffer per device, allocated on the first call on that device and held until the
+// process ends.
 static double* extremes_buffer() {
     static double* per_device[64] = {nullptr};
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
     if (!per_device[dev]) {
         void* p = nullptr;
-        if (hipMalloc(&p, 256) != hipSuccess) return nullptr;
+        if (hipMalloc(&p, sizeof(double) * (2 + 2 * kExtBlocks)) != hipSuccess) return nullptr;
         per_device[dev] = (double*)p;
     }
     return per_device[dev];
@@ -305,7 +331,12 @@ extern "C" int bm_opacity_table_build(const double* nu0, const double* s296, con
     double* d_ext = extremes_buffer();
     if (!d_ext) return BM_EHIP;
     LineArrays ln{nu0, s296, gamma296, elow, mass_amu, n_lines};
-    if (n_lines > 0) hipLaunchKernelGGL(k_line_extremes, dim3(1), dim3(256), 0, st, ln, d_ext);
+    if (n_lines > 0) {
+        const int nb = (int)std::min<int64_t>(kExtBlocks, (n_lines + 255) / 256);
+        hipLaunchKernelGGL(k_line_extremes, dim3(nb), dim3(256), 0, st, ln, d_ext);
+        BM_CHECK_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_line_extremes_final, dim3(1), dim3(256), 0, st, d_ext, nb);
+    }
     BM_CHECK_HIP(hipGetLastError());
     dim3 grid((n_nu + kOpThreads - 1) / kOpThreads, n_temp * n_p);
     // every cell is built by exactly one of the two kernels (the other's workgroups exit)
