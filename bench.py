@@ -440,8 +440,8 @@ def section_mcmc(args, setup, prior):
     # 3. local surrogate: inputs on a +-5 sd box around the burn-in states, outputs
     #    standardised on spectra drawn around them (BF16 inputs resolve ~1/256 of the box)
     t0 = time.perf_counter()
-    lo_l = np.maximum(mu_b - 5 * sd_b, prior.lo)
-    hi_l = np.minimum(mu_b + 5 * sd_b, prior.hi)
+    lo_l = np.maximum(mu_b - args.surrogate_box * sd_b, prior.lo)
+    hi_l = np.minimum(mu_b + args.surrogate_box * sd_b, prior.hi)
     Xl = dev(gaussian_states(mu_b, cov_b, args.local_spectra, lo_l, hi_l, seed=args.seed + 65,
                              inflate=2.0))
     Yl = spectra(Xl)
@@ -474,8 +474,8 @@ def section_mcmc(args, setup, prior):
         m = rd.s.archive_size
         z0 = rd.s.z[max(0, m - 10 * C):m].clone()
         t0 = time.perf_counter()
-        lo_l = np.maximum(mu_b - 5 * sd_b, prior.lo)
-        hi_l = np.minimum(mu_b + 5 * sd_b, prior.hi)
+        lo_l = np.maximum(mu_b - args.surrogate_box * sd_b, prior.lo)
+        hi_l = np.minimum(mu_b + args.surrogate_box * sd_b, prior.hi)
         Xl = dev(gaussian_states(mu_b, cov_b, args.local_spectra, lo_l, hi_l, seed=args.seed + 68,
                                  inflate=2.0))
         Yl = spectra(Xl)
@@ -787,6 +787,8 @@ def main():
                     help="further burn-in generations with delayed acceptance before production")
     ap.add_argument("--per-sample-gens", type=int, default=200)
     ap.add_argument("--train-spectra", type=int, default=200000)
+    ap.add_argument("--surrogate-box", type=float, default=5.0,
+                    help="half-width of the local surrogate's input box, in burn-in sd")
     ap.add_argument("--local-spectra", type=int, default=100000)
     ap.add_argument("--epochs", type=int, default=30)
     ap.add_argument("--opacity-lines", type=int, default=10_000_000)
