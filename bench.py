@@ -541,6 +541,16 @@ def section_mcmc(args, setup, prior):
     da_rep, mu_r, sd_r = stats(h_r, w_r, acc_r, G)
     del h_r
     diff_rep = (mu_r - mu_d) / sd_b2
+    plain_rep = None
+    if args.plain_replicate:
+        # opt-in: a second plain run on another random stream, the plain sampler's own spread
+        log(f"mcmc: plain batched replicate (another random stream), {G} generations")
+        _, h_q, w_q, acc_q = production(stream=72)
+        pq, mu_q, _ = stats(h_q, w_q, acc_q, G)
+        del h_q
+        plain_rep = {"ess": pq["ess"], "acceptance": pq["acceptance"],
+                     "marginal_mean_diff_sd_vs_plain": ((mu_q - mu_b2) / sd_b2).tolist(),
+                     "marginal_mean_diff_sd_vs_delayed_acceptance": ((mu_q - mu_d) / sd_b2).tolist()}
     log(f"mcmc: plain per-sample, {args.per_sample_gens} generations timed")
     _, h_p, w_p, _ = production(per_sample=1, n_gen=args.per_sample_gens)
     identical = bool(torch.equal(h_p, h_b[:args.per_sample_gens]))
@@ -590,6 +600,7 @@ def section_mcmc(args, setup, prior):
         "marginal_mean": {"plain": mu_b2.tolist(), "delayed_acceptance": mu_d.tolist(),
                           "delayed_acceptance_replicate": mu_r.tolist()},
         "marginal_sd": {"plain": sd_b2.tolist(), "delayed_acceptance": sd_d.tolist()},
+        **({"plain_replicate": plain_rep} if plain_rep is not None else {}),
     }
 
 
@@ -787,6 +798,8 @@ def main():
                     help="further burn-in generations with delayed acceptance before production")
     ap.add_argument("--per-sample-gens", type=int, default=200)
     ap.add_argument("--train-spectra", type=int, default=200000)
+    ap.add_argument("--plain-replicate", action="store_true",
+                    help="also run a second plain production on another random stream")
     ap.add_argument("--surrogate-box", type=float, default=5.0,
                     help="half-width of the local surrogate's input box, in burn-in sd")
     ap.add_argument("--local-spectra", type=int, default=100000)
