@@ -131,38 +131,34 @@ def point_cross_section(lines, temp: float, p_bar: float, nu: float) -> float:
 
 
 # ---- the paper's profile-table mode (Sec. 4 items 4-6; Sec. 4, integer-shift sampling) ----
-# Widths and positions that decide an integer (profile node, shift, extent) are written with
-# the operation order the library uses, so that both sides take the same decisions.
-
-TWO_LN2 = 1.3862943611198906  # 2 ln 2
-
-
-def table_hwhm(sigma, gamma):
-    """Olivero-Longbothum Voigt HWHM, 0.5346 gamma + sqrt(0.2166 gamma^2 + 2 ln2 sigma^2)."""
-    return 0.5346 * gamma + np.sqrt(0.2166 * gamma * gamma + TWO_LN2 * sigma * sigma)
+# Profiles are kept in double precision and every width, extent, node and shift comes from
+# the direct-mode functions above, written plainly. Integer decisions (extent, node, shift)
+# are exact functions of these doubles; a value that lands within rounding of a decision
+# boundary (an integer extent, a node midpoint, a half-integer shift) can go either way in
+# another implementation, so parity cases keep their inputs away from such ties.
 
 
 def profile_table(sigma_nodes, gamma_nodes, dnu: float, oversample: int, cutoff_hwhm: float):
     """Sec. 4 item 4: the 3D table of Voigt profiles. Profile (i, j) has Doppler width
     sigma_i and Lorentz half width gamma_j; it is sampled oversample times per output
     interval (fine step delta = dnu / oversample, so that the samples align with the
-    output grid) over t = -T..T fine steps, T = floor(cutoff_hwhm HWHM_ij / delta), and
-    stored in single precision. Returns dict(ext[i][j] = T, prof[(i, j)] = values at
-    t = -T..T, delta, oversample, sigma_nodes, gamma_nodes)."""
+    output grid) over t = -T..T fine steps, T = floor(cutoff_hwhm HWHM_ij / delta).
+    Returns dict(ext[i][j] = T, prof[(i, j)] = values at t = -T..T (double), delta,
+    oversample, sigma_nodes, gamma_nodes)."""
     sigma_nodes = np.asarray(sigma_nodes, dtype=np.float64)
     gamma_nodes = np.asarray(gamma_nodes, dtype=np.float64)
     delta = dnu / oversample
     ext = np.zeros((sigma_nodes.size, gamma_nodes.size), dtype=np.int64)
     for i, s in enumerate(sigma_nodes):
         for j, g in enumerate(gamma_nodes):
-            ext[i, j] = int(math.floor(cutoff_hwhm * table_hwhm(s, g) / delta))
+            ext[i, j] = int(math.floor(cutoff_hwhm * voigt_hwhm(s, g) / delta))
 
     class _Profiles(dict):
         # the values of a profile are evaluated when first used
         def __missing__(self, key):
             i, j = key
             t = np.arange(-ext[i, j], ext[i, j] + 1, dtype=np.float64)
-            val = voigt(t * delta, sigma_nodes[i], gamma_nodes[j]).astype(np.float32)
+            val = voigt(t * delta, sigma_nodes[i], gamma_nodes[j])
             self[key] = val
             return val
 
@@ -179,11 +175,10 @@ def nearest_node(x, nodes):
 
 
 def table_line_parameters(lines, temp: float, p_bar: float):
-    """S(T), Doppler sigma and Lorentz gamma of every line, as in the direct mode."""
-    s_t = line_strength(lines.s296, lines.nu0, lines.elow, temp)
-    sig = lines.nu0 / C_LIGHT * np.sqrt(K_B * temp / (lines.mass_amu * M_U))
-    gam = lines.gamma296 * (p_bar / ATM_BAR) * np.sqrt(T_REF / temp)
-    return s_t, sig, gam
+    """S(T), Doppler sigma and Lorentz gamma of every line: the direct mode's functions."""
+    return (line_strength(lines.s296, lines.nu0, lines.elow, temp),
+            doppler_sigma(lines.nu0, lines.mass_amu, temp),
+            lorentz_gamma(lines.gamma296, temp, p_bar))
 
 
 def table_cell_cross_section(lines, temp: float, p_bar: float, nu_start: float, n_nu: int, table,
@@ -215,7 +210,7 @@ def table_cell_cross_section(lines, temp: float, p_bar: float, nu_start: float, 
         if k_hi < k_lo:
             continue
         k = np.arange(k_lo, k_hi + 1, dtype=np.int64)
-        vals = table["prof"][i, j][k * O - s + t_max].astype(np.float64)
+        vals = table["prof"][i, j][k * O - s + t_max]
         out[k_lo:k_hi + 1] += strength * vals
     return out
 

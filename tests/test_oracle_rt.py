@@ -313,6 +313,27 @@ def test_rayleigh_h2_cross_section():
     assert 1.0 < rt.rayleigh_h2(np.array([20000.0]))[0] / leading < 1.1
 
 
+def test_rayleigh_h2_leading_coefficient_from_refractivity():
+    # the Rayleigh cross section of a gas from its refractive index (Lorenz-Lorentz):
+    # sigma = 24 pi^3 / (lam^4 N^2) ((n^2 - 1) / (n^2 + 2))^2 at the number density N of the
+    # refractivity measurement (0 C, 1 atm: Loschmidt N = 2.6868e19 cm^-3). Published H2
+    # refractivities there are n - 1 = 1.32e-4 to 1.36e-4 at long wavelengths and up to
+    # 1.40e-4 at 5000 A; the depolarisation (King) correction adds a few per cent. The
+    # expansion must fall inside that band, widened by -5 % / +10 %; a wrong power of ten,
+    # a wrong wavelength unit or a dropped pi^3 falls far outside it.
+    N = 2.6868e19
+
+    def lorenz(n_minus_1, lam_cm):
+        n2 = (1.0 + n_minus_1) ** 2
+        return 24 * math.pi ** 3 / (lam_cm ** 4 * N ** 2) * ((n2 - 1) / (n2 + 2)) ** 2
+
+    lam_a = 1.0e7                        # 1 mm: the lam^-6 and lam^-8 terms are negligible
+    got = rt.rayleigh_h2(np.array([1e8 / lam_a]))[0]
+    assert 0.95 * lorenz(1.32e-4, lam_a * 1e-8) <= got <= 1.10 * lorenz(1.36e-4, lam_a * 1e-8)
+    got5 = rt.rayleigh_h2(np.array([20000.0]))[0]   # 5000 A, the whole expansion
+    assert 0.95 * lorenz(1.36e-4, 5000e-8) <= got5 <= 1.10 * lorenz(1.40e-4, 5000e-8)
+
+
 def test_cloud_layer_index():
     p = np.logspace(2, -8, 11)            # 100 ... 1e-8 bar, deepest first
     assert rt.cloud_layer(p, 3.0) == -1   # below every layer

@@ -85,6 +85,55 @@ def test_widths_reference_conditions():
     assert hw == pytest.approx(3.581e-7 * 2000.0 * math.sqrt(296.0 / 18.0), rel=2e-4)
 
 
+def test_line_strength_partition_direction():
+    # E'' = 0 removes the Boltzmann factor, and at nu0 = 1e5 cm^-1 the stimulated-emission
+    # factor 1 - exp(-c2 nu0 / T) is 1 to within exp(-48) for every T below 3000 K, so
+    # S(T)/S(296) is the partition ratio alone: Q ~ T^1.5 makes it (296/T)^1.5 -- a smaller
+    # strength when hotter (Q(T)/Q(296) in its place would give the inverse)
+    for T in (148.0, 592.0, 1184.0, 2960.0):
+        s = op.line_strength(np.array([1.0]), np.array([1e5]), np.array([0.0]), T)[0]
+        assert s == pytest.approx((296.0 / T) ** 1.5, rel=1e-12)
+    # and between two temperatures S(T1)/S(T2) = (T2/T1)^1.5
+    s1 = op.line_strength(np.array([1.0]), np.array([1e5]), np.array([0.0]), 700.0)[0]
+    s2 = op.line_strength(np.array([1.0]), np.array([1e5]), np.array([0.0]), 2100.0)[0]
+    assert s1 / s2 == pytest.approx(3.0 ** 1.5, rel=1e-12)
+
+
+def test_line_strength_stimulated_emission_limit():
+    # c2 nu0 << T: 1 - exp(-c2 nu0 / T) -> c2 nu0 / T, so the stimulated-emission factor
+    # contributes 296/T and with the partition ratio S(T)/S(296) -> (296/T)^2.5; at
+    # nu0 = 1e-4 cm^-1 the next order is c2 nu0 / (2 T) < 3e-7 relative
+    for T in (1184.0, 2960.0):
+        s = op.line_strength(np.array([1.0]), np.array([1e-4]), np.array([0.0]), T)[0]
+        assert s == pytest.approx((296.0 / T) ** 2.5, rel=1e-6)
+    # the factor is absent at the reference temperature whatever nu0
+    s = op.line_strength(np.array([1.0, 1.0]), np.array([1e-4, 1e5]), np.array([0.0, 0.0]), 296.0)
+    np.testing.assert_allclose(s, 1.0, rtol=1e-12)
+
+
+def test_lorentz_width_scaling():
+    # Eq. 3 widths scale linearly with pressure (in atmospheres) and as T^-1/2:
+    # twice the pressure doubles the width, four times the reference temperature halves it
+    g = 0.07
+    assert op.lorentz_gamma(g, 296.0, 2 * 1.01325) == pytest.approx(2 * g, rel=1e-15)
+    assert op.lorentz_gamma(g, 4 * 296.0, 1.01325) == pytest.approx(g / 2, rel=1e-15)
+    assert op.lorentz_gamma(g, 4 * 296.0, 2 * 1.01325) == pytest.approx(g, rel=1e-15)
+    # 1 bar is 1/1.01325 atm
+    assert op.lorentz_gamma(g, 296.0, 1.0) == pytest.approx(g / 1.01325, rel=1e-15)
+
+
+def test_doppler_width_scaling():
+    # thermal Doppler width ~ nu0 sqrt(T / m): doubles at four times the temperature,
+    # halves at four times the mass, doubles at twice the line centre
+    base = op.doppler_sigma(2000.0, 18.0, 296.0)
+    assert op.doppler_sigma(2000.0, 18.0, 4 * 296.0) == pytest.approx(2 * base, rel=1e-15)
+    assert op.doppler_sigma(2000.0, 72.0, 296.0) == pytest.approx(base / 2, rel=1e-15)
+    assert op.doppler_sigma(4000.0, 18.0, 296.0) == pytest.approx(2 * base, rel=1e-15)
+    # absolute value at 1184 K: the textbook HWHM 3.581e-7 nu0 sqrt(T / M[amu])
+    hw = math.sqrt(2 * math.log(2)) * op.doppler_sigma(3000.0, 44.0, 1184.0)
+    assert hw == pytest.approx(3.581e-7 * 3000.0 * math.sqrt(1184.0 / 44.0), rel=2e-4)
+
+
 def _single_line(nu0=2000.1, s=1e-20, g=0.07, e=300.0, m=18.015):
     return LineList(np.array([nu0]), np.array([s]), np.array([g]), np.array([e]),
                     np.array([m]))
@@ -166,7 +215,7 @@ def _widths(ln, T=F04_T, p=F04_P):
 
 def test_table_mode_line_on_node_and_sample_equals_direct():
     # a line whose widths are grid nodes and whose centre is a fine sample: the table
-    # mode samples exactly the direct-mode profile (to single-precision storage)
+    # mode samples the direct-mode profile (the two offsets differ by rounding only)
     ln = _single_line(nu0=2000.1)
     _, sig, gam = _widths(ln)
     tab = op.profile_table([sig / 2, sig, 2 * sig], [gam / 3, gam, 3 * gam], 0.005, 100, 25.0)
@@ -177,7 +226,7 @@ def test_table_mode_line_on_node_and_sample_equals_direct():
     s = int(np.rint((ln.nu0[0] - nu_start) / tab["delta"]))
     t = np.arange(n) * 100 - s
     core = np.abs(t) < t_max - 100
-    np.testing.assert_allclose(got[core], ref[core], rtol=2e-7)
+    np.testing.assert_allclose(got[core], ref[core], rtol=1e-9)
     assert np.all(got[np.abs(t) > t_max] == 0.0) and np.all(got[np.abs(t) <= t_max] > 0.0)
 
 
