@@ -47,6 +47,14 @@ def log(msg):
 
 
 # ----------------------------------------------------------------------------- inputs
+def device_lines(lines):
+    """The line list's arrays as device tensors (resident in HBM before a timed build)."""
+    import torch
+    import workloads as wl
+    return wl.LineList(*(torch.as_tensor(np.ascontiguousarray(getattr(lines, f)), device="cuda")
+                         for f in ("nu0", "s296", "gamma296", "elow", "mass_amu")))
+
+
 def build_tables(setup, how: str, seed: int):
     import torch
     import workloads as wl
@@ -618,11 +626,13 @@ def section_opacity(args):
     dnu = float(nu[1] - nu[0])
     bm.opacity_table_build(lines.subset(slice(0, 1000)), temps, p_bar, float(nu[0]), dnu, nu.size,
                            out=out)
+    d_lines = device_lines(lines)
+    ws = bm.opacity_build_workspace(n_lines)
     torch.cuda.synchronize()
     start = torch.cuda.Event(enable_timing=True)
     end = torch.cuda.Event(enable_timing=True)
     start.record()
-    bm.opacity_table_build(lines, temps, p_bar, float(nu[0]), dnu, nu.size, out=out)
+    bm.opacity_table_build(d_lines, temps, p_bar, float(nu[0]), dnu, nu.size, out=out, workspace=ws)
     end.record()
     torch.cuda.synchronize()
     ms = start.elapsed_time(end)
@@ -724,20 +734,91 @@ def section_copy(args):
             "gbs": 8 * n / (ms * 1e-3) / 1e9}
 
 
-def cpu_baseline(setup, sigma_np, cia_np, params, budget_s: float):
-    """The FP64 oracle, as it stands, on a bounded sample of the same workload."""
+def cpu_model_name() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+_POOL_JOB = {}
+
+
+def _oracle_spectrum(i):
     from oracle import rt as ort
-    n = 0
+    j = _POOL_JOB
+    ort.forward(j["params"][i % len(j["params"])], j["setup"], j["sigma"], j["cia"])
+    return i
+
+
+def oracle_pool_main(path: str, budget_s: float, max_workers: int):
+    """Child process of the CPU-baseline leg (no GPU in it): the FP64 oracle on spectra of
+    the headline workload, first on one thread, then as a process pool over all usable
+    host cores; tables memory-mapped from `path` (shared by every worker)."""
+    import multiprocessing as mp
+    import workloads as wl
+    from oracle import rt as ort
+    setup = wl.config2()
+    setup.bin_width = 0
+    sigma = np.load(path + "_sigma.npy", mmap_mode="r")
+    cia = np.load(path + "_cia.npy")
+    params = np.load(path + "_params.npy")
+    # one thread
+    n1, t0 = 0, time.perf_counter()
+    while n1 < 3 or time.perf_counter() - t0 < min(4.0, budget_s / 4):
+        ort.forward(params[n1 % len(params)], setup, sigma, cia)
+        n1 += 1
+    dt1 = time.perf_counter() - t0
+    rate1 = n1 / dt1
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    workers = max(1, min(usable, max_workers))
+    n_par = max(workers, int(rate1 * workers * budget_s * 0.8))
+    _POOL_JOB.update(params=params, setup=setup, sigma=sigma, cia=cia)
+    ctx = mp.get_context("fork")
     t0 = time.perf_counter()
-    while n < len(params):
-        ort.forward(params[n], setup, sigma_np, cia_np)
-        n += 1
-        if time.perf_counter() - t0 > budget_s:
-            break
-    dt = time.perf_counter() - t0
-    return {"value": n / dt, "unit": "spectra/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n} spectra of the full workload (100 layers x 30000 nu, 4 species), "
-                      f"float64 numpy, single thread, {dt:.1f} s"}
+    with ctx.Pool(workers) as pool:
+        for _ in pool.imap_unordered(_oracle_spectrum, range(n_par), chunksize=1):
+            pass
+    dtp = time.perf_counter() - t0
+    print(json.dumps({"n1": n1, "dt1": dt1, "n_par": n_par, "dtp": dtp, "workers": workers,
+                      "usable": usable, "nproc": os.cpu_count(), "cpu_model": cpu_model_name()}),
+          flush=True)
+
+
+def cpu_baseline(sigma_np32, cia_np, params, budget_s: float, max_workers: int):
+    """The FP64 oracle, as it stands, on a bounded sample of the headline workload: one
+    thread, then every usable host core (a process pool over spectra), in a child process
+    that never touches the GPU."""
+    import subprocess
+    import tempfile
+    base = os.path.join("/dev/shm" if os.path.isdir("/dev/shm") else tempfile.gettempdir(),
+                        f"bartmi_oracle_{os.getpid()}")
+    files = [base + x for x in ("_sigma.npy", "_cia.npy", "_params.npy")]
+    try:
+        np.save(files[0], sigma_np32.astype(np.float64))
+        np.save(files[1], cia_np)
+        np.save(files[2], params)
+        res = subprocess.run([sys.executable, os.path.abspath(__file__), "--oracle-pool", base,
+                              "--cpu-seconds", str(budget_s), "--cpu-workers", str(max_workers)],
+                             capture_output=True, text=True, timeout=budget_s * 6 + 120)
+    finally:
+        for f in files:
+            if os.path.exists(f):
+                os.remove(f)
+    if res.returncode != 0:
+        raise RuntimeError("oracle pool failed: " + res.stderr[-2000:])
+    r = json.loads(res.stdout.strip().splitlines()[-1])
+    return {"value": r["n_par"] / r["dtp"], "unit": "spectra/s", "cores": r["workers"], "kind": "oracle",
+            "sample": f"{r['n_par']} spectra of the full workload (100 layers x 30000 nu, 4 species), "
+                      f"float64 numpy, a process pool of {r['workers']} single-threaded workers over "
+                      f"spectra, {r['dtp']:.1f} s",
+            "nproc": r["nproc"], "usable_cores": r["usable"], "cpu_model": r["cpu_model"],
+            "single_thread": {"value": r["n1"] / r["dt1"], "spectra": r["n1"], "seconds": r["dt1"]}}
 
 
 def cpu_baseline_opacity(seed: int):
@@ -758,11 +839,13 @@ def cpu_baseline_opacity(seed: int):
         oop.cell_cross_section(lines, temps[0], p, float(nu[0]), dnu, nu.size)
     t_cpu = time.perf_counter() - t0
     out = torch.empty(1, len(p_bar), nu.size, dtype=torch.float32, device="cuda")
-    bm.opacity_table_build(lines, temps, p_bar, float(nu[0]), dnu, nu.size, out=out)
+    d_lines = device_lines(lines)
+    ws = bm.opacity_build_workspace(len(lines))
+    bm.opacity_table_build(d_lines, temps, p_bar, float(nu[0]), dnu, nu.size, out=out, workspace=ws)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
-    bm.opacity_table_build(lines, temps, p_bar, float(nu[0]), dnu, nu.size, out=out)
+    bm.opacity_table_build(d_lines, temps, p_bar, float(nu[0]), dnu, nu.size, out=out, workspace=ws)
     e1.record()
     torch.cuda.synchronize()
     t_gpu = e0.elapsed_time(e1) * 1e-3
@@ -784,6 +867,9 @@ def main():
                     help="comma list of forward, batched, mcmc, opacity, copy")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-workers", type=int, default=16,
+                    help="most processes of the CPU-baseline pool (capped by the usable cores)")
+    ap.add_argument("--oracle-pool", default=None, help=argparse.SUPPRESS)
     ap.add_argument("--seed", type=int, default=2104_12522 + 2)
     ap.add_argument("--workers", type=int, default=1,
                     help="extra multi-stream figure with W concurrent one-spectrum callers")
@@ -806,6 +892,9 @@ def main():
     ap.add_argument("--epochs", type=int, default=30)
     ap.add_argument("--opacity-lines", type=int, default=10_000_000)
     args = ap.parse_args()
+    if args.oracle_pool:
+        oracle_pool_main(args.oracle_pool, args.cpu_seconds, args.cpu_workers)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU; multi-GPU runs are not "
                                    "part of this build (the forward model shards by chain or "
@@ -843,12 +932,8 @@ def main():
     if not args.no_cpu and "forward" in sections:
         log("timing the CPU oracle")
         params_np = prior.draw(200, seed=args.seed + 1)
-        sig_np = sigma.cpu().numpy().astype(np.float64)
-        cia_np = cia.cpu().numpy().astype(np.float64)
-        setup_cpu = wl.config2()
-        setup_cpu.bin_width = 0
-        out["cpu_baseline"] = cpu_baseline(setup_cpu, sig_np, cia_np, params_np, args.cpu_seconds)
-        del sig_np
+        out["cpu_baseline"] = cpu_baseline(sigma.cpu().numpy(), cia.cpu().numpy().astype(np.float64),
+                                           params_np, args.cpu_seconds, args.cpu_workers)
         log("timing the CPU oracle's opacity build on a line subset")
         out["cpu_baseline"]["opacity_subset"] = cpu_baseline_opacity(wl.SEED_BASE + 4)
     if "batched" in sections:

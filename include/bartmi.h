@@ -420,13 +420,32 @@ int bm_da_accept(const bm_demcz* s, const double* chi2, const int32_t* flags,
  * temp [NT <= BM_MAX_TEMPS] and p_bar [NP <= BM_MAX_LAYERS] are HOST doubles; sigma_out
  * is device [NT][NP][Nnu] of dtype and every element is written once (no zero-fill
  * needed). Each element is a double sum over lines in line order, rounded once: the
- * result is deterministic. On its first call on a device the library allocates 256
- * bytes of device memory there, held until the process ends. */
+ * result is deterministic. `workspace` (device, caller-owned, workspace_bytes >=
+ * bm_opacity_build_workspace(n_lines), no initialisation needed) receives the line list's
+ * extremes that bound every cell's widest window; builds that may overlap need workspaces
+ * of their own (calls on one stream are ordered). The library allocates nothing. Errors:
+ * BM_EINVAL (NULL pointers, non-positive dnu, cutoff, temperature or pressure, bad dtype),
+ * BM_ESHAPE (counts out of range), BM_ENOSPACE (workspace too small). */
+size_t bm_opacity_build_workspace(int64_t n_lines);
 int bm_opacity_table_build(const double* nu0, const double* s296, const double* gamma296,
                            const double* elow, const double* mass_amu, int64_t n_lines,
                            const double* temp, int n_temp, const double* p_bar, int n_p,
                            double nu_start, double dnu, int n_nu, double cutoff_hwhm,
-                           int dtype, void* sigma_out, void* stream);
+                           int dtype, void* sigma_out, void* workspace, size_t workspace_bytes,
+                           void* stream);
+
+/* Range of the line widths over a set of cells (Sec. 4: the profile table spans the
+ * expected Doppler and Lorentz widths; Eq. 2 and Eq. 3 widths as in
+ * bm_opacity_table_build): range_out (device double [4]) = {min sigma_D, max sigma_D,
+ * min gamma_L, max gamma_L} over the n_lines >= 1 lines (device doubles nu0, gamma296,
+ * mass_amu; any order) and every temperature in temp [n_temp] and pressure in p_bar [n_p]
+ * (HOST doubles, bar): sigma_D = nu0/c sqrt(k_B T / m) is extreme at the extreme nu0/sqrt(m)
+ * and T, gamma_L = gamma296 (p/1 atm)(296/T)^0.5 at the extreme gamma296, p and T.
+ * workspace as bm_opacity_table_build's. Asynchronous on `stream`. */
+int bm_line_width_range(const double* nu0, const double* gamma296, const double* mass_amu,
+                        int64_t n_lines, const double* temp, int n_temp, const double* p_bar,
+                        int n_p, double* range_out, void* workspace, size_t workspace_bytes,
+                        void* stream);
 
 /* Voigt profile V(x; sigma, gamma) = Re w(z) / (sigma sqrt(2 pi)), z = (x + i gamma) /
  * (sigma sqrt 2) (Eqs. 4-11), evaluated with the library's Faddeeva routine in double.

@@ -57,6 +57,16 @@ def _ptr(t: torch.Tensor | None) -> C.c_void_p:
     return C.c_void_p(t.data_ptr())
 
 
+def _keep_for_stream(tensors, stream=None) -> None:
+    """Temporaries a call reads on a stream other than the current one: the caching
+    allocator must not hand their memory out again until that stream's work is done."""
+    if stream is None or stream == torch.cuda.current_stream():
+        return
+    for t in tensors:
+        if t is not None and t.is_cuda:
+            t.record_stream(stream)
+
+
 def _dtype_code(dt: torch.dtype) -> int:
     if dt == torch.float32:
         return BM_F32
@@ -384,11 +394,21 @@ class KernelTiming:
 
 
 # ------------------------------------------------------------------------------- opacity
+def opacity_build_workspace(n_lines: int, device="cuda") -> torch.Tensor:
+    """A device workspace for bm_opacity_table_build / bm_line_width_range."""
+    nb = int(lib().bm_opacity_build_workspace(int(n_lines)))
+    if nb == 0:
+        raise BartmiError("invalid line count")
+    return torch.empty(nb, dtype=torch.uint8, device=device)
+
+
 def opacity_table_build(lines, temps, p_bar, nu_start: float, dnu: float, n_nu: int,
                         cutoff_hwhm: float = 25.0, dtype=torch.float32, device="cuda",
-                        out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+                        out: torch.Tensor | None = None, stream=None,
+                        workspace: torch.Tensor | None = None) -> torch.Tensor:
     """Cross-section table [NT][NP][Nnu] of one species. ``lines`` has attributes nu0,
-    s296, gamma296, elow, mass_amu (numpy or torch, sorted by nu0)."""
+    s296, gamma296, elow, mass_amu (numpy or torch, sorted by nu0). Builds that may run
+    concurrently (other streams) need workspaces of their own."""
     arrs = [_dev(getattr(lines, f), device=device) for f in
             ("nu0", "s296", "gamma296", "elow", "mass_amu")]
     n = int(arrs[0].numel())
@@ -396,13 +416,33 @@ def opacity_table_build(lines, temps, p_bar, nu_start: float, dnu: float, n_nu: 
     p_bar = np.ascontiguousarray(np.asarray(p_bar, dtype=np.float64))
     if out is None:
         out = torch.empty(len(temps), len(p_bar), n_nu, dtype=dtype, device=device)
+    if workspace is None:
+        workspace = opacity_build_workspace(n, device=device)
     dp = C.POINTER(C.c_double)
     _check(lib().bm_opacity_table_build(*[_ptr(a) for a in arrs], n, temps.ctypes.data_as(dp),
                                         len(temps), p_bar.ctypes.data_as(dp), len(p_bar),
                                         C.c_double(nu_start), C.c_double(dnu), n_nu,
                                         C.c_double(cutoff_hwhm), _dtype_code(out.dtype),
-                                        _ptr(out), _stream(stream)), "bm_opacity_table_build")
+                                        _ptr(out), _ptr(workspace), workspace.numel(),
+                                        _stream(stream)), "bm_opacity_table_build")
+    _keep_for_stream(arrs + [workspace], stream)
     return out
+
+
+def line_width_range(lines, temps, p_bar, device="cuda", stream=None) -> np.ndarray:
+    """(min sigma_D, max sigma_D, min gamma_L, max gamma_L) of the lines over the cells of
+    these temperatures and pressures (bm_line_width_range); waits for the result."""
+    arrs = [_dev(getattr(lines, f), device=device) for f in ("nu0", "gamma296", "mass_amu")]
+    n = int(arrs[0].numel())
+    temps = np.ascontiguousarray(np.asarray(temps, dtype=np.float64))
+    p_bar = np.ascontiguousarray(np.asarray(p_bar, dtype=np.float64))
+    ws = opacity_build_workspace(n, device=device)
+    out = torch.empty(4, dtype=torch.float64, device=device)
+    dp = C.POINTER(C.c_double)
+    _check(lib().bm_line_width_range(*[_ptr(a) for a in arrs], n, temps.ctypes.data_as(dp), len(temps),
+                                     p_bar.ctypes.data_as(dp), len(p_bar), _ptr(out), _ptr(ws), ws.numel(),
+                                     _stream(stream)), "bm_line_width_range")
+    return out.cpu().numpy()
 
 
 class VoigtTable:
@@ -429,20 +469,12 @@ class VoigtTable:
                "bm_voigt_table_build")
 
     @staticmethod
-    def nodes_for(lines, temps, p_bar, n_sigma: int = 60, n_gamma: int = 60, margin: float = 1.01):
+    def nodes_for(lines, temps, p_bar, n_sigma: int = 60, n_gamma: int = 60, margin: float = 1.01,
+                  device="cuda"):
         """Log-spaced nodes over the Doppler and Lorentz widths the lines take in these
-        cells (the range of expected widths), widened by `margin` at both ends."""
-        k_b, amu, c_light, atm, t_ref = 1.380649e-16, 1.66053906660e-24, 2.99792458e10, 1.01325, 296.0
-        nu0 = np.asarray(lines.nu0, dtype=np.float64)
-        mass = np.asarray(lines.mass_amu, dtype=np.float64)
-        g296 = np.asarray(lines.gamma296, dtype=np.float64)
-        temps = np.asarray(temps, dtype=np.float64)
-        p_bar = np.asarray(p_bar, dtype=np.float64)
-        s0 = nu0 / c_light / np.sqrt(mass * amu)
-        s_lo = s0.min() * np.sqrt(k_b * temps.min())
-        s_hi = s0.max() * np.sqrt(k_b * temps.max())
-        g_lo = g296.min() * (p_bar.min() / atm) * np.sqrt(t_ref / temps.max())
-        g_hi = g296.max() * (p_bar.max() / atm) * np.sqrt(t_ref / temps.min())
+        cells (the range of expected widths, from bm_line_width_range), widened by `margin`
+        at both ends."""
+        s_lo, s_hi, g_lo, g_hi = line_width_range(lines, temps, p_bar, device=device)
         return (np.geomspace(s_lo / margin, s_hi * margin, n_sigma),
                 np.geomspace(g_lo / margin, g_hi * margin, n_gamma))
 
@@ -470,6 +502,7 @@ def opacity_table_build_profiles(lines, temps, p_bar, nu_start: float, n_nu: int
         len(p_bar), C.c_double(nu_start), n_nu, C.byref(table.grid), _ptr(table.table),
         C.c_double(strength_cutoff), _dtype_code(out.dtype), _ptr(out), _ptr(ws), wsb, _stream(stream)),
         "bm_opacity_table_build_profiles")
+    _keep_for_stream(arrs + [ws], stream)
     return out
 
 

@@ -104,8 +104,12 @@ PROTOTYPES = {
     "bm_demcz_accept": (_I, [C.POINTER(BmDemcz), _VP, _VP, _VP]),
     "bm_da_screen": (_I, [C.POINTER(BmDemcz), _VP, _VP, _VP]),
     "bm_da_accept": (_I, [C.POINTER(BmDemcz), _VP, _VP, _VP, _VP, _VP]),
+    "bm_opacity_build_workspace": (C.c_size_t, [_I64]),
     "bm_opacity_table_build": (_I, [_VP, _VP, _VP, _VP, _VP, _I64, C.POINTER(C.c_double), _I,
-                                    C.POINTER(C.c_double), _I, _D, _D, _I, _D, _I, _VP, _VP]),
+                                    C.POINTER(C.c_double), _I, _D, _D, _I, _D, _I, _VP, _VP,
+                                    C.c_size_t, _VP]),
+    "bm_line_width_range": (_I, [_VP, _VP, _VP, _I64, C.POINTER(C.c_double), _I, C.POINTER(C.c_double), _I,
+                                 _VP, _VP, C.c_size_t, _VP]),
     "bm_voigt": (_I, [_VP, _I64, _D, _D, _VP, _VP]),
     "bm_gemm_bf16": (_I, [_I, _I, _I, _VP, _I, _I, _VP, _I, _I, _I, _VP, _VP, _I, _VP, _I, _VP, _I,
                           C.c_float, _VP]),

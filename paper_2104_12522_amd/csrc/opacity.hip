@@ -37,52 +37,84 @@ struct CellGrid {
     int n_p;
 };
 
-// widest window inputs over all lines, max gamma296 and max nu0 / sqrt(mass), in two
-// stages: up to kExtBlocks workgroups each reduce a grid-strided share of the lines into
-// out[2 + 2 b], out[3 + 2 b]; one workgroup then reduces those into out[0], out[1] (maxima
-// are exact in any order)
+// Line-list extremes in the caller's workspace, in two stages: up to kExtBlocks workgroups
+// each reduce a grid-strided share of the lines into the partials ws[kExtFinal + 4 b ..],
+// one workgroup then reduces those into ws[0..4): max gamma296, max nu0 / sqrt(mass) (the
+// widest-window inputs), min gamma296, min nu0 / sqrt(mass). Maxima and minima are exact in
+// any order. With no lines the final stage writes max 0 and min +inf.
 constexpr int kExtBlocks = 256;
-__device__ __forceinline__ void block_max2(double& g, double& d, double* s0, double* s1) {
-    s0[threadIdx.x] = g;
-    s1[threadIdx.x] = d;
+constexpr int kExtFinal = 4;
+constexpr size_t kExtWorkspaceBytes = sizeof(double) * (kExtFinal + 4 * kExtBlocks);
+struct Ext4 {
+    double gmax, dmax, gmin, dmin;
+};
+__device__ __forceinline__ Ext4 block_ext4(Ext4 v, Ext4* s) {
+    s[threadIdx.x] = v;
     __syncthreads();
     for (int off = blockDim.x / 2; off > 0; off >>= 1) {
         if ((int)threadIdx.x < off) {
-            s0[threadIdx.x] = fmax(s0[threadIdx.x], s0[threadIdx.x + off]);
-            s1[threadIdx.x] = fmax(s1[threadIdx.x], s1[threadIdx.x + off]);
+            Ext4& a = s[threadIdx.x];
+            const Ext4 b = s[threadIdx.x + off];
+            a.gmax = fmax(a.gmax, b.gmax);
+            a.dmax = fmax(a.dmax, b.dmax);
+            a.gmin = fmin(a.gmin, b.gmin);
+            a.dmin = fmin(a.dmin, b.dmin);
         }
         __syncthreads();
     }
-    g = s0[0];
-    d = s1[0];
+    return s[0];
 }
 
-__global__ void __launch_bounds__(256) k_line_extremes(LineArrays ln, double* out) {
-    __shared__ double s0[256], s1[256];
-    double g = 0.0, d = 0.0;
+__global__ void __launch_bounds__(256) k_line_extremes(LineArrays ln, double* ws) {
+    __shared__ Ext4 s[256];
+    Ext4 v{0.0, 0.0, __builtin_huge_val(), __builtin_huge_val()};
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ln.n; i += (int64_t)gridDim.x * blockDim.x) {
-        g = fmax(g, ln.gamma296[i]);
-        d = fmax(d, ln.nu0[i] / sqrt(ln.mass[i]));
+        const double g = ln.gamma296[i];
+        const double d = ln.nu0[i] / sqrt(ln.mass[i]);
+        v.gmax = fmax(v.gmax, g);
+        v.dmax = fmax(v.dmax, d);
+        v.gmin = fmin(v.gmin, g);
+        v.dmin = fmin(v.dmin, d);
     }
-    block_max2(g, d, s0, s1);
+    v = block_ext4(v, s);
     if (threadIdx.x == 0) {
-        out[2 + 2 * blockIdx.x] = g;
-        out[3 + 2 * blockIdx.x] = d;
+        double* o = ws + kExtFinal + 4 * blockIdx.x;
+        o[0] = v.gmax;
+        o[1] = v.dmax;
+        o[2] = v.gmin;
+        o[3] = v.dmin;
     }
 }
 
-__global__ void __launch_bounds__(256) k_line_extremes_final(double* out, int n_blocks) {
-    __shared__ double s0[256], s1[256];
-    double g = 0.0, d = 0.0;
+__global__ void __launch_bounds__(256) k_line_extremes_final(double* ws, int n_blocks) {
+    __shared__ Ext4 s[256];
+    Ext4 v{0.0, 0.0, __builtin_huge_val(), __builtin_huge_val()};
     for (int b = threadIdx.x; b < n_blocks; b += blockDim.x) {
-        g = fmax(g, out[2 + 2 * b]);
-        d = fmax(d, out[3 + 2 * b]);
+        const double* o = ws + kExtFinal + 4 * b;
+        v.gmax = fmax(v.gmax, o[0]);
+        v.dmax = fmax(v.dmax, o[1]);
+        v.gmin = fmin(v.gmin, o[2]);
+        v.dmin = fmin(v.dmin, o[3]);
     }
-    block_max2(g, d, s0, s1);
+    v = block_ext4(v, s);
     if (threadIdx.x == 0) {
-        out[0] = g;
-        out[1] = d;
+        ws[0] = v.gmax;
+        ws[1] = v.dmax;
+        ws[2] = v.gmin;
+        ws[3] = v.dmin;
     }
+}
+
+// Range of the Doppler sigma and Lorentz gamma that the lines take over the cells with
+// temperatures in [t_lo, t_hi] and pressures in [p_lo, p_hi] (bar), from the extremes:
+// out = {sigma_min, sigma_max, gamma_min, gamma_max}
+__global__ void k_width_range(const double* __restrict__ ext, double t_lo, double t_hi, double p_lo,
+                              double p_hi, double* __restrict__ out) {
+    if (threadIdx.x != 0) return;
+    out[0] = ext[3] / kLight * sqrt(kBoltz * t_lo / kAmu);
+    out[1] = ext[1] / kLight * sqrt(kBoltz * t_hi / kAmu);
+    out[2] = ext[2] * (p_lo / kAtmBar) * sqrt(kTRef / t_hi);
+    out[3] = ext[0] * (p_hi / kAtmBar) * sqrt(kTRef / t_lo);
 }
 
 // the cell's widest window plus one grid step: every line's window is at most wmax - dnu
@@ -291,32 +323,58 @@ extern "C" int bm_voigt(const double* x, int64_t n, double sigma, double gamma, 
     return BM_OK;
 }
 
-// The widest-window inputs (two doubles, then the per-workgroup partials) live in a
-// buffer per device, allocated on the first call on that device and held until the
-// process ends.
-static double* extremes_buffer() {
-    static double* per_device[64] = {nullptr};
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
-    if (!per_device[dev]) {
-        void* p = nullptr;
-        if (hipMalloc(&p, sizeof(double) * (2 + 2 * kExtBlocks)) != hipSuccess) return nullptr;
-        per_device[dev] = (double*)p;
+static void launch_line_extremes(const LineArrays& ln, double* ws, hipStream_t st) {
+    const int nb = (int)std::min<int64_t>(kExtBlocks, (ln.n + 255) / 256);
+    if (nb > 0) hipLaunchKernelGGL(k_line_extremes, dim3(nb), dim3(256), 0, st, ln, ws);
+    hipLaunchKernelGGL(k_line_extremes_final, dim3(1), dim3(256), 0, st, ws, nb);
+}
+
+extern "C" size_t bm_opacity_build_workspace(int64_t n_lines) {
+    if (n_lines < 0) return 0;
+    return kExtWorkspaceBytes;
+}
+
+extern "C" int bm_line_width_range(const double* nu0, const double* gamma296, const double* mass_amu,
+                                   int64_t n_lines, const double* temp, int n_temp, const double* p_bar,
+                                   int n_p, double* range_out, void* workspace, size_t workspace_bytes,
+                                   void* stream) {
+    if (!nu0 || !gamma296 || !mass_amu || !temp || !p_bar || !range_out || !workspace) return BM_EINVAL;
+    if (n_lines < 1 || n_temp < 1 || n_p < 1) return BM_ESHAPE;
+    if (workspace_bytes < kExtWorkspaceBytes) return BM_ENOSPACE;
+    double t_lo = temp[0], t_hi = temp[0], p_lo = p_bar[0], p_hi = p_bar[0];
+    for (int i = 0; i < n_temp; ++i) {
+        if (!(temp[i] > 0.0)) return BM_EINVAL;
+        t_lo = std::min(t_lo, temp[i]);
+        t_hi = std::max(t_hi, temp[i]);
     }
-    return per_device[dev];
+    for (int i = 0; i < n_p; ++i) {
+        if (!(p_bar[i] > 0.0)) return BM_EINVAL;
+        p_lo = std::min(p_lo, p_bar[i]);
+        p_hi = std::max(p_hi, p_bar[i]);
+    }
+    hipStream_t st = (hipStream_t)stream;
+    double* ws = (double*)workspace;
+    LineArrays ln{nu0, nullptr, gamma296, nullptr, mass_amu, n_lines};
+    launch_line_extremes(ln, ws, st);
+    BM_CHECK_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_width_range, dim3(1), dim3(64), 0, st, ws, t_lo, t_hi, p_lo, p_hi, range_out);
+    BM_CHECK_HIP(hipGetLastError());
+    return BM_OK;
 }
 
 extern "C" int bm_opacity_table_build(const double* nu0, const double* s296, const double* gamma296,
                                       const double* elow, const double* mass_amu, int64_t n_lines,
                                       const double* temp, int n_temp, const double* p_bar, int n_p,
                                       double nu_start, double dnu, int n_nu, double cutoff_hwhm, int dtype,
-                                      void* sigma_out, void* stream) {
-    if (!temp || !p_bar || !sigma_out) return BM_EINVAL;
+                                      void* sigma_out, void* workspace, size_t workspace_bytes,
+                                      void* stream) {
+    if (!temp || !p_bar || !sigma_out || !workspace) return BM_EINVAL;
     if (n_lines > 0 && (!nu0 || !s296 || !gamma296 || !elow || !mass_amu)) return BM_EINVAL;
     if (n_lines < 0 || n_temp < 1 || n_temp > BM_MAX_TEMPS || n_p < 1 || n_p > BM_MAX_LAYERS || n_nu < 1)
         return BM_ESHAPE;
     if (!(dnu > 0.0) || !(cutoff_hwhm > 0.0)) return BM_EINVAL;
     if (dtype != BM_F32 && dtype != BM_F64) return BM_EINVAL;
+    if (workspace_bytes < kExtWorkspaceBytes) return BM_ENOSPACE;
     CellGrid cg{};
     for (int i = 0; i < n_temp; ++i) {
         if (!(temp[i] > 0.0)) return BM_EINVAL;
@@ -328,15 +386,11 @@ extern "C" int bm_opacity_table_build(const double* nu0, const double* s296, con
     }
     cg.n_p = n_p;
     hipStream_t st = (hipStream_t)stream;
-    double* d_ext = extremes_buffer();
-    if (!d_ext) return BM_EHIP;
+    // the widest-window inputs, written on every call (with no lines: zeros, and every
+    // cell's line range is empty)
+    double* d_ext = (double*)workspace;
     LineArrays ln{nu0, s296, gamma296, elow, mass_amu, n_lines};
-    if (n_lines > 0) {
-        const int nb = (int)std::min<int64_t>(kExtBlocks, (n_lines + 255) / 256);
-        hipLaunchKernelGGL(k_line_extremes, dim3(nb), dim3(256), 0, st, ln, d_ext);
-        BM_CHECK_HIP(hipGetLastError());
-        hipLaunchKernelGGL(k_line_extremes_final, dim3(1), dim3(256), 0, st, d_ext, nb);
-    }
+    launch_line_extremes(ln, d_ext, st);
     BM_CHECK_HIP(hipGetLastError());
     dim3 grid((n_nu + kOpThreads - 1) / kOpThreads, n_temp * n_p);
     // every cell is built by exactly one of the two kernels (the other's workgroups exit)

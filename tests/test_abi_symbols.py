@@ -120,3 +120,30 @@ def test_sigma_tiles_size_and_argument_errors(lib):
     assert lib.bm_sigma_tiles_bytes(C.byref(m), 60) == 2 * need
     m.n_layers = 1
     assert lib.bm_sigma_tiles_bytes(C.byref(m), 60) == 0                             # bad model
+
+
+def test_opacity_build_workspace_and_argument_errors(lib):
+    # the opacity build allocates nothing: it takes a caller workspace of the size the
+    # library reports, and rejects a smaller one before any launch
+    from paper_2104_12522_amd import _abi
+    f = lib.bm_opacity_table_build
+    f.restype, f.argtypes = _abi.PROTOTYPES["bm_opacity_table_build"]
+    lib.bm_opacity_build_workspace.restype = C.c_size_t
+    lib.bm_opacity_build_workspace.argtypes = [C.c_int64]
+    need = lib.bm_opacity_build_workspace(1000)
+    assert need >= 4 * 8 and need % 8 == 0
+    assert lib.bm_opacity_build_workspace(0) == need
+    assert lib.bm_opacity_build_workspace(-1) == 0
+    dummy = C.c_void_p(16)
+    temps = (C.c_double * 2)(500.0, 1000.0)
+    p_bar = (C.c_double * 1)(1.0)
+    args = [dummy] * 5 + [10, temps, 2, p_bar, 1, 1000.0, 0.1, 100, 25.0, 0, dummy]
+    assert f(*args, dummy, need - 1, None) == -4          # BM_ENOSPACE
+    assert f(*args, None, need, None) == -1               # no workspace
+    bad = list(args)
+    bad[6] = (C.c_double * 2)(500.0, -1.0)                # non-positive temperature
+    assert f(*bad, dummy, need, None) == -1
+    g = lib.bm_line_width_range
+    g.restype, g.argtypes = _abi.PROTOTYPES["bm_line_width_range"]
+    assert g(dummy, dummy, dummy, 0, temps, 2, p_bar, 1, dummy, dummy, need, None) == -2   # no lines
+    assert g(dummy, dummy, dummy, 5, temps, 2, p_bar, 1, dummy, dummy, need - 8, None) == -4

@@ -102,6 +102,47 @@ def test_opacity_build_dense_narrow_lines():
     _compare_table(lines, temps, p_bar, 2000.0, dnu, 3100, torch.float64, rtol=1e-9)
     _compare_table(lines, temps[1:], p_bar[:2], 2000.0, dnu, 3100, torch.float32, rtol=2e-6)
 
+def test_opacity_builds_on_two_streams_match_sequential_builds():
+    """Two builds issued on two streams at once, each with its own workspace, give the
+    same tables, bit for bit, as the same builds run one after the other; the two line
+    lists have very different widest windows (narrow Doppler lines against strongly
+    pressure-broadened ones), so builds that shared their line-list extremes would cut
+    the windows of one of them short."""
+    narrow = wl.line_list(3000, seed=21, nu_min=2000.0, nu_max=2040.0)
+    wide = wl.line_list(2000, seed=22, nu_min=2000.0, nu_max=2040.0)
+    wide.gamma296 = wide.gamma296 * 40.0
+    args_n = ([300.0, 900.0], [1e-6, 1e-3], 1995.0, 0.01, 5000)
+    args_w = ([1500.0, 3000.0], [10.0, 100.0], 1995.0, 0.01, 5000)
+    seq_n = bm.opacity_table_build(narrow, *args_n, dtype=torch.float64)
+    seq_w = bm.opacity_table_build(wide, *args_w, dtype=torch.float64)
+    torch.cuda.synchronize()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    out_n = torch.empty_like(seq_n)
+    out_w = torch.empty_like(seq_w)
+    ws_n, ws_w = bm.opacity_build_workspace(len(narrow)), bm.opacity_build_workspace(len(wide))
+    for _ in range(3):
+        out_n.fill_(-1.0)
+        out_w.fill_(-1.0)
+        torch.cuda.synchronize()
+        bm.opacity_table_build(narrow, *args_n, dtype=torch.float64, out=out_n, stream=s1, workspace=ws_n)
+        bm.opacity_table_build(wide, *args_w, dtype=torch.float64, out=out_w, stream=s2, workspace=ws_w)
+        torch.cuda.synchronize()
+        assert torch.equal(out_n, seq_n) and torch.equal(out_w, seq_w)
+    # and both against the oracle on one cell each
+    for lines, (temps, p_bar, nu_start, dnu, n_nu), got in ((narrow, args_n, seq_n), (wide, args_w, seq_w)):
+        ref = oop.cell_cross_section(lines, temps[1], p_bar[1], nu_start, dnu, n_nu)
+        np.testing.assert_allclose(got[1, 1].cpu().numpy(), ref, rtol=1e-9, atol=1e-13 * ref.max())
+
+
+def test_line_width_range_matches_oracle_widths():
+    lines = wl.line_list(5000, seed=23, nu_min=1000.0, nu_max=5000.0, mass_amu=None)
+    temps, p_bar = np.array([300.0, 1442.58, 3000.0]), np.array([1e-8, 0.33516, 100.0])
+    got = bm.line_width_range(lines, temps, p_bar)
+    sig = np.concatenate([oop.doppler_sigma(lines.nu0, lines.mass_amu, t) for t in temps])
+    gam = np.concatenate([oop.lorentz_gamma(lines.gamma296, t, p) for t in temps for p in p_bar])
+    np.testing.assert_allclose(got, [sig.min(), sig.max(), gam.min(), gam.max()], rtol=1e-14)
+
+
 # ---- profile-table mode (Sec. 4 items 4-6) ---------------------------------------------
 def _node_grid(lines, temps, p_bar, n_sigma, n_gamma):
     """Nodes log-spaced over the widths the lines take in these cells (the paper's
@@ -110,6 +151,27 @@ def _node_grid(lines, temps, p_bar, n_sigma, n_gamma):
     gam = np.concatenate([oop.table_line_parameters(lines, float(t), float(p))[2] for t in temps for p in p_bar])
     return (np.geomspace(sig.min() * 0.97, sig.max() * 1.03, n_sigma),
             np.geomspace(gam.min() * 0.97, gam.max() * 1.03, n_gamma))
+
+
+def _assert_off_ties(lines, temps, p_bar, nu_start, sn, gn, dnu, O, cutoff=25.0, margin=1e-9):
+    """The table mode's integer decisions (profile extent, nearest node, fine shift) are
+    taken away from their boundaries by more than `margin` (relative), so that rounding
+    differences between two correct implementations cannot flip one."""
+    delta = dnu / O
+    for s in sn:
+        x = cutoff * oop.voigt_hwhm(s, gn) / delta
+        assert np.all(np.abs(x - np.rint(x)) > margin * x)
+    u = (lines.nu0 - nu_start) / delta
+    assert np.all(np.abs(np.abs(u - np.floor(u)) - 0.5) > margin * np.abs(u))
+    mids_s, mids_g = np.sqrt(sn[:-1] * sn[1:]), np.sqrt(gn[:-1] * gn[1:])
+    for t in temps:
+        sig = oop.doppler_sigma(lines.nu0, lines.mass_amu, float(t))
+        if mids_s.size:
+            assert np.min(np.abs(sig[:, None] / mids_s[None, :] - 1.0)) > margin
+        for p in p_bar:
+            gam = oop.lorentz_gamma(lines.gamma296, float(t), float(p))
+            if mids_g.size:
+                assert np.min(np.abs(gam[:, None] / mids_g[None, :] - 1.0)) > margin
 
 
 def _table_case(seed, n_lines, dups=0):
@@ -127,6 +189,7 @@ def test_profile_table_mode_matches_oracle(dtype, cut):
     temps, p_bar = np.array([700.0, 1442.58, 2600.0]), np.array([0.33516, 4.0])
     nu_start, dnu, n_nu = 1999.0, 0.01, 1300
     sn, gn = _node_grid(lines, temps, p_bar, 7, 6)
+    _assert_off_ties(lines, temps, p_bar, nu_start, sn, gn, dnu, 64)
     tab = bm.VoigtTable(sn, gn, dnu, 64, 25.0)
     ref_tab = oop.profile_table(sn, gn, dnu, 64, 25.0)
     out = bm.opacity_table_build_profiles(lines, temps, p_bar, nu_start, n_nu, tab, strength_cutoff=cut,
@@ -143,8 +206,9 @@ def test_profile_table_mode_matches_oracle(dtype, cut):
 
 
 def test_profile_table_values_match_oracle():
-    # the stored profiles themselves (single precision), read back in their residue-major
-    # layout: row rho = u mod O holds u = rho, rho + O, ... with t = u - T
+    # the stored profiles themselves (single precision in the library, against the
+    # oracle's double values), read back in their residue-major layout: row
+    # rho = u mod O holds u = rho, rho + O, ... with t = u - T
     sn, gn = np.array([2e-3, 5e-3]), np.array([1e-3, 3e-2, 0.4])
     O, dnu = 16, 0.01
     tab = bm.VoigtTable(sn, gn, dnu, O, 25.0)
