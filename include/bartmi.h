@@ -48,6 +48,7 @@ extern "C" {
 #define BM_ESHAPE -2       /* sizes inconsistent or outside the supported range */
 #define BM_EHIP -3         /* the HIP runtime reported an error when enqueuing */
 #define BM_ENOSPACE -4     /* the caller's workspace is smaller than required */
+#define BM_ESCRATCH -5     /* a no-allocation call needs more than the library's fixed array */
 
 /* ---- element types --------------------------------------------------------------- */
 #define BM_F32 0
@@ -256,6 +257,24 @@ int bm_forward_batch(const bm_model* models, int n_models, const int32_t* instan
                      const double* params, int param_stride, int B, const int32_t* active,
                      double* depth, double* binned, double* chi2, int32_t* flags,
                      void* workspace, size_t workspace_bytes, void* stream);
+
+/* ---- a1-a6 fused, no allocation -------------------------------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): bm_forward_batch with its workspace in
+ * a library-owned device array of BM_NOALLOC_SCRATCH_BYTES (64 MiB), one per GPU, present
+ * from the library's load on that GPU until the process ends. Arguments, outputs, launch
+ * configuration and results are those of bm_forward_batch (bit-identical), without the
+ * workspace arguments. The call allocates nothing and enqueues only kernels; the array
+ * needs no clearing between calls (every call writes what it reads). Returns BM_ESCRATCH,
+ * before any device work, when bm_workspace_size(models, n_models, instance, B) exceeds
+ * the array (about 1600 samples of 100 layers x 30000 wavenumbers). Every call on one GPU
+ * shares that GPU's array: calls that overlap on one GPU (other streams, other threads)
+ * race, so order them on one stream. */
+#define BM_NOALLOC_SCRATCH_BYTES (64u << 20)
+int bm_forward_batch_noalloc(const bm_model* models, int n_models, const int32_t* instance,
+                             const double* params, int param_stride, int B, const int32_t* active,
+                             double* depth, double* binned, double* chi2, int32_t* flags,
+                             void* stream);
 
 /* ---- launch configurations and the autotuner --------------------------------------------
  * The fused kernel of bm_forward_batch has several launch configurations (waves per

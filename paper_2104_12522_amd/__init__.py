@@ -325,6 +325,20 @@ class Forward:
                "bm_forward_batch")
         return self
 
+    def call_noalloc(self, params: torch.Tensor, stream=None, active: torch.Tensor | None = None):
+        """The same call through bm_forward_batch_noalloc: the library's fixed per-GPU array
+        replaces this object's workspace (calls overlapping on one GPU race)."""
+        if params.shape[0] != self.B or params.dtype != torch.float64 or not params.is_contiguous():
+            raise BartmiError("params must be a contiguous float64 [B][P] device tensor")
+        if active is not None and (active.dtype != torch.int32 or active.numel() != self.B):
+            raise BartmiError("active must be an int32 [B] device tensor")
+        _check(lib().bm_forward_batch_noalloc(self._structs, len(self.models), self._inst, _ptr(params),
+                                              params.shape[1], self.B, _ptr(active), _ptr(self.depth),
+                                              _ptr(self.binned), _ptr(self.chi2), _ptr(self.flags),
+                                              _stream(stream)),
+               "bm_forward_batch_noalloc")
+        return self
+
     def tune(self, params: torch.Tensor, reps: int = 5, stream=None):
         """Autotune the fused kernel's launch configuration for this batch (bm_forward_tune);
         returns (chosen index, mean ms per call of every configuration). Overwrites the

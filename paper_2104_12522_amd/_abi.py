@@ -4,7 +4,8 @@ from __future__ import annotations
 import ctypes as C
 import os
 
-BM_OK, BM_EINVAL, BM_ESHAPE, BM_EHIP, BM_ENOSPACE = 0, -1, -2, -3, -4
+BM_OK, BM_EINVAL, BM_ESHAPE, BM_EHIP, BM_ENOSPACE, BM_ESCRATCH = 0, -1, -2, -3, -4, -5
+BM_NOALLOC_SCRATCH_BYTES = 64 << 20
 BM_F32, BM_F64 = 0, 1
 BM_FLAG_T_CLAMP, BM_FLAG_SUM_X, BM_FLAG_RADIUS, BM_FLAG_NONFINITE = 1, 2, 4, 8
 BM_TP_ISOTHERMAL, BM_TP_LINE2013 = 0, 1
@@ -91,6 +92,8 @@ PROTOTYPES = {
     "bm_sigma_tiles": (_I, [_PM, _I, C.c_void_p, C.c_size_t, C.c_void_p]),
     "bm_forward_batch": (_I, [_PM, _I, C.POINTER(C.c_int32), _VP, _I, _I, _VP, _VP, _VP, _VP, _VP,
                               _VP, C.c_size_t, _VP]),
+    "bm_forward_batch_noalloc": (_I, [_PM, _I, C.POINTER(C.c_int32), _VP, _I, _I, _VP, _VP, _VP, _VP, _VP,
+                                      _VP]),
     "bm_forward_config_count": (_I, []),
     "bm_forward_config_name": (C.c_char_p, [_I]),
     "bm_forward_tune": (_I, [_PM, _I, C.POINTER(C.c_int32), _VP, _I, _I, _VP, _VP, _VP, _VP, _VP,

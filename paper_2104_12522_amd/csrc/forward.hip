@@ -657,6 +657,7 @@ extern "C" const char* bm_status_string(int status) {
         case BM_ESHAPE: return "unsupported or inconsistent shape";
         case BM_EHIP: return "HIP runtime error";
         case BM_ENOSPACE: return "workspace too small";
+        case BM_ESCRATCH: return "request needs more than the no-allocation scratch array (BM_NOALLOC_SCRATCH_BYTES)";
         default: return "unknown status";
     }
 }
@@ -809,6 +810,56 @@ extern "C" int bm_forward_batch(const bm_model* models, int n_models, const int3
     if (B == 0) return BM_OK;
     const int cfg = tuned_config(models, hp);
     return run_forward(models, hp, cfg, params, param_stride, active, depth, binned, chi2, flags, workspace,
+                       (hipStream_t)stream);
+}
+
+// ---- no-allocation form ----------------------------------------------------------------
+// The per-sample records and the list of requested samples live in a fixed device array
+// instead of a caller workspace. Host code never passes the array's name to a kernel (on
+// the host it is a stand-in, not a device address): its address on each device is looked
+// up once, with that device current, and kept.
+static __device__ __align__(256) char scratch[BM_NOALLOC_SCRATCH_BYTES];
+
+static int scratch_address(void** out) {
+    constexpr int kMaxDevices = 64;
+    static void* per_device[kMaxDevices] = {nullptr};
+    static std::mutex mu;
+    int dev = 0;
+    BM_CHECK_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return BM_EHIP;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!per_device[dev]) {
+        void* p = nullptr;
+        BM_CHECK_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return BM_EHIP;
+        per_device[dev] = p;
+    }
+    *out = per_device[dev];
+    return BM_OK;
+}
+
+extern "C" int bm_forward_batch_noalloc(const bm_model* models, int n_models, const int32_t* instance,
+                                        const double* params, int param_stride, int B, const int32_t* active,
+                                        double* depth, double* binned, double* chi2, int32_t* flags,
+                                        void* stream) {
+    // the size check runs before any device call: a request beyond the array fails at once
+    {
+        HostPlan probe;
+        const int st = build_plans(models, n_models, instance, B, probe);
+        if (st != BM_OK) return st;
+        if (probe.ws_bytes > (size_t)BM_NOALLOC_SCRATCH_BYTES) return BM_ESCRATCH;
+    }
+    HostPlan hp;
+    int st;
+    void* ws = nullptr;
+    st = scratch_address(&ws);
+    if (st != BM_OK) return st;
+    st = check_forward_args(models, n_models, instance, params, param_stride, B, depth, binned, chi2, flags, ws,
+                            (size_t)BM_NOALLOC_SCRATCH_BYTES, hp);
+    if (st != BM_OK) return st;
+    if (B == 0) return BM_OK;
+    const int cfg = tuned_config(models, hp);
+    return run_forward(models, hp, cfg, params, param_stride, active, depth, binned, chi2, flags, ws,
                        (hipStream_t)stream);
 }
 

@@ -147,3 +147,22 @@ def test_opacity_build_workspace_and_argument_errors(lib):
     g.restype, g.argtypes = _abi.PROTOTYPES["bm_line_width_range"]
     assert g(dummy, dummy, dummy, 0, temps, 2, p_bar, 1, dummy, dummy, need, None) == -2   # no lines
     assert g(dummy, dummy, dummy, 5, temps, 2, p_bar, 1, dummy, dummy, need - 8, None) == -4
+
+
+def test_noalloc_size_limit_is_checked_on_the_host(lib):
+    # a request larger than the library's fixed array is refused before any device call
+    from paper_2104_12522_amd import _abi
+    f = lib.bm_forward_batch_noalloc
+    f.restype, f.argtypes = _abi.PROTOTYPES["bm_forward_batch_noalloc"]
+    lib.bm_workspace_size.restype = C.c_size_t
+    lib.bm_workspace_size.argtypes = [C.POINTER(_abi.BmModel), C.c_int, C.c_void_p, C.c_int]
+    m = _abi.BmModel()
+    m.dtype, m.n_species, m.n_temp, m.n_layers, m.n_nu = _abi.BM_F32, 4, 20, 100, 30000
+    m.tp_mode = 1
+    m.sigma = m.temp = m.p_bar = 16          # never dereferenced by this call
+    B = 4000
+    assert lib.bm_workspace_size(C.byref(m), 1, None, B) > _abi.BM_NOALLOC_SCRATCH_BYTES
+    dummy = C.c_void_p(16)
+    assert f(C.byref(m), 1, None, dummy, 10, B, None, dummy, None, None, dummy, None) == _abi.BM_ESCRATCH
+    lib.bm_status_string.restype = C.c_char_p
+    assert b"scratch" in lib.bm_status_string(_abi.BM_ESCRATCH)
