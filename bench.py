@@ -210,6 +210,51 @@ def section_forward(args, setup, model, prior):
     return out
 
 
+def section_fp64(args):
+    """The FP64 single-spectrum workload: one absorber with 1e4 lines, its table built by
+    the library in double (10 T x 50 p x 1000 nu at 4 cm^-1), an isothermal 1200 K
+    atmosphere with x = 1e-4; one spectrum per call, back to back on one stream. Latency
+    per spectrum from HIP events, and the fused kernel's own time."""
+    import torch
+    import workloads as wl
+    import paper_2104_12522_amd as bm
+    s = wl.config1()
+    lines = device_lines(wl.line_list(s.lines_per_species[0], seed=wl.SEED_BASE + 1,
+                                      mass_amu=float(s.mass_amu[0])))
+    dnu = float(s.nu[1] - s.nu[0])
+    table = bm.opacity_table_build(lines, s.temps, s.p_bar, float(s.nu[0]), dnu, s.nu.size,
+                                   dtype=torch.float64)
+    model = bm.Model(table.reshape(1, *table.shape).contiguous(), s.temps, s.p_bar, s.mass_amu,
+                     s.tp_mode, s.planet)
+    n = args.warmup + args.steps
+    draws = np.array([wl.config1_params()] * n)        # isothermal 1200 K, x = 1e-4
+    params = torch.as_tensor(draws, device="cuda").contiguous()
+    rows = [params[i:i + 1] for i in range(n)]
+    f = bm.Forward(model, 1)
+    for i in range(args.warmup):
+        f(rows[i])
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for i in range(args.steps):
+        f(rows[args.warmup + i])
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    with bm.KernelTiming(args.steps) as kt:
+        for i in range(args.steps):
+            f(rows[args.warmup + i])
+        torch.cuda.synchronize()
+    # algorithmic bytes: two temperature rows per layer (double), the spectrum out
+    nbytes = 8 * (2 * s.p_bar.size * s.nu.size) + 8 * s.nu.size
+    log(f"fp64 single spectrum: {ms * 1e3:.2f} us per call, fused kernel {kt.mean_ms * 1e3:.2f} us")
+    return {"workload": "FP64, 1 absorber (1e4 lines, library-built double table), 10 T x 50 layers "
+                        "x 1000 nu, isothermal, 1 spectrum per call on one stream",
+            "us_per_spectrum": ms * 1e3, "spectra_per_s": 1000.0 / ms, "kernel_us": kt.mean_ms * 1e3,
+            "bytes_per_launch": nbytes, "kernel_gbs": nbytes / (kt.mean_ms * 1e-3) / 1e9,
+            "steps": args.steps}
+
+
 def multi_worker(args, model, rows):
     """BART's layout: one forward-model worker per chain, here W concurrent streams each
     issuing one-spectrum calls (step i on worker i mod W)."""
@@ -504,7 +549,10 @@ def section_mcmc(args, setup, prior):
             f"surrogate refit, rms {rms_local:.2f} ppm")
         del Xl, Yl
 
-    # 4. production runs from the same burned-in state and random stream
+    # 4. production runs from the burned-in state, each on its own random stream: two plain
+    #    batched runs (the second is the plain sampler's own run-to-run yardstick) and a
+    #    longer delayed-acceptance run
+    G_da = args.da_gens
     def production(surrogate=None, per_sample=0, n_gen=G, stream=70):
         r = Retrieval(model, C, prior.lo, prior.hi, seed=args.seed + stream, thin=10, hist_cap=n_gen,
                       surrogate=surrogate, per_sample_workers=per_sample,
@@ -526,59 +574,64 @@ def section_mcmc(args, setup, prior):
         hn = h.cpu().numpy()
         sp = dg.speis_per_chain(hn)
         ess = hn.shape[0] * hn.shape[1] / sp.max()
+        # the multi-chain integrated time, on every 10th state of long runs (scaled back)
+        th = 10 if n_gen > 40000 else 1
+        tau = dg.integrated_time_multichain(hn[::th]) * th
+        ess_mc = hn.shape[0] * hn.shape[1] / tau
         mu, sd = dg.marginal_summary(hn)
         out = {"generations": n_gen, "wall_s": wall, "ms_per_generation": wall / n_gen * 1e3,
                "acceptance": float(acc[1]), "speis_max": float(sp.max()),
                "speis_median": float(np.median(sp)), "ess": float(ess),
                "ess_per_s": float(ess / wall),
+               "integrated_time_multichain": tau.tolist(),
+               "ess_multichain_min": float(ess_mc.min()),
+               "ess_multichain_per_s": float(ess_mc.min() / wall),
                "gelman_rubin_max": float(dg.gelman_rubin(hn).max())}
         out.update(extra)
-        return out, mu, sd
+        return out, mu, sd, tau
 
     log(f"mcmc: plain batched production, {G} generations")
-    _, h_b, w_b, acc_b = production()
-    plain_b, mu_b2, sd_b2 = stats(h_b, w_b, acc_b, G)
-    log(f"mcmc: delayed-acceptance production, {G} generations")
-    _, h_d, w_d, acc_d = production(surrogate=sur)
-    da, mu_d, sd_d = stats(h_d, w_d, acc_d, G, stage1_pass_rate=float(acc_d[0]))
+    _, h_b, w_b, acc_b = production(stream=70)
+    plain_b, mu_b2, sd_b2, tau_b = stats(h_b, w_b, acc_b, G)
+    log(f"mcmc: plain batched replicate (another random stream), {G} generations")
+    _, h_q, w_q, acc_q = production(stream=72)
+    plain_q, mu_q, sd_q, tau_q = stats(h_q, w_q, acc_q, G)
+    del h_q
+    log(f"mcmc: delayed-acceptance production, {G_da} generations")
+    _, h_d, w_d, acc_d = production(surrogate=sur, n_gen=G_da, stream=71)
+    da, mu_d, sd_d, tau_d = stats(h_d, w_d, acc_d, G_da, stage1_pass_rate=float(acc_d[0]))
     del h_d
-    # a second delayed-acceptance run from the same state with another random stream: the
-    # spread between runs of G generations, the yardstick for the plain-vs-DA difference
-    log(f"mcmc: delayed-acceptance replicate (another random stream), {G} generations")
-    _, h_r, w_r, acc_r = production(surrogate=sur, stream=71)
-    da_rep, mu_r, sd_r = stats(h_r, w_r, acc_r, G)
-    del h_r
-    diff_rep = (mu_r - mu_d) / sd_b2
-    plain_rep = None
-    if args.plain_replicate:
-        # opt-in: a second plain run on another random stream, the plain sampler's own spread
-        log(f"mcmc: plain batched replicate (another random stream), {G} generations")
-        _, h_q, w_q, acc_q = production(stream=72)
-        pq, mu_q, _ = stats(h_q, w_q, acc_q, G)
-        del h_q
-        plain_rep = {"ess": pq["ess"], "acceptance": pq["acceptance"],
-                     "marginal_mean_diff_sd_vs_plain": ((mu_q - mu_b2) / sd_b2).tolist(),
-                     "marginal_mean_diff_sd_vs_delayed_acceptance": ((mu_q - mu_d) / sd_b2).tolist()}
     log(f"mcmc: plain per-sample, {args.per_sample_gens} generations timed")
     _, h_p, w_p, _ = production(per_sample=1, n_gen=args.per_sample_gens)
     identical = bool(torch.equal(h_p, h_b[:args.per_sample_gens]))
+    del h_b
     ms_ps = w_p / args.per_sample_gens * 1e3
     # the per-sample form computes the same chains (checked above on the timed slice), so
-    # its ESS over G generations is the batched plain run's
+    # its effective samples over G generations are the batched plain run's
     ps_wall = ms_ps * 1e-3 * G
     plain_ps = {"ms_per_generation": ms_ps, "timed_generations": args.per_sample_gens,
                 "chains_identical_to_batched": identical, "ess": plain_b["ess"],
-                "ess_per_s": plain_b["ess"] / ps_wall}
-    diff = (mu_d - mu_b2) / sd_b2
-    # the same differences in units of their standard error, sd / sqrt(ESS) for each run
-    se = np.sqrt(sd_b2 ** 2 / plain_b["ess"] + sd_d ** 2 / da["ess"])
-    diff_z = (mu_d - mu_b2) / se
+                "ess_per_s": plain_b["ess"] / ps_wall,
+                "ess_multichain_min": plain_b["ess_multichain_min"],
+                "ess_multichain_per_s": plain_b["ess_multichain_min"] / ps_wall}
+    # posterior agreement: marginal means in units of the posterior sd (pooled plain runs),
+    # with the Monte Carlo standard error of each run's mean from its integrated time
+    sd_ref = 0.5 * (sd_b2 + sd_q)
+    mu_plain = 0.5 * (mu_b2 + mu_q)
+    se = lambda tau, n: sd_ref * np.sqrt(tau / (n * C))  # noqa: E731
+    se_plain = 0.5 * np.sqrt(se(tau_b, G) ** 2 + se(tau_q, G) ** 2)
+    diff = (mu_d - mu_plain) / sd_ref
+    diff_se = np.sqrt(se_plain ** 2 + se(tau_d, G_da) ** 2) / sd_ref
+    diff_pp = (mu_q - mu_b2) / sd_ref
+    diff_pp_se = np.sqrt(se(tau_b, G) ** 2 + se(tau_q, G) ** 2) / sd_ref
     ratio = da["ess_per_s"] / plain_ps["ess_per_s"]
+    ratio_mc = da["ess_multichain_per_s"] / plain_ps["ess_multichain_per_s"]
     # end to end: surrogate data and training charged to the delayed-acceptance run
-    e2e = (da["ess"] / (w_d + t_local)) / (plain_b["ess"] / ps_wall)
+    e2e = (da["ess_multichain_min"] / (w_d + t_local)) / plain_ps["ess_multichain_per_s"]
     log(f"mcmc: ESS/s per-sample {plain_ps['ess_per_s']:.2f}, batched {plain_b['ess_per_s']:.2f}, "
-        f"delayed acceptance {da['ess_per_s']:.2f} -> {ratio:.1f}x; max |mean diff| "
-        f"{np.abs(diff).max():.3f} sd (two delayed-acceptance runs: {np.abs(diff_rep).max():.3f} sd)")
+        f"delayed acceptance {da['ess_per_s']:.2f} -> {ratio:.1f}x (multi-chain ESS: {ratio_mc:.1f}x); "
+        f"max |mean diff| delayed acceptance vs plain {np.abs(diff).max():.3f} sd "
+        f"(plain vs plain {np.abs(diff_pp).max():.3f} sd)")
     return {
         "chains": C, "burn_in": BURN, "da_burn_in": args.da_burn, "truth": truth.tolist(),
         "prior": {"lo": prior.lo.tolist(), "hi": prior.hi.tolist()},
@@ -593,22 +646,25 @@ def section_mcmc(args, setup, prior):
                                 "chi2_error_sd": float(dchi2.std())}},
         "plain_per_sample": plain_ps,
         "plain_batched": plain_b,
+        "plain_batched_replicate": plain_q,
         "delayed_acceptance": da,
         "ess_per_s_ratio_vs_per_sample": ratio,
+        "ess_multichain_per_s_ratio_vs_per_sample": ratio_mc,
         "ess_per_s_ratio_vs_batched": da["ess_per_s"] / plain_b["ess_per_s"],
-        "ess_per_s_ratio_end_to_end": e2e,
-        "marginal_mean_diff_sd": diff.tolist(),
-        "max_abs_mean_diff_sd": float(np.abs(diff).max()),
-        "marginal_mean_diff_in_standard_errors": diff_z.tolist(),
-        "max_abs_mean_diff_in_standard_errors": float(np.abs(diff_z).max()),
-        "delayed_acceptance_replicate": {
-            "ess": da_rep["ess"], "gelman_rubin_max": da_rep["gelman_rubin_max"],
-            "marginal_mean_diff_sd_vs_delayed_acceptance": diff_rep.tolist(),
-            "max_abs_mean_diff_sd_vs_delayed_acceptance": float(np.abs(diff_rep).max())},
-        "marginal_mean": {"plain": mu_b2.tolist(), "delayed_acceptance": mu_d.tolist(),
-                          "delayed_acceptance_replicate": mu_r.tolist()},
+        "ess_multichain_per_s_ratio_end_to_end": e2e,
+        "agreement": {
+            "marginal_mean_diff_sd_vs_plain": diff.tolist(),
+            "max_abs_mean_diff_sd_vs_plain": float(np.abs(diff).max()),
+            "standard_error_sd": diff_se.tolist(),
+            "plain_vs_plain_diff_sd": diff_pp.tolist(),
+            "max_abs_plain_vs_plain_diff_sd": float(np.abs(diff_pp).max()),
+            "plain_vs_plain_standard_error_sd": diff_pp_se.tolist(),
+            "note": "delayed acceptance against the mean of the two plain runs; standard errors "
+                    "sd sqrt(tau / (generations x chains)) from each run's multi-chain integrated "
+                    "time"},
+        "marginal_mean": {"plain": mu_b2.tolist(), "plain_replicate": mu_q.tolist(),
+                          "delayed_acceptance": mu_d.tolist()},
         "marginal_sd": {"plain": sd_b2.tolist(), "delayed_acceptance": sd_d.tolist()},
-        **({"plain_replicate": plain_rep} if plain_rep is not None else {}),
     }
 
 
@@ -863,7 +919,7 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--table", choices=("opacity", "random"), default="opacity")
-    ap.add_argument("--sections", default="forward,batched,mcmc",
+    ap.add_argument("--sections", default="forward,fp64,batched,mcmc,opacity",
                     help="comma list of forward, batched, mcmc, opacity, copy")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -878,14 +934,16 @@ def main():
     ap.add_argument("--no-mixed", dest="mixed", action="store_false")
     ap.add_argument("--opacity-oversample", type=int, default=1000,
                     help="fine samples per output interval of the profile table (opacity section)")
-    ap.add_argument("--mcmc-gens", type=int, default=20000)
+    ap.add_argument("--mcmc-gens", type=int, default=30000,
+                    help="generations of each of the two plain production runs")
+    ap.add_argument("--da-gens", type=int, default=150000,
+                    help="generations of the delayed-acceptance production run")
     ap.add_argument("--mcmc-burn", type=int, default=1000)
-    ap.add_argument("--da-burn", type=int, default=0,
-                    help="further burn-in generations with delayed acceptance before production")
+    ap.add_argument("--da-burn", type=int, default=50000,
+                    help="further burn-in generations with delayed acceptance before production "
+                         "(about twice the slowest integrated time of this posterior)")
     ap.add_argument("--per-sample-gens", type=int, default=200)
     ap.add_argument("--train-spectra", type=int, default=200000)
-    ap.add_argument("--plain-replicate", action="store_true",
-                    help="also run a second plain production on another random stream")
     ap.add_argument("--surrogate-box", type=float, default=5.0,
                     help="half-width of the local surrogate's input box, in burn-in sd")
     ap.add_argument("--local-spectra", type=int, default=100000)
@@ -936,6 +994,8 @@ def main():
                                            params_np, args.cpu_seconds, args.cpu_workers)
         log("timing the CPU oracle's opacity build on a line subset")
         out["cpu_baseline"]["opacity_subset"] = cpu_baseline_opacity(wl.SEED_BASE + 4)
+    if "fp64" in sections:
+        out["fp64_single_spectrum"] = section_fp64(args)
     if "batched" in sections:
         out["batched"] = section_batched(args, setup, model, prior)
     if "mcmc" in sections:

@@ -404,6 +404,9 @@ typedef struct bm_demcz {
                            ter Braak & Vrugt 2008; 0.1 there), 0 = archive DE moves only     */
     double* log_q;      /* [C] log proposal factor of each chain's current proposal (0 for DE
                            moves); required when p_snooker > 0, else may be NULL           */
+    double gamma_scale; /* DE-move step factor: gamma = gamma_scale 2.38/sqrt(2d) (ter Braak's
+                           value for Gaussian targets); 0 is read as 1. The every-10th-
+                           generation gamma = 1 moves are not scaled                         */
 } bm_demcz;
 
 /* Chains at uniform prior draws, archive with z_init further draws, counters reset. */

@@ -58,14 +58,15 @@ def init_state(seed: int, n_chains: int, z_init: int, lo, hi):
     return draws[z_init:].copy(), draws[:z_init].copy()
 
 
-def propose(x, z, m: int, g: int, seed: int, lo, hi, eps_scale: float):
+def propose(x, z, m: int, g: int, seed: int, lo, hi, eps_scale: float, gamma_scale: float = 1.0):
     """DE-MCz proposals of generation g: y = x + gamma (z_r1 - z_r2) + e, r1 != r2 uniform
-    over the m archive rows, gamma = 2.38/sqrt(2d) (1 every 10th generation),
-    e ~ N(0, (eps_scale * width)^2). Returns (y, r1, r2)."""
+    over the m archive rows, gamma = gamma_scale 2.38/sqrt(2d) (1 every 10th generation;
+    ter Braak's value for Gaussian targets at gamma_scale = 1), e ~ N(0, (eps_scale *
+    width)^2). Returns (y, r1, r2)."""
     n_chains, d = x.shape
     y = np.empty_like(x)
     r1s, r2s = np.empty(n_chains, int), np.empty(n_chains, int)
-    gamma = 1.0 if g % 10 == 9 else 2.38 / math.sqrt(2.0 * d)
+    gamma = 1.0 if g % 10 == 9 else gamma_scale * (2.38 / math.sqrt(2.0 * d))
     for c in range(n_chains):
         r1 = min(int(u01(seed, counter(g, c, n_chains, SLOT_R1)) * m), m - 1)
         r2 = min(int(u01(seed, counter(g, c, n_chains, SLOT_R2)) * (m - 1)), m - 2)
@@ -118,12 +119,13 @@ def third_row(u: float, m: int, r1: int, r2: int) -> int:
     return rz
 
 
-def propose_zs(x, z, m: int, g: int, seed: int, lo, hi, eps_scale: float, p_snooker: float):
+def propose_zs(x, z, m: int, g: int, seed: int, lo, hi, eps_scale: float, p_snooker: float,
+               gamma_scale: float = 1.0):
     """DEMCzs proposals of generation g: chain c takes a snooker move when its move-choice
     uniform is below p_snooker (and the archive has at least 3 rows), otherwise the
     parallel-direction move of propose(). Returns (y, log_q) with log_q the log proposal
     factor of each chain (0 for parallel-direction moves)."""
-    y, r1s, r2s = propose(x, z, m, g, seed, lo, hi, eps_scale)
+    y, r1s, r2s = propose(x, z, m, g, seed, lo, hi, eps_scale, gamma_scale)
     n_chains, d = x.shape
     log_q = np.zeros(n_chains)
     if p_snooker <= 0.0 or m < 3:

@@ -52,6 +52,34 @@ def ess(chains: np.ndarray, threshold: float = 0.01) -> float:
     return c.shape[0] * c.shape[1] / speis(c, threshold)
 
 
+def integrated_time_multichain(chains: np.ndarray) -> np.ndarray:
+    """Integrated autocorrelation time per parameter from m chains together (the
+    within/between-chain method of Vehtari et al., which Sec. 5 discusses as the
+    alternative to its SPEIS): the combined autocorrelation
+    rho_t = 1 - (W - mean_c acov_c(t)) / var_plus, var_plus = (n-1)/n W + B/n,
+    summed with Geyer's (1992) initial monotone sequence: pairs P_k = rho_2k + rho_2k+1
+    while positive, made non-increasing, tau = -1 + 2 sum_k P_k.
+    chains: [m][n][n_params]. ESS = m n / tau."""
+    c = np.asarray(chains, dtype=np.float64)
+    m, n, n_par = c.shape
+    out = np.empty(n_par)
+    for p in range(n_par):
+        acov = np.array([autocorrelation(c[i, :, p]) * np.var(c[i, :, p]) for i in range(m)])
+        w = np.mean([np.var(c[i, :, p], ddof=1) for i in range(m)])
+        b_over_n = np.var([np.mean(c[i, :, p]) for i in range(m)], ddof=1)
+        var_plus = (n - 1.0) / n * w + b_over_n
+        rho = 1.0 - (w - acov.mean(axis=0)) / var_plus
+        total, prev = 0.0, np.inf
+        for k in range(n // 2):
+            pair = rho[2 * k] + rho[2 * k + 1]
+            if pair < 0.0:
+                break
+            prev = min(prev, pair)
+            total += prev
+        out[p] = -1.0 + 2.0 * total
+    return out
+
+
 def credible_region_error(c_hat: float, n: float) -> float:
     """Posterior standard deviation of the probability content of a credible region
     from n independent samples (App. C): s_C = sqrt(C (1 - C) / (n + 3))."""

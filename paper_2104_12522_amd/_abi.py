@@ -44,7 +44,7 @@ class BmDemcz(C.Structure):
         ("x", C.c_void_p), ("lp", C.c_void_p), ("lp_surr", C.c_void_p), ("prop", C.c_void_p),
         ("z", C.c_void_p), ("counters", C.c_void_p), ("n_accept", C.c_void_p),
         ("history", C.c_void_p), ("lo", C.c_void_p), ("hi", C.c_void_p),
-        ("p_snooker", C.c_double), ("log_q", C.c_void_p),
+        ("p_snooker", C.c_double), ("log_q", C.c_void_p), ("gamma_scale", C.c_double),
     ]
 
 

@@ -248,6 +248,7 @@ static int check_demcz(const bm_demcz* s) {
     if (s->thin < 1 || s->z_cap < 2) return BM_ESHAPE;
     if (!(s->eps_scale >= 0.0)) return BM_EINVAL;
     if (!(s->p_snooker >= 0.0 && s->p_snooker <= 1.0)) return BM_EINVAL;
+    if (!(s->gamma_scale >= 0.0 && s->gamma_scale <= 4.0)) return BM_EINVAL;
     if (s->p_snooker > 0.0 && !s->log_q) return BM_EINVAL;
     return BM_OK;
 }
@@ -277,8 +278,9 @@ extern "C" int bm_demcz_set_lp(const bm_demcz* s, const double* chi2, const int3
 extern "C" int bm_demcz_propose(const bm_demcz* s, void* stream) {
     int st = check_demcz(s);
     if (st != BM_OK) return st;
-    // gamma = 2.38 / sqrt(2 d) (correctly rounded host arithmetic)
-    const double gamma_de = 2.38 / std::sqrt(2.0 * s->n_params);
+    // gamma = gamma_scale (2.38 / sqrt(2 d)) (correctly rounded host arithmetic)
+    const double scale = s->gamma_scale > 0.0 ? s->gamma_scale : 1.0;
+    const double gamma_de = scale * (2.38 / std::sqrt(2.0 * s->n_params));
     hipLaunchKernelGGL(k_demcz_propose, dim3((s->n_chains + 255) / 256), dim3(256), 0, (hipStream_t)stream, *s,
                        gamma_de);
     BM_CHECK_HIP(hipGetLastError());

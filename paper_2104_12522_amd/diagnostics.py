@@ -62,6 +62,40 @@ def ess_per_parameter(history: np.ndarray, threshold: float = 0.01) -> np.ndarra
     return h.shape[0] * h.shape[1] / speis_per_chain(h, threshold).max(axis=0)
 
 
+def integrated_time_multichain(history: np.ndarray) -> np.ndarray:
+    """Integrated autocorrelation time per parameter from all chains together (the
+    within/between-chain method of Vehtari et al., the alternative to SPEIS that Sec. 5
+    discusses): combined autocorrelation rho_t = 1 - (W - mean_c acov_c(t)) / var_plus,
+    var_plus = (n-1)/n W + B/n, summed with Geyer's initial monotone sequence of pair
+    sums. Unlike the largest per-chain SPEIS it includes the spread between chains, so
+    it does not shrink when every chain is still far from independent samples."""
+    h = np.asarray(history, dtype=np.float64)
+    n, m, n_par = h.shape
+    x = h - h.mean(axis=0, keepdims=True)
+    size = 1
+    while size < 2 * n:
+        size *= 2
+    out = np.empty(n_par)
+    w = h.var(axis=0, ddof=1).mean(axis=0)
+    b_over_n = h.mean(axis=0).var(axis=0, ddof=1)
+    var_plus = (n - 1.0) / n * w + b_over_n
+    for p in range(n_par):
+        spec = np.fft.rfft(x[:, :, p], n=size, axis=0)
+        acov = np.fft.irfft(spec.real ** 2 + spec.imag ** 2, n=size, axis=0)[:n] / n
+        rho = 1.0 - (w[p] - acov.mean(axis=1)) / var_plus[p]
+        pairs = rho[0:2 * (n // 2):2] + rho[1:2 * (n // 2):2]
+        neg = np.flatnonzero(pairs < 0.0)
+        pairs = pairs[:neg[0]] if neg.size else pairs
+        out[p] = -1.0 + 2.0 * np.minimum.accumulate(pairs).sum()
+    return out
+
+
+def ess_multichain(history: np.ndarray) -> np.ndarray:
+    """Per parameter: all kept steps of all chains over the multi-chain integrated time."""
+    h = np.asarray(history)
+    return h.shape[0] * h.shape[1] / integrated_time_multichain(h)
+
+
 def gelman_rubin(history: np.ndarray) -> np.ndarray:
     """Potential scale reduction per parameter from m chains of n steps:
     sqrt(((n-1)/n W + (m+1)/(m n) B) / W), W the mean within-chain variance and B/n the

@@ -23,7 +23,7 @@ class DEMCz:
 
     def __init__(self, n_chains: int, lo, hi, seed: int, thin: int = 10, z_cap: int | None = None,
                  hist_cap: int = 0, eps_scale: float = 1e-6, surrogate: bool = False,
-                 p_snooker: float = 0.0, device="cuda"):
+                 p_snooker: float = 0.0, gamma_scale: float = 1.0, device="cuda"):
         lo = np.asarray(lo, dtype=np.float64)
         hi = np.asarray(hi, dtype=np.float64)
         d = lo.size
@@ -47,6 +47,7 @@ class DEMCz:
         st.seed = seed & 0xFFFFFFFFFFFFFFFF
         st.eps_scale = eps_scale
         st.p_snooker = float(p_snooker)
+        st.gamma_scale = float(gamma_scale)
         for name in ("x", "lp", "lp_surr", "prop", "z", "counters", "n_accept", "history", "lo", "hi",
                      "log_q"):
             setattr(st, name, _ptr(getattr(self, name)))
@@ -152,7 +153,7 @@ class Retrieval:
 
     def __init__(self, model, n_chains: int, lo, hi, seed: int, thin: int = 10,
                  hist_cap: int = 0, surrogate=None, eps_scale: float = 1e-6, z_cap=None,
-                 per_sample_workers: int = 0, p_snooker: float = 0.1):
+                 per_sample_workers: int = 0, p_snooker: float = 0.1, gamma_scale: float = 1.0):
         self.model = model
         if per_sample_workers:
             if surrogate is not None:
@@ -161,7 +162,8 @@ class Retrieval:
         else:
             self.fwd = Forward(model, n_chains, binned=True, chi2=True)
         self.s = DEMCz(n_chains, lo, hi, seed, thin=thin, hist_cap=hist_cap, z_cap=z_cap,
-                       eps_scale=eps_scale, surrogate=surrogate is not None, p_snooker=p_snooker)
+                       eps_scale=eps_scale, surrogate=surrogate is not None, p_snooker=p_snooker,
+                       gamma_scale=gamma_scale)
         self.surrogate = surrogate
         self.active = torch.ones(n_chains, dtype=torch.int32, device=self.s.x.device)
 

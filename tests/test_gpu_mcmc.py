@@ -26,10 +26,10 @@ def _np(t):
 PRIOR = wl.line2013_prior(4)
 
 
-@pytest.mark.parametrize("p_snooker", [0.0, 0.5])
-def test_init_and_proposals_match_reference(p_snooker):
+@pytest.mark.parametrize("p_snooker,gscale", [(0.0, 1.0), (0.5, 1.0), (0.0, 0.3)])
+def test_init_and_proposals_match_reference(p_snooker, gscale):
     C, seed, z_init = 37, 987654321, 100
-    s = DEMCz(C, PRIOR.lo, PRIOR.hi, seed, z_cap=400, p_snooker=p_snooker)
+    s = DEMCz(C, PRIOR.lo, PRIOR.hi, seed, z_cap=400, p_snooker=p_snooker, gamma_scale=gscale)
     s.init(z_init)
     x_ref, z_ref = om.init_state(seed, C, z_init, PRIOR.lo, PRIOR.hi)
     torch.cuda.synchronize()
@@ -37,7 +37,7 @@ def test_init_and_proposals_match_reference(p_snooker):
     assert np.array_equal(_np(s.z)[:z_init], z_ref)
     assert s.archive_size == z_init and s.generation == 0
     s.propose()
-    y_ref, lq_ref = om.propose_zs(x_ref, z_ref, z_init, 0, seed, PRIOR.lo, PRIOR.hi, 1e-6, p_snooker)
+    y_ref, lq_ref = om.propose_zs(x_ref, z_ref, z_init, 0, seed, PRIOR.lo, PRIOR.hi, 1e-6, p_snooker, gscale)
     # DE moves carry normals (device log/cos); snooker moves are +-*/ only: bit-exact
     np.testing.assert_allclose(_np(s.prop), y_ref, rtol=4.5e-16, atol=1e-300)
     snk = lq_ref != 0.0

@@ -82,3 +82,42 @@ def test_product_diagnostics_match_oracle():
     assert dg.speis(hist) == pytest.approx(stats.speis(chains), rel=1e-10)
     assert dg.ess(hist) == pytest.approx(stats.ess(chains), rel=1e-10)
     np.testing.assert_allclose(dg.gelman_rubin(hist), stats.gelman_rubin(chains), rtol=1e-12)
+
+
+def _ar1_chains(a, m, n, seed):
+    g = np.random.default_rng(seed)
+    x = np.empty((m, n))
+    x[:, 0] = g.normal(size=m) / np.sqrt(1 - a * a)      # stationary start
+    eps = g.normal(size=(m, n))
+    for i in range(1, n):
+        x[:, i] = a * x[:, i - 1] + eps[:, i]
+    return x
+
+
+def test_multichain_time_of_ar1_matches_closed_form():
+    # AR(1) chains with coefficient a: tau = (1 + a) / (1 - a); the estimator's error on
+    # m chains of n steps is of order tau sqrt(tau / (m n))
+    for a in (0.5, 0.9):
+        x = _ar1_chains(a, 8, 40_000, seed=int(a * 10))
+        tau = stats.integrated_time_multichain(x[:, :, None])[0]
+        assert tau == pytest.approx((1 + a) / (1 - a), rel=0.08)
+    # independent samples: tau ~ 1
+    x = np.random.default_rng(5).normal(size=(6, 20_000, 1))
+    assert stats.integrated_time_multichain(x)[0] == pytest.approx(1.0, abs=0.06)
+
+
+def test_multichain_time_counts_chains_that_have_not_mixed():
+    # chains that each sit at their own level (no mixing between them within the run):
+    # per-chain autocorrelations look independent, the combined estimate does not
+    g = np.random.default_rng(6)
+    x = g.normal(size=(8, 5000, 1)) + 3.0 * g.normal(size=(8, 1, 1))
+    assert stats.speis(x, threshold=0.01) < 1.5
+    assert stats.integrated_time_multichain(x)[0] > 100
+
+
+def test_product_multichain_time_matches_oracle():
+    from paper_2104_12522_amd import diagnostics as dg
+    x = np.stack([_ar1_chains(a, 5, 3000, seed=9 + i) for i, a in enumerate((0.0, 0.7, 0.97))], axis=2)
+    ref = stats.integrated_time_multichain(x)
+    got = dg.integrated_time_multichain(x.transpose(1, 0, 2))
+    np.testing.assert_allclose(got, ref, rtol=1e-9)
