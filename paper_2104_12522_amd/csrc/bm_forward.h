@@ -1,5 +1,6 @@
 // Shared declarations of the forward-model kernels (internal).
 #pragma once
+#include <cstddef>
 
 #include <vector>
 
@@ -117,6 +118,9 @@ struct RecordHeader {
     int32_t jcloud;  // chords j <= jcloud lie in or below the cloud deck (-1: none)
     int32_t pad;
 };
+// the fused kernel reads flags .. pad as int32 words 4 .. 7 of the header
+static_assert(offsetof(RecordHeader, flags) == 16 && offsetof(RecordHeader, jcloud) == 24 &&
+                  sizeof(RecordHeader) == 32, "record header layout");
 
 inline __host__ __device__ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 inline __host__ __device__ int row_blocks(int L) { return (L + kRows - 1) / kRows; }

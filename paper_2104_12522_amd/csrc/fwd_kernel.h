@@ -179,12 +179,17 @@ __global__ void __launch_bounds__(kWaves * kWave)
     const int kx = g / kXcds;
     const int tile = (g % kXcds) * sg.tiles_per_xcd + kx / slots;
     const int slot = kx % slots;
-    if (tile >= sg.tiles) return;  // padding workgroup of the XCD split
+    // The pipelined unmasked-list variant checks its exits (padding workgroup, sample not
+    // requested) only after its first record loads are in flight: those loads are in bounds
+    // for any workgroup, and the kernel-argument reads behind the checks then overlap them.
+    constexpr bool kLateExit = kPipe && !kCompact;
+    const bool pad = tile >= sg.tiles;  // padding workgroup of the XCD split
+    if (!kLateExit && pad) return;
     // one sample of this workgroup's tile (the compacted variant runs it for each of its
     // list entries; the loop stays out of the other variants' code)
     auto run = [&](const int s_in) {
         const int b = sg.first + s_in;
-        if (active && !active[b]) return;  // sample not requested in this call
+        if (!kLateExit && active && !active[b]) return;  // sample not requested in this call
         const int L = m.L, Nnu = m.Nnu;
         const RecordView<T> rec(ws + sg.ws_off + (size_t)s_in * sg.rec_bytes, kS, L);
         const FwdLds<T> lay(L, kWaves, plan.max_ntc, kPipe);
@@ -214,8 +219,23 @@ __global__ void __launch_bounds__(kWaves * kWave)
         double* part = reinterpret_cast<double*>(smem + lay.part);
         double* dsh = reinterpret_cast<double*>(smem + lay.bins);
         double* dout = depth + sg.depth_off + (size_t)s_in * Nnu;
-        const int flags = rec.hdr->flags;
-        const int jcl = m.cloud ? rec.hdr->jcloud : -1;  // chords j <= jcl are opaque (cloud deck)
+        // record header: the pipelined path reads it with a vector load after its record
+        // fields (a scalar load of this freshly written record would hold up every scalar
+        // wait of the prologue until it returned)
+        int flags = 0, jcl = -1;  // jcl: chords j <= jcl are opaque (cloud deck)
+        if constexpr (!kPipe) {
+            flags = rec.hdr->flags;
+            jcl = m.cloud ? rec.hdr->jcloud : -1;
+        }
+        // this tile's channels (phase 3); the pipelined path fetches their data and errors
+        // with its first loads, so that phase 3 does not wait on memory
+        const int bw = m.bin_width;
+        const int nbt = bw > 0 ? sg.tile_w / bw : 0;  // whole channels per tile
+        const int nbins = bw > 0 ? Nnu / bw : 0;
+        const bool want_chi2 = (chi2 != nullptr) && m.data && m.err;
+        const int cg = tile * nbt + lane;
+        const bool own_bin = binned != nullptr && sg.fused_bins && lane < nbt && cg < nbins;
+        double ch_data = 0.0, ch_err = 1.0;
         // this lane's H2 Rayleigh cross section (the record holds n_H2 per layer); zero without
         // Rayleigh scattering, so that the per-layer term needs no branch (a branch in the
         // extinction loop cost 16 % at 256 samples per launch)
@@ -228,7 +248,18 @@ __global__ void __launch_bounds__(kWaves * kWave)
         // return in issue order, so waiting for them does not wait for the copies).
         if (kPipe || !(flags & BM_FLAG_RADIUS)) {
             PipeFields<T, kS, kCia> pf;
-            if constexpr (kPipe) pf.load(rec, L, kPipeMaxLayers, wave, lane, m.NT, m.NTc);
+            int hv = 0;  // header words flags, (unused), jcloud, pad in lanes 0-3 (pipelined)
+            if constexpr (kPipe) {
+                pf.load(rec, L, kPipeMaxLayers, wave, lane, m.NT, m.NTc);
+                // header words 0-7 (base, rs2, flags, unused, jcloud, pad) in lanes 0-7
+                hv = reinterpret_cast<const int32_t*>(rec.hdr)[lane & 7];
+                if (want_chi2 && own_bin && wave == 0) {
+                    ch_data = m.data[cg];
+                    ch_err = m.err[cg];
+                }
+                if constexpr (kLateExit)
+                    if (pad || (active && !active[b])) return;
+            }
             // impact-parameter weights (read per optical depth in phase 2) and this tile's
             // columns of every CIA temperature row (read by many layers) go to LDS; all their
             // loads are issued before the first store
@@ -406,6 +437,8 @@ __global__ void __launch_bounds__(kWaves * kWave)
                 issue(1, vb0, vb1);
                 // keep the stage loads ahead of the waits that the LDS stores below need
                 __builtin_amdgcn_sched_barrier(0);
+                flags = __builtin_amdgcn_readlane(hv, 4);
+                if (m.cloud) jcl = __builtin_amdgcn_readlane(hv, 6);
                 if ((int)threadIdx.x < L) cw_s[threadIdx.x] = cwv;
                 if constexpr (kCia) cia_store();
                 // zero rows past the last layer (read by the top stages against zero weights)
@@ -426,10 +459,12 @@ __global__ void __launch_bounds__(kWaves * kWave)
                 }
                 __syncthreads();
                 if (wave == 0) {
-                    double sum = rec.hdr->base;
+                    const double base = __hiloint2double(__builtin_amdgcn_readlane(hv, 1), __builtin_amdgcn_readlane(hv, 0));
+                    const double rs2 = __hiloint2double(__builtin_amdgcn_readlane(hv, 3), __builtin_amdgcn_readlane(hv, 2));
+                    double sum = base;
                     if (jcl >= L - 1) sum += cw_s[L - 1];  // the top chord lies in the deck
                     for (int J = 0; J < nJ; ++J) sum += part[J * kTileNu + lane];
-                    dval = (flags & BM_FLAG_RADIUS) ? __builtin_nan("") : sum / rec.hdr->rs2;
+                    dval = (flags & BM_FLAG_RADIUS) ? __builtin_nan("") : sum / rs2;
                 }
             } else {
             // ---- phase 1: extinction into LDS --------------------------------------------
@@ -609,21 +644,20 @@ __global__ void __launch_bounds__(kWaves * kWave)
         // ---- phase 3: channels of this tile; chi^2 partial; last tile sums the partials ----
         if (binned == nullptr || !sg.fused_bins) return;
         __syncthreads();
-        const int bw = m.bin_width;
-        const int nbt = sg.tile_w / bw;   // whole channels per tile
-        const int nbins = Nnu / bw;
-        const bool want_chi2 = (chi2 != nullptr) && m.data && m.err;
         double* bout = binned + sg.bin_off + (size_t)s_in * nbins;
         if (wave == 0) {
             double term = 0.0;
-            const int cg = tile * nbt + lane;
-            if (lane < nbt && cg < nbins) {
+            if (own_bin) {
                 double acc = 0.0;
                 for (int q = 0; q < bw; ++q) acc += dsh[lane * bw + q];
                 const double mean = acc / bw;
                 bout[cg] = mean;
                 if (want_chi2) {
-                    const double d = (mean - m.data[cg]) / m.err[cg];
+                    if constexpr (!kPipe) {
+                        ch_data = m.data[cg];
+                        ch_err = m.err[cg];
+                    }
+                    const double d = (mean - ch_data) / ch_err;
                     term = d * d;
                 }
             }
