@@ -466,7 +466,7 @@ def section_mcmc(args, setup, prior):
 
     # launch configuration of the C-chain forward call, tuned once for every run below
     tune_fwd = bm.Forward(model, C, binned=True, chi2=True)
-    chosen, _ = tune_fwd.tune(dev(prior.draw(C, seed=args.seed + 66)), reps=3)
+    chosen, _ = tune_fwd.tune(dev(prior.draw(C, seed=args.seed + 66)), reps=8)
     log(f"mcmc: {C}-chain forward call tuned -> config {chosen}")
     del tune_fwd
 

@@ -229,8 +229,9 @@ int bm_bin_chi2(const double* depth, int B, int n_nu, int bin_width, const doubl
  * depth, binned, chi2 and flags entries are left untouched (delayed acceptance runs the
  * exact model only for the proposals its first stage passed, with static shapes). A
  * masked transit call of one model over more than 16 samples builds the list of
- * requested samples on the device and launches the fused kernel over that list, so its
- * cost follows the number of requested samples.
+ * requested samples on the device and launches the record preparation and the fused
+ * kernel over that list (the requested samples' workgroups first), so its cost follows the
+ * number of requested samples.
  * The workspace (device, `workspace_bytes` >= bm_workspace_size(...)) holds per-sample
  * records and the list of requested samples; it needs no initialisation. Calls sharing
  * one workspace must be ordered on one stream. Only kernels are enqueued (no memset or copy), so a call can be captured

@@ -250,14 +250,16 @@ __device__ inline double chord_weight(const double* r, int L, int j, int l) {
 // Per-sample record for the fused forward kernel. Grid: B samples x P slices. Every
 // workgroup of a sample evaluates its atmosphere (a latency-bound chain of a few us);
 // slice p fills 1/P of the chord weights, slice 0 also the per-layer fields.
+// A masked call with a device-built list of its requested samples (compact, its count at
+// *compact_count) launches a few sample slots instead of every sample: slot x takes list
+// entries x, x + gridDim.x, ... in turn.
 template <typename T, bool kSingle, bool kMasked>
 __global__ void __launch_bounds__(kAtmThreads)
     k_atm_prep(LaunchPlan plan, const double* __restrict__ params, int stride, const int32_t* __restrict__ active,
-               char* __restrict__ ws, int32_t* __restrict__ flags_out) {
+               char* __restrict__ ws, int32_t* __restrict__ flags_out, const int32_t* __restrict__ compact,
+               const int32_t* __restrict__ compact_count) {
     __shared__ AtmShared sh;
-    const int b = blockIdx.x;
-    if constexpr (kMasked)
-        if (!active[b]) return;  // sample not requested in this call
+  auto one = [&](const int b) {
     const int slice = blockIdx.y, n_slices = gridDim.y;
     // a single-segment plan keeps its model in slot 0, so the model's fields sit at fixed
     // kernel-argument offsets and are fetched in one round
@@ -358,16 +360,37 @@ __global__ void __launch_bounds__(kAtmThreads)
         }
         rec.wb[idx] = (T)chord_weight(r, L, j, l);
     }
+  };
+    if constexpr (kMasked) {
+        if (compact) {
+            const int n_items = *compact_count;
+            for (int q = blockIdx.x; q < n_items; q += gridDim.x) {
+                if (q != (int)blockIdx.x) __syncthreads();  // the previous sample's shared reads are done
+                one(compact[q]);
+            }
+            return;
+        }
+        if (!active[blockIdx.x]) return;  // sample not requested in this call
+    }
+    one(blockIdx.x);
 }
 
-template __global__ void k_atm_prep<float, true, true>(LaunchPlan, const double*, int, const int32_t*, char*, int32_t*);
-template __global__ void k_atm_prep<float, true, false>(LaunchPlan, const double*, int, const int32_t*, char*, int32_t*);
-template __global__ void k_atm_prep<float, false, true>(LaunchPlan, const double*, int, const int32_t*, char*, int32_t*);
-template __global__ void k_atm_prep<float, false, false>(LaunchPlan, const double*, int, const int32_t*, char*, int32_t*);
-template __global__ void k_atm_prep<double, true, true>(LaunchPlan, const double*, int, const int32_t*, char*, int32_t*);
-template __global__ void k_atm_prep<double, true, false>(LaunchPlan, const double*, int, const int32_t*, char*, int32_t*);
-template __global__ void k_atm_prep<double, false, true>(LaunchPlan, const double*, int, const int32_t*, char*, int32_t*);
-template __global__ void k_atm_prep<double, false, false>(LaunchPlan, const double*, int, const int32_t*, char*, int32_t*);
+template __global__ void k_atm_prep<float, true, true>(LaunchPlan, const double*, int, const int32_t*, char*, int32_t*,
+                                                      const int32_t*, const int32_t*);
+template __global__ void k_atm_prep<float, true, false>(LaunchPlan, const double*, int, const int32_t*, char*, int32_t*,
+                                                      const int32_t*, const int32_t*);
+template __global__ void k_atm_prep<float, false, true>(LaunchPlan, const double*, int, const int32_t*, char*, int32_t*,
+                                                      const int32_t*, const int32_t*);
+template __global__ void k_atm_prep<float, false, false>(LaunchPlan, const double*, int, const int32_t*, char*, int32_t*,
+                                                      const int32_t*, const int32_t*);
+template __global__ void k_atm_prep<double, true, true>(LaunchPlan, const double*, int, const int32_t*, char*, int32_t*,
+                                                      const int32_t*, const int32_t*);
+template __global__ void k_atm_prep<double, true, false>(LaunchPlan, const double*, int, const int32_t*, char*, int32_t*,
+                                                      const int32_t*, const int32_t*);
+template __global__ void k_atm_prep<double, false, true>(LaunchPlan, const double*, int, const int32_t*, char*, int32_t*,
+                                                      const int32_t*, const int32_t*);
+template __global__ void k_atm_prep<double, false, false>(LaunchPlan, const double*, int, const int32_t*, char*, int32_t*,
+                                                      const int32_t*, const int32_t*);
 
 }  // namespace bm
 

@@ -232,10 +232,12 @@ int launch_k_forward(const HostPlan& hp, const LaunchPlan& lp, size_t lds, char*
                      hipEvent_t ev1);
 
 // record preparation; kSingle: a single-segment plan whose model is in slot 0;
-// kMasked: `active` is not null
+// kMasked: `active` is not null; compact (or null): the list of requested samples of a
+// masked call and compact_count its length, taken in turn by gridDim.x sample slots
 template <typename T, bool kSingle, bool kMasked>
 __global__ void k_atm_prep(LaunchPlan plan, const double* __restrict__ params, int stride,
                            const int32_t* __restrict__ active, char* __restrict__ ws,
-                           int32_t* __restrict__ flags_out);
+                           int32_t* __restrict__ flags_out, const int32_t* __restrict__ compact,
+                           const int32_t* __restrict__ compact_count);
 
 }  // namespace bm

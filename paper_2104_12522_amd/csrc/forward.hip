@@ -337,6 +337,7 @@ static int build_plans(const bm_model* models, int n_models, const int32_t* inst
 // 1024 samples), so that the forward kernel's grid can cover a few sample slots per tile
 // instead of every sample. Graph-safe: it writes every entry it later reads.
 constexpr int kCompactSlots = 16;
+constexpr int kCompactSlotsPipe = 4;  // pipelined launches: two workgroups per CU
 __global__ void __launch_bounds__(1024)
     k_active_list(const int32_t* __restrict__ active, int B, int32_t* __restrict__ list) {
     __shared__ int wsum[1024 / kWave];
@@ -494,7 +495,7 @@ static int launch_forward(const HostPlan& hp, int cfg, const double* params, int
         BM_CHECK_HIP(hipGetLastError());
     }
     const int32_t* list_n = compact ? list + B : nullptr;
-    const int slots = compact ? kCompactSlots : 0;
+    const int slots = compact ? (kFwdConfigs[cfg].mode == kModePipelined ? kCompactSlotsPipe : kCompactSlots) : 0;
     for (size_t p = 0; p < hp.plans.size(); ++p) {
         const LaunchPlan& lp = hp.plans[p];
         const int b0 = hp.first_sample[p];
@@ -510,16 +511,23 @@ static int launch_forward(const HostPlan& hp, int cfg, const double* params, int
                 lp1.model[0] = lp.model[lp.seg[0].model];
                 lp1.seg[0].model = 0;
             }
-            const dim3 grid(nb, prep_slices(hp, nb));
+            // a compacted call prepares the records of its requested samples only, in a few
+            // sample slots that take the list's entries in turn
+            const int n_prep = compact ? kCompactSlots : nb;
+            const dim3 grid(n_prep, prep_slices(hp, n_prep));
             const double* pp = params + (size_t)b0 * stride;
             if (single && act)
-                hipLaunchKernelGGL((k_atm_prep<T, true, true>), grid, dim3(kAtmThreads), 0, st, lp1, pp, stride, act, ws, flags + b0);
+                hipLaunchKernelGGL((k_atm_prep<T, true, true>), grid, dim3(kAtmThreads), 0, st, lp1, pp, stride, act, ws,
+                                   flags + b0, list, list_n);
             else if (single)
-                hipLaunchKernelGGL((k_atm_prep<T, true, false>), grid, dim3(kAtmThreads), 0, st, lp1, pp, stride, act, ws, flags + b0);
+                hipLaunchKernelGGL((k_atm_prep<T, true, false>), grid, dim3(kAtmThreads), 0, st, lp1, pp, stride, act, ws,
+                                   flags + b0, nullptr, nullptr);
             else if (act)
-                hipLaunchKernelGGL((k_atm_prep<T, false, true>), grid, dim3(kAtmThreads), 0, st, lp1, pp, stride, act, ws, flags + b0);
+                hipLaunchKernelGGL((k_atm_prep<T, false, true>), grid, dim3(kAtmThreads), 0, st, lp1, pp, stride, act, ws,
+                                   flags + b0, list, list_n);
             else
-                hipLaunchKernelGGL((k_atm_prep<T, false, false>), grid, dim3(kAtmThreads), 0, st, lp1, pp, stride, act, ws, flags + b0);
+                hipLaunchKernelGGL((k_atm_prep<T, false, false>), grid, dim3(kAtmThreads), 0, st, lp1, pp, stride, act, ws,
+                                   flags + b0, nullptr, nullptr);
         }
         BM_CHECK_HIP(hipGetLastError());
         double* c2 = chi2 ? chi2 + b0 : nullptr;

@@ -174,11 +174,16 @@ __global__ void __launch_bounds__(kWaves * kWave)
     // samples, compact_count[0] of them) has compact_slots sample slots per tile, and
     // workgroup (tile, slot k) takes list entries k, k + slots, ... in turn, so that a call
     // that requests few samples launches few workgroups.
+    // A compacted launch orders its workgroups slot-major (all tiles of slot 0, then slot 1,
+    // ...): a call that requests few samples has its working workgroups dispatched first and
+    // the idle slots' workgroups after them, instead of interleaved with them.
     const int slots = kCompact ? compact_slots : sg.count;
     const int g = blockIdx.x - sg.tile_begin;
-    const int kx = g / kXcds;
-    const int tile = (g % kXcds) * sg.tiles_per_xcd + kx / slots;
-    const int slot = kx % slots;
+    const int per_slot = kXcds * sg.tiles_per_xcd;
+    const int gs = kCompact ? g % per_slot : g;
+    const int kx = gs / kXcds;
+    const int tile = (gs % kXcds) * sg.tiles_per_xcd + (kCompact ? kx : kx / slots);
+    const int slot = kCompact ? g / per_slot : kx % slots;
     // The pipelined unmasked-list variant checks its exits (padding workgroup, sample not
     // requested) only after its first record loads are in flight: those loads are in bounds
     // for any workgroup, and the kernel-argument reads behind the checks then overlap them.

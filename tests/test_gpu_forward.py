@@ -580,12 +580,14 @@ def test_tiled_tables_fp64_and_mixed_instances():
     assert torch.equal(res[0][0], res[1][0]) and torch.equal(res[0][1], res[1][1])
 
 
-@pytest.mark.parametrize("n_on", [0, 1, 5, 16, 17, 40])
+@pytest.mark.parametrize("n_on", [0, 1, 3, 4, 5, 9, 16, 17, 40])
 def test_masked_calls_match_unmasked(n_on):
-    # a masked call of one run of samples launches the forward kernel over the list of
-    # requested samples (a few slots per tile; more than 16 requested samples make slots
-    # take several in turn): requested samples get exactly the unmasked call's depth,
-    # channels, chi^2 and flags, the others' outputs are left as they were
+    # a masked call of one run of samples prepares records and launches the forward kernel
+    # over the list of requested samples only, in a few slots that take the list's entries
+    # in turn (16 per tile, 4 with pipelined stages; more requested samples than slots make
+    # slots take several): requested samples get exactly the unmasked call's depth,
+    # channels, chi^2 and flags in every configuration, the others' outputs are left as
+    # they were
     s, sigma, cia = small_config2(n_nu=995, n_layers=70, seed=90)
     nb = s.nu.size // s.bin_width
     data, err = np.full(nb, 0.02), np.full(nb, 6e-5)
@@ -614,4 +616,33 @@ def test_masked_calls_match_unmasked(n_on):
             else:
                 assert bool((f.depth[d] == -7.0).all()) and bool((f.binned[k] == -7.0).all()), (c, b)
                 assert float(f.chi2[b]) == -7.0 and int(f.flags[b]) == -7, (c, b)
+    f.set_config(-1)
+
+
+def test_masked_calls_beyond_the_pipelined_layers():
+    # 150 layers (more than the pipelined and staged modes hold): a masked call with the
+    # batch pinned to streamed chord weights matches the unmasked call
+    s, sigma, cia = small_config2(n_nu=300, n_layers=150, seed=93)
+    nb = s.nu.size // s.bin_width
+    model = gpu_model(s, sigma, cia, data=np.full(nb, 0.02), err=np.full(nb, 6e-5))
+    B = 20
+    params = torch.as_tensor(prior_for(s).draw(B, seed=94), device="cuda")
+    on = np.zeros(B, dtype=np.int32)
+    on[[2, 7, 19]] = 1
+    act = torch.as_tensor(on, device="cuda")
+    f = bm.Forward(model, B, binned=True, chi2=True)
+    names = bm.forward_configs()
+    streamed = [c for c, n in enumerate(names) if "streamed" in n and n.startswith("cached")][0]
+    f.set_config(streamed)
+    f(params)
+    ref = [t.clone() for t in (f.depth, f.chi2)]
+    f.depth.fill_(-7.0)
+    f(params, active=act)
+    torch.cuda.synchronize()
+    for b in range(B):
+        d = slice(int(f.depth_off[b]), int(f.depth_off[b + 1]))
+        if on[b]:
+            assert torch.equal(f.depth[d], ref[0][d]) and torch.equal(f.chi2[b], ref[1][b]), b
+        else:
+            assert bool((f.depth[d] == -7.0).all()), b
     f.set_config(-1)
