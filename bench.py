@@ -40,6 +40,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
+BF16_PEAK_TFLOPS = 2500.0   # dense matrix cores
 
 
 def log(msg):
@@ -513,6 +514,33 @@ def section_mcmc(args, setup, prior):
         f"{rms_prior_post:.2f} ppm, local {rms_local:.2f} ppm")
     del Xl, Yl
 
+    # the surrogate's matrix-core work: one C-chain inference (input scaling, five BF16
+    # products with fused epilogues, chi^2) timed with events; training steps from the
+    # prior surrogate's training wall time
+    xs = post_x[:C].contiguous()
+    sur(xs)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(200):
+        sur(xs)
+    e1.record()
+    torch.cuda.synchronize()
+    us_inf = e0.elapsed_time(e1) / 200 * 1e3
+    macs = sum(dims[i] * dims[i + 1] for i in range(len(dims) - 1))
+    fl_inf = 2.0 * C * macs
+    # a training step: forward (2 B macs), weight gradients (2 B macs) and input gradients
+    # of every layer but the first (2 B macs each)
+    fl_step = 2.0 * 512 * (3 * macs - dims[0] * dims[1])
+    mfma = {"inference_us_per_call": us_inf, "inference_gflop": fl_inf / 1e9,
+            "inference_tflops": fl_inf / (us_inf * 1e-6) / 1e12,
+            "train_step_us": t_train / max(net.step, 1) * 1e6, "train_step_gflop": fl_step / 1e9,
+            "train_tflops": fl_step * net.step / t_train / 1e12, "peak_tflops": BF16_PEAK_TFLOPS}
+    mfma["inference_frac"] = mfma["inference_tflops"] / BF16_PEAK_TFLOPS
+    mfma["train_frac"] = mfma["train_tflops"] / BF16_PEAK_TFLOPS
+    log(f"mcmc: surrogate inference {us_inf:.1f} us per {C}-chain call ({mfma['inference_tflops']:.1f} "
+        f"TFLOP/s), training {mfma['train_tflops']:.1f} TFLOP/s (BF16 peak {BF16_PEAK_TFLOPS:.0f})")
+
     # 3b. longer burn-in with delayed acceptance (exact, and cheap), then the local
     #     surrogate is refit to the wider set of states
     if args.da_burn > 0:
@@ -600,7 +628,10 @@ def section_mcmc(args, setup, prior):
     log(f"mcmc: delayed-acceptance production, {G_da} generations")
     _, h_d, w_d, acc_d = production(surrogate=sur, n_gen=G_da, stream=71)
     da, mu_d, sd_d, tau_d = stats(h_d, w_d, acc_d, G_da, stage1_pass_rate=float(acc_d[0]))
+    # the same run over its first G generations: equal length and start as the plain runs
+    mu_d_g = h_d[:G].reshape(-1, d).mean(0).cpu().numpy()
     del h_d
+    mu_start = x0.mean(0).cpu().numpy()
     log(f"mcmc: plain per-sample, {args.per_sample_gens} generations timed")
     _, h_p, w_p, _ = production(per_sample=1, n_gen=args.per_sample_gens)
     identical = bool(torch.equal(h_p, h_b[:args.per_sample_gens]))
@@ -623,6 +654,7 @@ def section_mcmc(args, setup, prior):
     diff = (mu_d - mu_plain) / sd_ref
     diff_se = np.sqrt(se_plain ** 2 + se(tau_d, G_da) ** 2) / sd_ref
     diff_pp = (mu_q - mu_b2) / sd_ref
+    diff_eq = (mu_d_g - mu_plain) / sd_ref
     diff_pp_se = np.sqrt(se(tau_b, G) ** 2 + se(tau_q, G) ** 2) / sd_ref
     ratio = da["ess_per_s"] / plain_ps["ess_per_s"]
     ratio_mc = da["ess_multichain_per_s"] / plain_ps["ess_multichain_per_s"]
@@ -631,14 +663,14 @@ def section_mcmc(args, setup, prior):
     log(f"mcmc: ESS/s per-sample {plain_ps['ess_per_s']:.2f}, batched {plain_b['ess_per_s']:.2f}, "
         f"delayed acceptance {da['ess_per_s']:.2f} -> {ratio:.1f}x (multi-chain ESS: {ratio_mc:.1f}x); "
         f"max |mean diff| delayed acceptance vs plain {np.abs(diff).max():.3f} sd "
-        f"(plain vs plain {np.abs(diff_pp).max():.3f} sd)")
+        f"(first {G} generations {np.abs(diff_eq).max():.3f} sd; plain vs plain {np.abs(diff_pp).max():.3f} sd)")
     return {
         "chains": C, "burn_in": BURN, "da_burn_in": args.da_burn, "truth": truth.tolist(),
         "prior": {"lo": prior.lo.tolist(), "hi": prior.hi.tolist()},
         "surrogate": {"dims": dims, "dtype": "bf16 weights/activations, fp32 accumulate",
                       "train_spectra": args.train_spectra, "epochs": args.epochs,
                       "data_s": t_data, "train_s": t_train, "adam_steps": net.step,
-                      "rms_ppm_prior_heldout": rms_prior,
+                      "rms_ppm_prior_heldout": rms_prior, "matrix_cores": mfma,
                       "rms_ppm_near_posterior": rms_prior_post,
                       "local": {"train_spectra": args.local_spectra, "s": t_local,
                                 "rms_ppm_near_posterior": rms_local,
@@ -659,13 +691,70 @@ def section_mcmc(args, setup, prior):
             "plain_vs_plain_diff_sd": diff_pp.tolist(),
             "max_abs_plain_vs_plain_diff_sd": float(np.abs(diff_pp).max()),
             "plain_vs_plain_standard_error_sd": diff_pp_se.tolist(),
+            "equal_length_diff_sd_vs_plain": diff_eq.tolist(),
+            "max_abs_equal_length_diff_sd_vs_plain": float(np.abs(diff_eq).max()),
+            "start_ensemble_diff_sd": {"plain": ((mu_plain - mu_start) / sd_ref).tolist(),
+                                       "delayed_acceptance": ((mu_d - mu_start) / sd_ref).tolist()},
             "note": "delayed acceptance against the mean of the two plain runs; standard errors "
                     "sd sqrt(tau / (generations x chains)) from each run's multi-chain integrated "
-                    "time"},
+                    "time; equal_length: the delayed-acceptance run's first generations (as many as "
+                    "each plain run), from the same start; start_ensemble: each mean against the "
+                    "mean of the common starting states"},
         "marginal_mean": {"plain": mu_b2.tolist(), "plain_replicate": mu_q.tolist(),
                           "delayed_acceptance": mu_d.tolist()},
         "marginal_sd": {"plain": sd_b2.tolist(), "delayed_acceptance": sd_d.tolist()},
     }
+
+
+def section_mlp(args):
+    """The surrogate network's kernels alone (10 -> 4 x 512 -> 1000, BF16 on the matrix cores):
+    a 256-row inference and training steps at batch 512 on synthetic inputs and targets,
+    timed with events; throughput against the dense BF16 peak."""
+    import torch
+    from paper_2104_12522_amd.surrogate import MLP, Trainer
+    dims = [10, 512, 512, 512, 512, 1000]
+    C, batch, n = args.chains, 512, 20480
+    g = torch.Generator(device="cuda").manual_seed(args.seed + 95)
+    X = torch.rand(n, dims[0], generator=g, device="cuda", dtype=torch.float64)
+    Y = torch.randn(n, dims[-1], generator=g, device="cuda", dtype=torch.float64)
+    lo = torch.zeros(dims[0], dtype=torch.float64, device="cuda")
+    hi = torch.ones(dims[0], dtype=torch.float64, device="cuda")
+    mean = torch.zeros(dims[-1], dtype=torch.float64, device="cuda")
+    scale = torch.ones(dims[-1], dtype=torch.float64, device="cuda")
+    net = MLP(dims, max_batch=max(C, batch), seed=11)
+    out = torch.empty(C, dims[-1], dtype=torch.float32, device="cuda")
+    xs = X[:C].contiguous()
+
+    def infer():
+        net.set_input(xs, lo, hi)
+        net.forward(C, out)
+
+    tr = Trainer(net, lo, hi, X, Y, mean, scale, batch=batch, seed=12)
+    rows = torch.arange(batch, dtype=torch.int32, device="cuda")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    res = {}
+    for name, fn, reps in (("inference", infer, 500), ("train_step", lambda: tr.step(rows, 1e-4), 300)):
+        for _ in range(20):
+            fn()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        res[name + "_us"] = e0.elapsed_time(e1) / reps * 1e3
+    macs = sum(dims[i] * dims[i + 1] for i in range(len(dims) - 1))
+    fl_inf = 2.0 * C * macs
+    fl_step = 2.0 * batch * (3 * macs - dims[0] * dims[1])
+    res.update({"dims": dims, "inference_rows": C, "train_batch": batch,
+                "inference_tflops": fl_inf / (res["inference_us"] * 1e-6) / 1e12,
+                "train_tflops": fl_step / (res["train_step_us"] * 1e-6) / 1e12,
+                "peak_tflops": BF16_PEAK_TFLOPS})
+    res["inference_frac"] = res["inference_tflops"] / BF16_PEAK_TFLOPS
+    res["train_frac"] = res["train_tflops"] / BF16_PEAK_TFLOPS
+    log(f"surrogate kernels: inference {res['inference_us']:.1f} us ({res['inference_tflops']:.1f} TFLOP/s), "
+        f"training step {res['train_step_us']:.1f} us ({res['train_tflops']:.1f} TFLOP/s)")
+    return res
 
 
 def section_opacity(args):
@@ -919,7 +1008,7 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--table", choices=("opacity", "random"), default="opacity")
-    ap.add_argument("--sections", default="forward,fp64,batched,mcmc,opacity",
+    ap.add_argument("--sections", default="forward,fp64,batched,mlp,mcmc,opacity",
                     help="comma list of forward, batched, mcmc, opacity, copy")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -998,6 +1087,8 @@ def main():
         out["fp64_single_spectrum"] = section_fp64(args)
     if "batched" in sections:
         out["batched"] = section_batched(args, setup, model, prior)
+    if "mlp" in sections:
+        out["surrogate_kernels"] = section_mlp(args)
     if "mcmc" in sections:
         # the retrieval labels the two visible streams (alpha <= 1/2), so that the
         # posterior has no mirror mode in (gamma1, gamma2, alpha)

@@ -134,8 +134,11 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
     constexpr int WM = BM / 2, WN = BN / 2;          // wave tile
     constexpr int TI = WM / 16, TJ = WN / 16;        // MFMA tiles per wave
     static_assert(TK % 32 == 0, "k slices of whole MFMA steps");
-    __shared__ __align__(16) uint16_t As[2][BM][TK + kPad];
-    __shared__ __align__(16) uint16_t Bs[2][BN][TK + kPad];
+    // slices of 512 or more hold the whole of k (one load round trip, launched only when
+    // K <= TK) and need no second buffer
+    constexpr int kBuf = TK >= 512 ? 1 : 2;
+    __shared__ __align__(16) uint16_t As[kBuf][BM][TK + kPad];
+    __shared__ __align__(16) uint16_t Bs[kBuf][BN][TK + kPad];
     const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = (wave >> 1) * WM, wn = (wave & 1) * WN;
@@ -153,8 +156,8 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
     cb.store(Bs[0], g.trans_b, tid);
     __syncthreads();
     for (int kt = 0; kt < nk; ++kt) {
-        const int cur = kt & 1;
-        if (kt + 1 < nk) {
+        const int cur = kt & (kBuf - 1);
+        if (kBuf == 2 && kt + 1 < nk) {
             ca.load(g.A, g.lda, g.trans_a, g.vec_a, g.M, g.K, m0, (kt + 1) * TK, tid);
             cb.load(g.B, g.ldb, g.trans_b, g.vec_b, g.N, g.K, n0, (kt + 1) * TK, tid);
         }
@@ -175,9 +178,9 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
                 for (int j = 0; j < TJ; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
         }
-        if (kt + 1 < nk) {
-            ca.store(As[cur ^ 1], g.trans_a, tid);
-            cb.store(Bs[cur ^ 1], g.trans_b, tid);
+        if (kBuf == 2 && kt + 1 < nk) {
+            ca.store(As[cur ^ (kBuf - 1)], g.trans_a, tid);
+            cb.store(Bs[cur ^ (kBuf - 1)], g.trans_b, tid);
         }
         __syncthreads();
     }
@@ -328,9 +331,12 @@ static int launch_gemm(GemmArgs a, hipStream_t st) {
         dim3 grid((a.N + 63) / 64, (a.M + 63) / 64);
         hipLaunchKernelGGL((k_gemm_bf16<64, 64, 32>), grid, dim3(256), 0, st, a);
     } else {
-        // small products: few workgroups, so each takes 128-deep k slices (fewer round trips)
+        // small products: few workgroups, so each takes deep k slices (fewer round trips):
+        // the whole of k at once up to 512, else 128-deep slices
         dim3 grid((a.N + 31) / 32, (a.M + 31) / 32);
-        if (a.K > 64)
+        if (a.K > 128 && a.K <= 512)
+            hipLaunchKernelGGL((k_gemm_bf16<32, 32, 512>), grid, dim3(256), 0, st, a);
+        else if (a.K > 64)
             hipLaunchKernelGGL((k_gemm_bf16<32, 32, 128>), grid, dim3(256), 0, st, a);
         else
             hipLaunchKernelGGL((k_gemm_bf16<32, 32, 32>), grid, dim3(256), 0, st, a);

@@ -46,7 +46,7 @@ def _bound(a, b):
 
 
 @pytest.mark.parametrize("ta,tb", [(0, 0), (1, 0), (0, 1), (1, 1)])
-@pytest.mark.parametrize("M,N,K", [(70, 130, 45), (1, 1, 1), (128, 64, 96), (33, 1000, 512),
+@pytest.mark.parametrize("M,N,K", [(70, 130, 45), (1, 1, 1), (128, 64, 96), (33, 1000, 512), (40, 200, 300),
                                    (1024, 1040, 72), (1030, 1030, 45)])
 def test_gemm_store_all_layouts(M, N, K, ta, tb):
     g = np.random.default_rng(M * 7 + N + K + 10 * ta + 20 * tb)
