@@ -731,9 +731,16 @@ def section_mlp(args):
 
     tr = Trainer(net, lo, hi, X, Y, mean, scale, batch=batch, seed=12)
     rows = torch.arange(batch, dtype=torch.int32, device="cuda")
+    # the same network at larger training batches (throughput grows with the product sizes:
+    # the batch-512 products are latency-bound)
+    big = MLP(dims, max_batch=4096, seed=13)
+    tr_big = {b: Trainer(big, lo, hi, X, Y, mean, scale, batch=b, seed=14) for b in (2048, 4096)}
+    rows_big = {b: torch.arange(b, dtype=torch.int32, device="cuda") for b in (2048, 4096)}
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     res = {}
-    for name, fn, reps in (("inference", infer, 500), ("train_step", lambda: tr.step(rows, 1e-4), 300)):
+    for name, fn, reps in (("inference", infer, 500), ("train_step", lambda: tr.step(rows, 1e-4), 300),
+                           ("train_step_2048", lambda: tr_big[2048].step(rows_big[2048], 1e-5), 100),
+                           ("train_step_4096", lambda: tr_big[4096].step(rows_big[4096], 1e-5), 100)):
         for _ in range(20):
             fn()
         torch.cuda.synchronize()
@@ -752,8 +759,11 @@ def section_mlp(args):
                 "peak_tflops": BF16_PEAK_TFLOPS})
     res["inference_frac"] = res["inference_tflops"] / BF16_PEAK_TFLOPS
     res["train_frac"] = res["train_tflops"] / BF16_PEAK_TFLOPS
+    for b in (2048, 4096):
+        res[f"train_tflops_{b}"] = fl_step * b / batch / (res[f"train_step_{b}_us"] * 1e-6) / 1e12
     log(f"surrogate kernels: inference {res['inference_us']:.1f} us ({res['inference_tflops']:.1f} TFLOP/s), "
-        f"training step {res['train_step_us']:.1f} us ({res['train_tflops']:.1f} TFLOP/s)")
+        f"training step {res['train_step_us']:.1f} us ({res['train_tflops']:.1f} TFLOP/s; batch 2048 "
+        f"{res['train_tflops_2048']:.1f}, 4096 {res['train_tflops_4096']:.1f} TFLOP/s)")
     return res
 
 

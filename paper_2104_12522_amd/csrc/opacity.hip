@@ -151,6 +151,14 @@ __device__ inline void line_range(const LineArrays& ln, double lo_v, double hi_v
     range[1] = a;
 }
 
+// Re w at the table's precision: single-precision tables take the single-precision far-wing
+// evaluation (each term then carries a relative rounding of ~1e-6, the sum stays in double)
+template <typename T>
+__device__ __forceinline__ double faddeeva_t(double x, double y, const WeidemanCoef& wc) {
+    if constexpr (sizeof(T) == 4) return faddeeva_re_f32wings(x, y, wc);
+    return faddeeva_re(x, y, wc);
+}
+
 // Lines staged in LDS: centre, window half-width, S(T) / (sigma sqrt(2 pi)), 1 / (sigma sqrt 2)
 // and the Faddeeva argument's imaginary part y = gamma / (sigma sqrt 2).
 struct StagedLines {
@@ -207,7 +215,7 @@ __global__ void __launch_bounds__(kOpThreads)
         if (k < n_nu) {
             for (int q = 0; q < cnt; ++q) {
                 const double d = nu - sl.nu0[q];
-                if (fabs(d) <= sl.half[q]) acc += sl.amp[q] * faddeeva_re(d * sl.inv[q], sl.y[q], wc);
+                if (fabs(d) <= sl.half[q]) acc += sl.amp[q] * faddeeva_t<T>(d * sl.inv[q], sl.y[q], wc);
             }
         }
         __syncthreads();
@@ -278,7 +286,7 @@ __global__ void __launch_bounds__(kOpThreads)
                 for (int j = r; j < n; j += 4) {
                     const double d = (nu_start + dnu * (double)(ka + j)) - nu0;
                     if (fabs(d) <= half) {
-                        s_f[ql][j] = (FVal)faddeeva_re(d * sl.inv[q], sl.y[q], wc);
+                        s_f[ql][j] = (FVal)faddeeva_t<T>(d * sl.inv[q], sl.y[q], wc);
                         mask |= 1ull << j;
                     }
                 }

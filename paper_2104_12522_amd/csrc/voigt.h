@@ -106,6 +106,40 @@ __device__ __forceinline__ double faddeeva_re(double x, double y, const Weideman
     return tr * ir - ti * ii;
 }
 
+// Re w(x + i y) far from the origin in single precision, for single-precision tables: the
+// same N-level truncation of the Laplace continued fraction, evaluated from the innermost
+// level outwards, t = z, t <- z - (k/2)/t for k = N .. 1, w = (i / sqrt(pi)) / t, so
+// Re w = Im t / (sqrt(pi) |t|^2). Every quantity stays of the order of |z| (no convergent
+// growth, so no overflow at any |z|); each level is one reciprocal and four fused
+// multiply-adds, with a relative rounding of a few units of the last place.
+template <int N>
+__device__ __forceinline__ float faddeeva_re_cf_f32(float x, float y) {
+    float tr = x, ti = y;
+#pragma unroll
+    for (int k = N; k >= 1; --k) {
+        const float c = (0.5f * (float)k) * __builtin_amdgcn_rcpf(fmaf(tr, tr, ti * ti));
+        tr = fmaf(-c, tr, x);
+        ti = fmaf(c, ti, y);
+    }
+    return ti * __builtin_amdgcn_rcpf(fmaf(tr, tr, ti * ti)) * 0.56418958f;  // 1/sqrt(pi)
+}
+
+// Re w for single-precision tables: the continued fraction in single precision where
+// |z| >= 8 (every point of pressure-broadened lines' windows), Weideman's expansion in
+// double inside |z| < 8 (line cores, where its terms cancel)
+__device__ __forceinline__ double faddeeva_re_f32wings(double x, double y, const WeidemanCoef& wc) {
+    x = fabs(x);
+    const double r2 = x * x + y * y;
+    if (r2 >= 64.0) {
+        const float xf = (float)x, yf = (float)y;
+        if (!__ballot(r2 < 1600.0)) return faddeeva_re_cf_f32<4>(xf, yf);
+        if (__ballot(r2 < 100.0)) return faddeeva_re_cf_f32<10>(xf, yf);
+        if (__ballot(r2 < 225.0)) return faddeeva_re_cf_f32<8>(xf, yf);
+        return faddeeva_re_cf_f32<6>(xf, yf);
+    }
+    return faddeeva_re(x, y, wc);
+}
+
 __device__ __forceinline__ double voigt_hwhm(double sig, double gam) {
     return 0.5346 * gam + sqrt(0.2166 * gam * gam + 2.0 * 0.69314718055994530942 * sig * sig);
 }
