@@ -232,14 +232,21 @@ __global__ void __launch_bounds__(kWaves * kWave)
             flags = rec.hdr->flags;
             jcl = m.cloud ? rec.hdr->jcloud : -1;
         }
-        // this tile's channels (phase 3); the pipelined path fetches their data and errors
-        // with its first loads, so that phase 3 does not wait on memory
-        const int bw = m.bin_width;
-        const int nbt = bw > 0 ? sg.tile_w / bw : 0;  // whole channels per tile
-        const int nbins = bw > 0 ? Nnu / bw : 0;
-        const bool want_chi2 = (chi2 != nullptr) && m.data && m.err;
-        const int cg = tile * nbt + lane;
-        const bool own_bin = binned != nullptr && sg.fused_bins && lane < nbt && cg < nbins;
+        // this tile's channels (phase 3). The pipelined path works them out and fetches their
+        // data and errors with its first loads, so that phase 3 does not wait on memory; the
+        // other paths do it in phase 3 (their workgroups are short, and the scalar waits and
+        // divisions in the prologue cost them up to 15 % at 256 samples per launch)
+        int bw = 0, nbt = 0, nbins = 0, cg = 0;
+        bool want_chi2 = false, own_bin = false;
+        auto channels = [&]() {
+            bw = m.bin_width;
+            nbt = bw > 0 ? sg.tile_w / bw : 0;  // whole channels per tile
+            nbins = bw > 0 ? Nnu / bw : 0;
+            want_chi2 = (chi2 != nullptr) && m.data && m.err;
+            cg = tile * nbt + lane;
+            own_bin = binned != nullptr && sg.fused_bins && lane < nbt && cg < nbins;
+        };
+        if constexpr (kPipe) channels();
         double ch_data = 0.0, ch_err = 1.0;
         // this lane's H2 Rayleigh cross section (the record holds n_H2 per layer); zero without
         // Rayleigh scattering, so that the per-layer term needs no branch (a branch in the
@@ -649,6 +656,7 @@ __global__ void __launch_bounds__(kWaves * kWave)
         // ---- phase 3: channels of this tile; chi^2 partial; last tile sums the partials ----
         if (binned == nullptr || !sg.fused_bins) return;
         __syncthreads();
+        if constexpr (!kPipe) channels();
         double* bout = binned + sg.bin_off + (size_t)s_in * nbins;
         if (wave == 0) {
             double term = 0.0;
