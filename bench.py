@@ -1038,9 +1038,9 @@ def main():
     ap.add_argument("--da-gens", type=int, default=150000,
                     help="generations of the delayed-acceptance production run")
     ap.add_argument("--mcmc-burn", type=int, default=1000)
-    ap.add_argument("--da-burn", type=int, default=50000,
+    ap.add_argument("--da-burn", type=int, default=100000,
                     help="further burn-in generations with delayed acceptance before production "
-                         "(about twice the slowest integrated time of this posterior)")
+                         "(two to three times the slowest integrated time of this posterior)")
     ap.add_argument("--per-sample-gens", type=int, default=200)
     ap.add_argument("--train-spectra", type=int, default=200000)
     ap.add_argument("--surrogate-box", type=float, default=5.0,
