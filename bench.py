@@ -32,6 +32,8 @@ import os
 import sys
 import time
 
+T_START = time.time()
+
 import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -581,6 +583,16 @@ def section_mcmc(args, setup, prior):
     #    batched runs (the second is the plain sampler's own run-to-run yardstick) and a
     #    longer delayed-acceptance run
     G_da = args.da_gens
+    # the two plain runs are shortened (to whole thousands of generations) when the rates
+    # measured in burn-in say that the whole run would not fit its time budget
+    s_gen = t_burn / BURN
+    s_gen_da = t_db / args.da_burn if args.da_burn > 0 else 0.3e-3
+    reserve = 30.0 + 1.2 * G_da * s_gen_da + (45.0 if "opacity" in args._sections else 0.0)
+    left = args.time_budget - (time.time() - args._t0) - reserve
+    G_asked = G
+    if 2 * G * s_gen > left:
+        G = max(5000, int(left / (2 * s_gen)) // 1000 * 1000)
+        log(f"mcmc: plain runs shortened to {G} generations ({left:.0f} s of the time budget left)")
     def production(surrogate=None, per_sample=0, n_gen=G, stream=70):
         r = Retrieval(model, C, prior.lo, prior.hi, seed=args.seed + stream, thin=10, hist_cap=n_gen,
                       surrogate=surrogate, per_sample_workers=per_sample,
@@ -666,6 +678,7 @@ def section_mcmc(args, setup, prior):
         f"(first {G} generations {np.abs(diff_eq).max():.3f} sd; plain vs plain {np.abs(diff_pp).max():.3f} sd)")
     return {
         "chains": C, "burn_in": BURN, "da_burn_in": args.da_burn, "truth": truth.tolist(),
+        "plain_generations_asked": G_asked, "time_budget_s": args.time_budget,
         "prior": {"lo": prior.lo.tolist(), "hi": prior.hi.tolist()},
         "surrogate": {"dims": dims, "dtype": "bf16 weights/activations, fp32 accumulate",
                       "train_spectra": args.train_spectra, "epochs": args.epochs,
@@ -1048,7 +1061,12 @@ def main():
     ap.add_argument("--local-spectra", type=int, default=100000)
     ap.add_argument("--epochs", type=int, default=30)
     ap.add_argument("--opacity-lines", type=int, default=10_000_000)
+    ap.add_argument("--time-budget", type=float, default=540.0,
+                    help="seconds the whole run may take: the sampler section shortens its two "
+                         "plain production runs when its measured generation rate says they "
+                         "would not fit")
     args = ap.parse_args()
+    args._t0 = T_START
     if args.oracle_pool:
         oracle_pool_main(args.oracle_pool, args.cpu_seconds, args.cpu_workers)
         return
@@ -1058,6 +1076,7 @@ def main():
                                    "by wavenumber range)", "n_gpus": args.gpus}))
         sys.exit(2)
     sections = [s.strip() for s in args.sections.split(",") if s.strip()]
+    args._sections = sections
 
     import torch
     import workloads as wl
