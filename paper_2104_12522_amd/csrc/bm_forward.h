@@ -87,6 +87,8 @@ struct LaunchPlan {
     int n_seg;
     int total_wgs;
     int max_ntc;   // largest CIA temperature grid among the models (LDS staging rows)
+    int prio_from; // pipelined launches: first workgroup of the second dispatch round, when the
+                   // launch has at most two rounds (set at launch; else no workgroup qualifies)
     __device__ int segment_of_sample(int b) const {
         int s = 0;
         for (int i = 1; i < n_seg; ++i)
@@ -196,6 +198,8 @@ __host__ __device__ inline size_t record_bytes_t(int S, int L, int tiles) {
 // host helpers (forward.hip)
 int validate_model(const bm_model& m, bool need_tables);
 ModelDev to_device_view(const bm_model& m);
+// compute units of the current device (cached per device; 0 if unknown)
+int device_cu_count();
 // raise a kernel's dynamic-LDS ceiling (once per kernel, device and size)
 int ensure_dynamic_lds(const void* fn, size_t bytes);
 

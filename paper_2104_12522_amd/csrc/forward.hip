@@ -4,6 +4,7 @@
 #include "fwd_kernel.h"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <map>
 #include <mutex>
@@ -283,6 +284,7 @@ static int build_plans(const bm_model* models, int n_models, const int32_t* inst
     int b = 0;
     while (b < B) {
         LaunchPlan lp{};
+        lp.prio_from = INT_MAX;  // set per launch
         for (int i = 0; i < n_models; ++i) lp.model[i] = to_device_view(models[i]);
         int first_of_plan = b;
         int tiles = 0;
@@ -423,6 +425,20 @@ static size_t device_lds_limit() {
         cached[dev] = v;
     }
     return (size_t)cached[dev];
+}
+
+// Compute units of the current device, queried once per device (0 if the query fails: the
+// fused kernel then skips its dispatch-round heuristics).
+int device_cu_count() {
+    static std::atomic<int> cached[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+    int v = cached[dev].load(std::memory_order_relaxed);
+    if (v == 0) {
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = -1;
+        cached[dev].store(v, std::memory_order_relaxed);
+    }
+    return v > 0 ? v : 0;
 }
 
 // Raise a kernel's dynamic-LDS ceiling once per device (hipFuncSetAttribute is host work

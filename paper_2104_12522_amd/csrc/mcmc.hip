@@ -64,10 +64,14 @@ __device__ inline double normal_draw(uint64_t seed, int64_t g, int c, int C, int
 }
 
 // counters: [0] generation, [1] archive size
+// One thread per (chain, parameter): the DE move's components, each with its own normal draw,
+// in parallel; the snooker move (sums over the parameters) by each chain's parameter-0
+// thread. Every element is computed with the same operations either way.
 __global__ void k_demcz_propose(bm_demcz s, double gamma_de) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= s.n_chains) return;
     const int d = s.n_params;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = t / d, p = t - c * d;
+    if (c >= s.n_chains) return;
     const int64_t g = s.counters[0];
     const int M = s.counters[1];
     // two distinct archive members
@@ -81,17 +85,16 @@ __global__ void k_demcz_propose(bm_demcz s, double gamma_de) {
     const bool snooker = s.p_snooker > 0.0 && M >= 3 && u01(s.seed, counter(g, c, s.n_chains, kSlotMove)) < s.p_snooker;
     if (!snooker) {
         const double gamma = (g % 10 == 9) ? 1.0 : gamma_de;
-        for (int p = 0; p < d; ++p) {
-            const double width = s.hi[p] - s.lo[p];
-            // written operation by operation; contraction is off in this file
-            const double e = (s.eps_scale * width) * normal_draw(s.seed, g, c, s.n_chains, p);
-            const double diff = s.z[(size_t)r1 * d + p] - s.z[(size_t)r2 * d + p];
-            const double step = gamma * diff;
-            y[p] = (x[p] + step) + e;
-        }
-        if (s.log_q) s.log_q[c] = 0.0;
+        const double width = s.hi[p] - s.lo[p];
+        // written operation by operation; contraction is off in this file
+        const double e = (s.eps_scale * width) * normal_draw(s.seed, g, c, s.n_chains, p);
+        const double diff = s.z[(size_t)r1 * d + p] - s.z[(size_t)r2 * d + p];
+        const double step = gamma * diff;
+        y[p] = (x[p] + step) + e;
+        if (p == 0 && s.log_q) s.log_q[c] = 0.0;
         return;
     }
+    if (p != 0) return;
     // snooker: a third row, uniform over the M - 2 rows other than r1 and r2
     int rz = (int)(u01(s.seed, counter(g, c, s.n_chains, kSlotZ)) * (M - 2));
     if (rz >= M - 2) rz = M - 3;
@@ -102,24 +105,24 @@ __global__ void k_demcz_propose(bm_demcz s, double gamma_de) {
     const double* z1 = s.z + (size_t)r1 * d;
     const double* z2 = s.z + (size_t)r2 * d;
     double nn = 0.0, dot = 0.0;
-    for (int p = 0; p < d; ++p) {
-        const double e = x[p] - zz[p];
+    for (int q = 0; q < d; ++q) {
+        const double e = x[q] - zz[q];
         nn = nn + e * e;
-        dot = dot + (z1[p] - z2[p]) * e;
+        dot = dot + (z1[q] - z2[q]) * e;
     }
     double lq = -INFINITY;  // x on z: no line, no move
     if (nn > 0.0) {
         const double gamma_s = 1.2 + u01(s.seed, counter(g, c, s.n_chains, kSlotGammaS));
         const double coef = gamma_s * (dot / nn);
         double n2 = 0.0;
-        for (int p = 0; p < d; ++p) {
-            y[p] = x[p] + coef * (x[p] - zz[p]);
-            const double f = y[p] - zz[p];
+        for (int q = 0; q < d; ++q) {
+            y[q] = x[q] + coef * (x[q] - zz[q]);
+            const double f = y[q] - zz[q];
             n2 = n2 + f * f;
         }
         if (n2 > 0.0) lq = (0.5 * (d - 1)) * (log(n2) - log(nn));
     } else {
-        for (int p = 0; p < d; ++p) y[p] = x[p];
+        for (int q = 0; q < d; ++q) y[q] = x[q];
     }
     s.log_q[c] = lq;
 }
@@ -281,8 +284,9 @@ extern "C" int bm_demcz_propose(const bm_demcz* s, void* stream) {
     // gamma = gamma_scale (2.38 / sqrt(2 d)) (correctly rounded host arithmetic)
     const double scale = s->gamma_scale > 0.0 ? s->gamma_scale : 1.0;
     const double gamma_de = scale * (2.38 / std::sqrt(2.0 * s->n_params));
-    hipLaunchKernelGGL(k_demcz_propose, dim3((s->n_chains + 255) / 256), dim3(256), 0, (hipStream_t)stream, *s,
-                       gamma_de);
+    const int64_t n_threads = (int64_t)s->n_chains * s->n_params;
+    hipLaunchKernelGGL(k_demcz_propose, dim3((unsigned)((n_threads + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+                       *s, gamma_de);
     BM_CHECK_HIP(hipGetLastError());
     return BM_OK;
 }
