@@ -184,7 +184,11 @@ def section_forward(args, setup, model, prior):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = start.elapsed_time(end) / args.steps
-    # the fused kernel alone: the same calls again, each kernel launch between two events
+    # the fused kernel alone: the same calls again, each kernel launch between two events,
+    # after a run-in of untimed calls that keeps the GPU busy while the host sets up the
+    # events (so that a short pass is not timed from an idle GPU)
+    for i in range(max(args.warmup, 100)):
+        f(rows[i % n_draw])
     with bm.KernelTiming(args.steps) as kt:
         for i in range(args.steps):
             f(rows[args.warmup + i])
