@@ -256,8 +256,8 @@ __device__ inline double chord_weight(const double* r, int L, int j, int l) {
 template <typename T, bool kSingle, bool kMasked>
 __global__ void __launch_bounds__(kAtmThreads)
     k_atm_prep(LaunchPlan plan, const double* __restrict__ params, int stride, const int32_t* __restrict__ active,
-               char* __restrict__ ws, int32_t* __restrict__ flags_out, const int32_t* __restrict__ compact,
-               const int32_t* __restrict__ compact_count) {
+               char* __restrict__ ws, int32_t* __restrict__ flags_out, int32_t* __restrict__ compact,
+               const int32_t* __restrict__ compact_count, int build_n) {
     __shared__ AtmShared sh;
   auto one = [&](const int b) {
     const int slice = blockIdx.y, n_slices = gridDim.y;
@@ -362,6 +362,49 @@ __global__ void __launch_bounds__(kAtmThreads)
     }
   };
     if constexpr (kMasked) {
+        if (compact && build_n > 0) {
+            // the list of requested samples (ascending), built by every workgroup from the
+            // B flags; the first workgroup also writes it, with its length after the B
+            // entries, for the fused kernel
+            __shared__ int32_t lst[kPrepListMax];
+            __shared__ int tsum[kAtmThreads / kWave];
+            constexpr int kPer = kPrepListMax / kAtmThreads;
+            int mine[kPer], c = 0;
+#pragma unroll
+            for (int j = 0; j < kPer; ++j) {
+                const int b = threadIdx.x * kPer + j;
+                mine[j] = (b < build_n && active[b] != 0) ? b : -1;
+                c += mine[j] >= 0;
+            }
+            // exclusive prefix of the counts over the threads: a scan within each wave, then
+            // the totals of the waves before
+            const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+            int incl = c;
+#pragma unroll
+            for (int o = 1; o < kWave; o <<= 1) {
+                const int v = __shfl_up(incl, o, kWave);
+                if (lane >= o) incl += v;
+            }
+            if (lane == kWave - 1) tsum[w] = incl;
+            __syncthreads();
+            int off = incl - c;
+            for (int q = 0; q < w; ++q) off += tsum[q];
+#pragma unroll
+            for (int j = 0; j < kPer; ++j)
+                if (mine[j] >= 0) lst[off++] = mine[j];
+            int n_items = 0;
+            for (int q = 0; q < kAtmThreads / kWave; ++q) n_items += tsum[q];
+            __syncthreads();
+            if (blockIdx.x == 0 && blockIdx.y == 0) {
+                for (int q = threadIdx.x; q < n_items; q += kAtmThreads) compact[q] = lst[q];
+                if (threadIdx.x == 0) compact[build_n] = n_items;
+            }
+            for (int q = blockIdx.x; q < n_items; q += gridDim.x) {
+                if (q != (int)blockIdx.x) __syncthreads();  // the previous sample's shared reads are done
+                one(lst[q]);
+            }
+            return;
+        }
         if (compact) {
             const int n_items = *compact_count;
             for (int q = blockIdx.x; q < n_items; q += gridDim.x) {
@@ -376,21 +419,21 @@ __global__ void __launch_bounds__(kAtmThreads)
 }
 
 template __global__ void k_atm_prep<float, true, true>(LaunchPlan, const double*, int, const int32_t*, char*, int32_t*,
-                                                      const int32_t*, const int32_t*);
+                                                      int32_t*, const int32_t*, int);
 template __global__ void k_atm_prep<float, true, false>(LaunchPlan, const double*, int, const int32_t*, char*, int32_t*,
-                                                      const int32_t*, const int32_t*);
+                                                      int32_t*, const int32_t*, int);
 template __global__ void k_atm_prep<float, false, true>(LaunchPlan, const double*, int, const int32_t*, char*, int32_t*,
-                                                      const int32_t*, const int32_t*);
+                                                      int32_t*, const int32_t*, int);
 template __global__ void k_atm_prep<float, false, false>(LaunchPlan, const double*, int, const int32_t*, char*, int32_t*,
-                                                      const int32_t*, const int32_t*);
+                                                      int32_t*, const int32_t*, int);
 template __global__ void k_atm_prep<double, true, true>(LaunchPlan, const double*, int, const int32_t*, char*, int32_t*,
-                                                      const int32_t*, const int32_t*);
+                                                      int32_t*, const int32_t*, int);
 template __global__ void k_atm_prep<double, true, false>(LaunchPlan, const double*, int, const int32_t*, char*, int32_t*,
-                                                      const int32_t*, const int32_t*);
+                                                      int32_t*, const int32_t*, int);
 template __global__ void k_atm_prep<double, false, true>(LaunchPlan, const double*, int, const int32_t*, char*, int32_t*,
-                                                      const int32_t*, const int32_t*);
+                                                      int32_t*, const int32_t*, int);
 template __global__ void k_atm_prep<double, false, false>(LaunchPlan, const double*, int, const int32_t*, char*, int32_t*,
-                                                      const int32_t*, const int32_t*);
+                                                      int32_t*, const int32_t*, int);
 
 }  // namespace bm
 

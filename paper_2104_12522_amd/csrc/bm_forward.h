@@ -237,11 +237,14 @@ int launch_k_forward(const HostPlan& hp, const LaunchPlan& lp, size_t lds, char*
 
 // record preparation; kSingle: a single-segment plan whose model is in slot 0;
 // kMasked: `active` is not null; compact (or null): the list of requested samples of a
-// masked call and compact_count its length, taken in turn by gridDim.x sample slots
+// masked call and compact_count its length, taken in turn by gridDim.x sample slots;
+// build_n > 0: the kernel builds that list itself from the build_n flags of `active` (at most
+// kPrepListMax) and writes it to compact, its length to compact[build_n]
+constexpr int kPrepListMax = 1024;
 template <typename T, bool kSingle, bool kMasked>
 __global__ void k_atm_prep(LaunchPlan plan, const double* __restrict__ params, int stride,
                            const int32_t* __restrict__ active, char* __restrict__ ws,
-                           int32_t* __restrict__ flags_out, const int32_t* __restrict__ compact,
-                           const int32_t* __restrict__ compact_count);
+                           int32_t* __restrict__ flags_out, int32_t* __restrict__ compact,
+                           const int32_t* __restrict__ compact_count, int build_n);
 
 }  // namespace bm

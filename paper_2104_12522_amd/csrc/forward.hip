@@ -506,7 +506,10 @@ static int launch_forward(const HostPlan& hp, int cfg, const double* params, int
     if (compact) cfg = config_cached(cfg);
     const size_t lds = forward_lds_bytes<T>(hp.max_L, kFwdConfigs[cfg].waves, hp.max_ntc, kFwdConfigs[cfg].mode);
     int32_t* list = compact ? reinterpret_cast<int32_t*>(ws + hp.list_off) : nullptr;
-    if (compact) {
+    // the record preparation builds the list itself for up to kPrepListMax samples (one
+    // launch fewer); larger batches take the list kernel first
+    const bool prep_builds = compact && B <= kPrepListMax && kAtmThreads * (kPrepListMax / kAtmThreads) == kPrepListMax;
+    if (compact && !prep_builds) {
         hipLaunchKernelGGL(k_active_list, dim3(1), dim3(1024), 0, st, active, B, list);
         BM_CHECK_HIP(hipGetLastError());
     }
@@ -534,16 +537,16 @@ static int launch_forward(const HostPlan& hp, int cfg, const double* params, int
             const double* pp = params + (size_t)b0 * stride;
             if (single && act)
                 hipLaunchKernelGGL((k_atm_prep<T, true, true>), grid, dim3(kAtmThreads), 0, st, lp1, pp, stride, act, ws,
-                                   flags + b0, list, list_n);
+                                   flags + b0, list, list_n, prep_builds ? B : 0);
             else if (single)
                 hipLaunchKernelGGL((k_atm_prep<T, true, false>), grid, dim3(kAtmThreads), 0, st, lp1, pp, stride, act, ws,
-                                   flags + b0, nullptr, nullptr);
+                                   flags + b0, nullptr, nullptr, 0);
             else if (act)
                 hipLaunchKernelGGL((k_atm_prep<T, false, true>), grid, dim3(kAtmThreads), 0, st, lp1, pp, stride, act, ws,
-                                   flags + b0, list, list_n);
+                                   flags + b0, list, list_n, prep_builds ? B : 0);
             else
                 hipLaunchKernelGGL((k_atm_prep<T, false, false>), grid, dim3(kAtmThreads), 0, st, lp1, pp, stride, act, ws,
-                                   flags + b0, nullptr, nullptr);
+                                   flags + b0, nullptr, nullptr, 0);
         }
         BM_CHECK_HIP(hipGetLastError());
         double* c2 = chi2 ? chi2 + b0 : nullptr;
