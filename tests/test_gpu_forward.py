@@ -646,3 +646,30 @@ def test_masked_calls_beyond_the_pipelined_layers():
         else:
             assert bool((f.depth[d] == -7.0).all()), b
     f.set_config(-1)
+
+
+@pytest.mark.parametrize("B", [1024, 1100])
+def test_masked_calls_on_both_sides_of_the_preparation_built_list(B):
+    # up to 1024 samples the record preparation builds the list of requested samples
+    # itself; beyond, a list kernel runs first: both give the unmasked call's results for the
+    # requested samples (first, last and scattered ones) and leave the others untouched
+    s, sigma, cia = small_config2(n_nu=120, n_layers=60, seed=95)
+    nb = s.nu.size // s.bin_width
+    model = gpu_model(s, sigma, cia, data=np.full(nb, 0.02), err=np.full(nb, 6e-5))
+    params = torch.as_tensor(prior_for(s).draw(B, seed=96), device="cuda")
+    on = np.zeros(B, dtype=np.int32)
+    on[[0, 5, 511, 512, 777, B - 2, B - 1]] = 1
+    act = torch.as_tensor(on, device="cuda")
+    f = bm.Forward(model, B, binned=True, chi2=True)
+    f(params)
+    ref = [t.clone() for t in (f.depth, f.chi2, f.flags)]
+    f.depth.fill_(-7.0)
+    f.chi2.fill_(-7.0)
+    f(params, active=act)
+    torch.cuda.synchronize()
+    for b in range(B):
+        d = slice(int(f.depth_off[b]), int(f.depth_off[b + 1]))
+        if on[b]:
+            assert torch.equal(f.depth[d], ref[0][d]) and torch.equal(f.chi2[b], ref[1][b]), b
+        else:
+            assert bool((f.depth[d] == -7.0).all()) and float(f.chi2[b]) == -7.0, b
