@@ -186,7 +186,25 @@ struct DType<double> {
     static constexpr int code = BM_F64;
 };
 
-__device__ inline float dev_expm1(float x) { return expm1f(x); }
-__device__ inline double dev_expm1(double x) { return expm1(x); }
+// Absorbed fraction 1 - exp(-t) of a chord of optical depth t >= 0 (the integrand of the
+// transit-depth integral, Sec. 6.1). FP32: the Taylor polynomial of degree 7 below t = 0.35
+// (truncation under 2e-8 relative) and 1 - 2^(-t log2 e) from 0.35 up, where the result is
+// at least 0.29 and the subtraction loses nothing; both are evaluated and one is selected,
+// so that the chord loops carry no divergent branch. Within 3e-7 relative of the exact
+// value (a correctly rounded result is within 6e-8), at a third of expm1f's instructions.
+// FP64: -expm1(-t).
+__device__ __forceinline__ float dev_absorbed(float t) {
+    float p = 1.f / 5040.f;
+    p = fmaf(p, t, -1.f / 720.f);
+    p = fmaf(p, t, 1.f / 120.f);
+    p = fmaf(p, t, -1.f / 24.f);
+    p = fmaf(p, t, 1.f / 6.f);
+    p = fmaf(p, t, -0.5f);
+    p = fmaf(p, t, 1.f);
+    const float small = p * t;
+    const float large = 1.f - __builtin_amdgcn_exp2f(-1.44269504f * t);
+    return t < 0.35f ? small : large;
+}
+__device__ __forceinline__ double dev_absorbed(double t) { return -expm1(-t); }
 
 }  // namespace bm

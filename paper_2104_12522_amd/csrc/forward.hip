@@ -130,9 +130,9 @@ __global__ void k_transit_depth(const double* __restrict__ radius, const T* __re
     const int nu = blockIdx.x * blockDim.x + threadIdx.x;
     if (nu >= Nnu) return;
     double acc = radius[0] * radius[0];
-    double f_lo = -(double)dev_expm1(-tau[nu]);
+    double f_lo = (double)dev_absorbed(tau[nu]);
     for (int j = 0; j < L - 1; ++j) {
-        const double f_hi = -(double)dev_expm1(-tau[(size_t)(j + 1) * Nnu + nu]);
+        const double f_hi = (double)dev_absorbed(tau[(size_t)(j + 1) * Nnu + nu]);
         acc += (radius[j + 1] - radius[j]) * (f_lo * radius[j] + f_hi * radius[j + 1]);
         f_lo = f_hi;
     }

@@ -114,10 +114,10 @@ typedef __attribute__((address_space(3))) void* lds_void_ptr;
 
 // absorbed fraction of a chord, 1 - exp(-tau), or 1 at and beyond the optical-depth limit
 __device__ __forceinline__ double opaque_fraction(float tau, double tau_max) {
-    return (double)tau >= tau_max ? 1.0 : (double)(-expm1f(-tau));
+    return (double)tau >= tau_max ? 1.0 : (double)dev_absorbed(tau);
 }
 __device__ __forceinline__ double opaque_fraction(double tau, double tau_max) {
-    return tau >= tau_max ? 1.0 : -dev_expm1(-tau);
+    return tau >= tau_max ? 1.0 : dev_absorbed(tau);
 }
 // chord j: opaque at and below the cloud deck's layer jcl, else as above
 template <typename F>
@@ -203,6 +203,7 @@ __global__ void __launch_bounds__(kWaves * kWave)
         const int b = sg.first + s_in;
         if (!kLateExit && active && !active[b]) return;  // sample not requested in this call
         const int L = m.L, Nnu = m.Nnu;
+        const double tau_max = m.tau_max;
         const RecordView<T> rec(ws + sg.ws_off + (size_t)s_in * sg.rec_bytes, kS, L);
         const FwdLds<T> lay(L, kWaves, plan.max_ntc, kPipe);
 
@@ -438,8 +439,10 @@ __global__ void __launch_bounds__(kWaves * kWave)
                             double pp = 0.0;
     #pragma unroll
                             for (int r = 0; r < 4; ++r) {
+                                // rows past the last chord keep pp (a select, not a branch)
                                 const int j = kMfmaM * J + 4 * (lane >> 4) + r;
-                                if (j <= L - 2) pp += cw_s[j] * chord_fraction(j, jcl, acc[q][r], m.tau_max);
+                                const double t = pp + cw_s[min(j, L - 1)] * chord_fraction(j, jcl, acc[q][r], tau_max);
+                                pp = j <= L - 2 ? t : pp;
                             }
                             pp += __shfl_xor(pp, 16);
                             pp += __shfl_xor(pp, 32);
@@ -607,8 +610,10 @@ __global__ void __launch_bounds__(kWaves * kWave)
                     double pp = 0.0;
     #pragma unroll
                     for (int r = 0; r < 4; ++r) {
+                        // rows past the last chord keep pp (a select, not a branch)
                         const int j = kMfmaM * J + 4 * (lane >> 4) + r;
-                        if (j <= L - 2) pp += cw_s[j] * chord_fraction(j, jcl, acc[r], m.tau_max);
+                        const double t = pp + cw_s[min(j, L - 1)] * chord_fraction(j, jcl, acc[r], tau_max);
+                        pp = j <= L - 2 ? t : pp;
                     }
                     pp += __shfl_xor(pp, 16);
                     pp += __shfl_xor(pp, 32);
@@ -642,7 +647,7 @@ __global__ void __launch_bounds__(kWaves * kWave)
     #pragma unroll
                     for (int r = 0; r < kRows; ++r) {
                         const int j = j0 + r;
-                        if (j <= L - 2) acc += cw_s[j] * chord_fraction(j, jcl, t[r], m.tau_max);
+                        if (j <= L - 2) acc += cw_s[j] * chord_fraction(j, jcl, t[r], tau_max);
                     }
                 }
                 part[wave * kTileNu + lane] = acc;
