@@ -369,11 +369,14 @@ int bm_opacity_table_build_profiles(const double* nu0, const double* s296, const
  * archive-based DEMCzs, ter Braak & Vrugt 2008), here in archive form for a whole
  * generation of chains at once, so every chain's forward model of a generation is one
  * batched bm_forward_batch call. DE move: y = x + gamma (z_r1 - z_r2) + e from two
- * distinct archive rows, gamma = 2.38/sqrt(2d) (1 every 10th generation), e ~
+ * distinct archive rows, gamma = 2.38/sqrt(2k) (1 every 10th generation), e ~
  * N(0, (eps_scale width)^2). Snooker move (with probability p_snooker): a third distinct
  * archive row z; z_r1 and z_r2 projected onto the line through x and z; y = x +
  * gamma_s (projection difference), gamma_s ~ U[1.2, 2.2); proposal factor
- * (|y - z| / |x - z|)^(d-1) (no move when x = z). Log posterior -chi^2/2 in the uniform
+ * (|y - z| / |x - z|)^(k-1) (no move when x = z), k the number of free parameters (a
+ * parameter with lo = hi is held fixed: every state and archive row holds its value, so
+ * no move changes it, and the chains move in the space of the other k). Log posterior
+ * -chi^2/2 in the uniform
  * prior box; Metropolis-Hastings acceptance. Delayed acceptance (Christen & Fox 2005): a
  * surrogate chi^2 screens proposals (stage 1, with the proposal factor) and the exact
  * model decides among the survivors with the corrected ratio (stage 2, in which the
@@ -388,7 +391,7 @@ typedef struct bm_demcz {
     int32_t z_cap;      /* archive capacity in rows (>= 2)                                  */
     int32_t thin;       /* append the C chain states to the archive every `thin` generations */
     int32_t hist_cap;   /* generations the history buffer can hold (0 when history is NULL) */
-    int32_t pad;
+    int32_t n_free;     /* k: parameters with hi > lo (the others fixed); 0 reads as d       */
     uint64_t seed;      /* random stream                                                     */
     double eps_scale;   /* jitter sd as a fraction of each prior width (e.g. 1e-6)           */
     double* x;          /* [C][d] current states                                             */
@@ -399,13 +402,13 @@ typedef struct bm_demcz {
     int64_t* counters;  /* [2]: generation, archive rows in use                              */
     int64_t* n_accept;  /* [C][2]: stage-1 passes (delayed acceptance), acceptances          */
     double* history;    /* [hist_cap][C][d] states after each generation, or NULL            */
-    const double* lo;   /* [d] prior box lower bounds                                        */
+    const double* lo;   /* [d] prior box lower bounds (lo = hi holds a parameter fixed)      */
     const double* hi;   /* [d] prior box upper bounds                                        */
     double p_snooker;   /* probability of a snooker move per chain and generation (DEMCzs,
                            ter Braak & Vrugt 2008; 0.1 there), 0 = archive DE moves only     */
     double* log_q;      /* [C] log proposal factor of each chain's current proposal (0 for DE
                            moves); required when p_snooker > 0, else may be NULL           */
-    double gamma_scale; /* DE-move step factor: gamma = gamma_scale 2.38/sqrt(2d) (ter Braak's
+    double gamma_scale; /* DE-move step factor: gamma = gamma_scale 2.38/sqrt(2k) (ter Braak's
                            value for Gaussian targets); 0 is read as 1. The every-10th-
                            generation gamma = 1 moves are not scaled                         */
 } bm_demcz;

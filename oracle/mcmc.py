@@ -58,15 +58,25 @@ def init_state(seed: int, n_chains: int, z_init: int, lo, hi):
     return draws[z_init:].copy(), draws[:z_init].copy()
 
 
+def free_count(lo, hi) -> int:
+    """Number of free parameters (Sec. 5 sizes the chain count by them): those whose prior
+    box has non-zero width. A parameter with lo = hi is held fixed: every archive row and
+    state holds its value, so its DE difference and its jitter are zero and no move changes
+    it, and the chains move in the space of the others. All fixed reads as d."""
+    k = int(np.sum(np.asarray(hi, np.float64) > np.asarray(lo, np.float64)))
+    return k if k > 0 else len(lo)
+
+
 def propose(x, z, m: int, g: int, seed: int, lo, hi, eps_scale: float, gamma_scale: float = 1.0):
     """DE-MCz proposals of generation g: y = x + gamma (z_r1 - z_r2) + e, r1 != r2 uniform
-    over the m archive rows, gamma = gamma_scale 2.38/sqrt(2d) (1 every 10th generation;
-    ter Braak's value for Gaussian targets at gamma_scale = 1), e ~ N(0, (eps_scale *
-    width)^2). Returns (y, r1, r2)."""
+    over the m archive rows, gamma = gamma_scale 2.38/sqrt(2k) over the k free parameters
+    (1 every 10th generation; ter Braak's value for Gaussian targets at gamma_scale = 1),
+    e ~ N(0, (eps_scale * width)^2). Returns (y, r1, r2)."""
     n_chains, d = x.shape
     y = np.empty_like(x)
     r1s, r2s = np.empty(n_chains, int), np.empty(n_chains, int)
-    gamma = 1.0 if g % 10 == 9 else gamma_scale * (2.38 / math.sqrt(2.0 * d))
+    k = free_count(lo, hi)
+    gamma = 1.0 if g % 10 == 9 else gamma_scale * (2.38 / math.sqrt(2.0 * k))
     for c in range(n_chains):
         r1 = min(int(u01(seed, counter(g, c, n_chains, SLOT_R1)) * m), m - 1)
         r2 = min(int(u01(seed, counter(g, c, n_chains, SLOT_R2)) * (m - 1)), m - 2)
@@ -80,15 +90,17 @@ def propose(x, z, m: int, g: int, seed: int, lo, hi, eps_scale: float, gamma_sca
     return y, r1s, r2s
 
 
-def snooker(x, zz, z1, z2, gamma_s: float):
+def snooker(x, zz, z1, z2, gamma_s: float, k: int | None = None):
     """ter Braak & Vrugt (2008) snooker move of one chain: z_R1 and z_R2 are projected
     orthogonally onto the line through the state x and the archive member zz, and x moves
     along that line by gamma_s times the difference of the projections,
         y = x + gamma_s ((z_R1 - z_R2) . u) u,   u = (x - zz) / |x - zz|.
-    The move is accepted with the extra factor (|y - zz| / |x - zz|)^(d - 1); returns y and
-    the log of that factor (-inf when x = zz, where the line is undefined and y = x).
-    Sums run over the parameters in order; every operation is written out."""
+    The move is accepted with the extra factor (|y - zz| / |x - zz|)^(k - 1), k the
+    dimension of the space the chains move in (the free parameters; all d by default);
+    returns y and the log of that factor (-inf when x = zz, where the line is undefined and
+    y = x). Sums run over the parameters in order; every operation is written out."""
     d = len(x)
+    k = d if k is None else k
     nn, dot = 0.0, 0.0
     for p in range(d):
         e = x[p] - zz[p]
@@ -105,7 +117,7 @@ def snooker(x, zz, z1, z2, gamma_s: float):
         n2 = n2 + f * f
     if not n2 > 0.0:
         return y, -math.inf
-    return y, (0.5 * (d - 1)) * (math.log(n2) - math.log(nn))
+    return y, (0.5 * (k - 1)) * (math.log(n2) - math.log(nn))
 
 
 def third_row(u: float, m: int, r1: int, r2: int) -> int:
@@ -130,12 +142,13 @@ def propose_zs(x, z, m: int, g: int, seed: int, lo, hi, eps_scale: float, p_snoo
     log_q = np.zeros(n_chains)
     if p_snooker <= 0.0 or m < 3:
         return y, log_q
+    k = free_count(lo, hi)
     for c in range(n_chains):
         if not u01(seed, counter(g, c, n_chains, SLOT_MOVE)) < p_snooker:
             continue
         rz = third_row(u01(seed, counter(g, c, n_chains, SLOT_Z)), m, r1s[c], r2s[c])
         gamma_s = 1.2 + u01(seed, counter(g, c, n_chains, SLOT_GAMMA_S))
-        y[c], log_q[c] = snooker(x[c], z[rz], z[r1s[c]], z[r2s[c]], gamma_s)
+        y[c], log_q[c] = snooker(x[c], z[rz], z[r1s[c]], z[r2s[c]], gamma_s, k)
     return y, log_q
 
 

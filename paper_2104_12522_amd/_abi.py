@@ -39,7 +39,7 @@ class BmModel(C.Structure):
 class BmDemcz(C.Structure):
     _fields_ = [
         ("n_chains", C.c_int32), ("n_params", C.c_int32), ("z_cap", C.c_int32),
-        ("thin", C.c_int32), ("hist_cap", C.c_int32), ("pad", C.c_int32),
+        ("thin", C.c_int32), ("hist_cap", C.c_int32), ("n_free", C.c_int32),
         ("seed", C.c_uint64), ("eps_scale", C.c_double),
         ("x", C.c_void_p), ("lp", C.c_void_p), ("lp_surr", C.c_void_p), ("prop", C.c_void_p),
         ("z", C.c_void_p), ("counters", C.c_void_p), ("n_accept", C.c_void_p),

@@ -120,7 +120,8 @@ __global__ void k_demcz_propose(bm_demcz s, double gamma_de) {
             const double f = y[q] - zz[q];
             n2 = n2 + f * f;
         }
-        if (n2 > 0.0) lq = (0.5 * (d - 1)) * (log(n2) - log(nn));
+        const int k = s.n_free > 0 ? s.n_free : d;  // the dimension the chains move in
+        if (n2 > 0.0) lq = (0.5 * (k - 1)) * (log(n2) - log(nn));
     } else {
         for (int q = 0; q < d; ++q) y[q] = x[q];
     }
@@ -252,6 +253,7 @@ static int check_demcz(const bm_demcz* s) {
     if (!(s->eps_scale >= 0.0)) return BM_EINVAL;
     if (!(s->p_snooker >= 0.0 && s->p_snooker <= 1.0)) return BM_EINVAL;
     if (!(s->gamma_scale >= 0.0 && s->gamma_scale <= 4.0)) return BM_EINVAL;
+    if (s->n_free < 0 || s->n_free > s->n_params) return BM_ESHAPE;
     if (s->p_snooker > 0.0 && !s->log_q) return BM_EINVAL;
     return BM_OK;
 }
@@ -281,9 +283,11 @@ extern "C" int bm_demcz_set_lp(const bm_demcz* s, const double* chi2, const int3
 extern "C" int bm_demcz_propose(const bm_demcz* s, void* stream) {
     int st = check_demcz(s);
     if (st != BM_OK) return st;
-    // gamma = gamma_scale (2.38 / sqrt(2 d)) (correctly rounded host arithmetic)
+    // gamma = gamma_scale (2.38 / sqrt(2 k)), k free parameters (correctly rounded host
+    // arithmetic)
     const double scale = s->gamma_scale > 0.0 ? s->gamma_scale : 1.0;
-    const double gamma_de = scale * (2.38 / std::sqrt(2.0 * s->n_params));
+    const int k = s->n_free > 0 ? s->n_free : s->n_params;
+    const double gamma_de = scale * (2.38 / std::sqrt(2.0 * k));
     const int64_t n_threads = (int64_t)s->n_chains * s->n_params;
     hipLaunchKernelGGL(k_demcz_propose, dim3((unsigned)((n_threads + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
                        *s, gamma_de);

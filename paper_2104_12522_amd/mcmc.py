@@ -19,7 +19,8 @@ from . import (BartmiError, BmDemcz, BmModel, Forward, _check, _ptr, _stream, li
 
 class DEMCz:
     """GPU state of a DE-MCz sampler with snooker moves at rate p_snooker (see bm_demcz in
-    bartmi.h)."""
+    bartmi.h). A parameter with lo = hi is held fixed; the step factor and the snooker
+    proposal factor then count the free parameters only."""
 
     def __init__(self, n_chains: int, lo, hi, seed: int, thin: int = 10, z_cap: int | None = None,
                  hist_cap: int = 0, eps_scale: float = 1e-6, surrogate: bool = False,
@@ -44,6 +45,8 @@ class DEMCz:
         st = BmDemcz()
         st.n_chains, st.n_params, st.z_cap, st.thin = n_chains, d, self.z_cap, thin
         st.hist_cap = hist_cap
+        # parameters with lo = hi are held fixed; gamma and the snooker factor use the rest
+        st.n_free = int(np.sum(hi > lo))
         st.seed = seed & 0xFFFFFFFFFFFFFFFF
         st.eps_scale = eps_scale
         st.p_snooker = float(p_snooker)
@@ -149,7 +152,8 @@ class Retrieval:
     the same stream; it enables two-stage delayed acceptance. ``per_sample_workers`` > 0
     selects the plain per-sample form (PerSampleForward) instead of one batched call per
     generation. ``p_snooker`` is the rate of snooker moves (DEMCzs; 0.1 as in ter Braak &
-    Vrugt 2008)."""
+    Vrugt 2008). A parameter with lo = hi is held at that value (states and archive rows
+    given to ``resume`` must hold it)."""
 
     def __init__(self, model, n_chains: int, lo, hi, seed: int, thin: int = 10,
                  hist_cap: int = 0, surrogate=None, eps_scale: float = 1e-6, z_cap=None,

@@ -47,6 +47,29 @@ def test_init_and_proposals_match_reference(p_snooker, gscale):
         assert 5 < snk.sum() < C - 5
 
 
+def test_fixed_parameters_match_reference():
+    # log gamma1 and alpha held at -0.6 and 0.3 (zero-width prior): gamma and the snooker
+    # factor count the eight free parameters, and no move changes the fixed two
+    lo, hi = PRIOR.lo.copy(), PRIOR.hi.copy()
+    lo[[1, 3]] = hi[[1, 3]] = [-0.6, 0.3]
+    C, seed, z_init = 37, 13579, 100
+    s = DEMCz(C, lo, hi, seed, z_cap=400, p_snooker=0.5)
+    assert s.struct.n_free == 8
+    s.init(z_init)
+    x_ref, z_ref = om.init_state(seed, C, z_init, lo, hi)
+    torch.cuda.synchronize()
+    assert np.array_equal(_np(s.x), x_ref) and np.all(x_ref[:, [1, 3]] == [-0.6, 0.3])
+    assert np.array_equal(_np(s.z)[:z_init], z_ref)
+    s.propose()
+    y_ref, lq_ref = om.propose_zs(x_ref, z_ref, z_init, 0, seed, lo, hi, 1e-6, 0.5)
+    y = _np(s.prop)
+    assert np.all(y[:, [1, 3]] == [-0.6, 0.3])
+    np.testing.assert_allclose(y, y_ref, rtol=4.5e-16, atol=1e-300)
+    snk = lq_ref != 0.0
+    assert 5 < snk.sum() < C - 5 and np.array_equal(y[snk], y_ref[snk])
+    np.testing.assert_allclose(_np(s.log_q), lq_ref, rtol=1e-13, atol=1e-15)
+
+
 @pytest.mark.parametrize("p_snooker", [0.0, 0.5])
 def test_accept_bookkeeping_matches_reference(p_snooker):
     C, seed, d = 64, 4242, PRIOR.lo.size

@@ -34,6 +34,22 @@ def test_proposal_uses_two_distinct_archive_rows():
         np.testing.assert_allclose(y, x + gamma * (z[r1] - z[r2]), rtol=0, atol=1e-15)
 
 
+def test_fixed_parameter_proposals():
+    # a parameter with lo = hi: initial states and archive hold its value, no DE move or
+    # jitter changes it, and gamma counts the two free parameters only
+    lo, hi = np.zeros(3), np.ones(3)
+    lo[1] = hi[1] = 0.25
+    assert mcmc.free_count(lo, hi) == 2
+    x, z = mcmc.init_state(5, 40, 30, lo, hi)
+    assert np.all(x[:, 1] == 0.25) and np.all(z[:, 1] == 0.25)
+    for g in range(12):
+        y, r1, r2 = mcmc.propose(x, z, len(z), g, 5, lo, hi, 1e-6)
+        assert np.all(y[:, 1] == 0.25)
+        y0, r1, r2 = mcmc.propose(x, z, len(z), g, 5, lo, hi, 0.0)
+        gamma = 1.0 if g % 10 == 9 else 2.38 / math.sqrt(4.0)
+        np.testing.assert_allclose(y0, x + gamma * (z[r1] - z[r2]), rtol=0, atol=1e-15)
+
+
 def _gauss_chi2(mu, cov):
     icov = np.linalg.inv(cov)
 
@@ -127,6 +143,24 @@ def test_snooker_moves_alone_sample_a_correlated_gaussian():
     assert np.all(np.abs(s.mean(0) - _MU4) < 5 * se)
     np.testing.assert_allclose(s.var(0), np.diag(_COV4), rtol=0.15)
     assert 0.1 < acc.mean() / 2500 < 0.8
+
+
+def test_fixed_parameters_with_snooker_moves_sample_the_conditional():
+    # two of the four parameters held at their means (lo = hi): no move changes them, and
+    # with snooker moves only the free pair samples the conditional Gaussian. The move's
+    # proposal factor is a power of the distance ratio set by the dimension the chains move
+    # in (2 here); taken over all four dimensions it nearly doubles these variances
+    lo, hi = np.full(4, -3.0), np.full(4, 3.0)
+    lo[2:] = hi[2:] = _MU4[2:]
+    hist, acc = mcmc.run(_gauss_chi2(_MU4, _COV4), 16, 2500, lo, hi, seed=13, thin=5, p_snooker=1.0)
+    assert np.all(hist[:, :, 2:] == _MU4[2:])
+    s = hist[500:, :, :2].reshape(-1, 2)
+    b = _COV4[:2, 2:]
+    cond = _COV4[:2, :2] - b @ np.linalg.solve(_COV4[2:, 2:], b.T)
+    se = np.sqrt(np.diag(cond) / (s.shape[0] / 25.0))
+    assert np.all(np.abs(s.mean(0) - _MU4[:2]) < 5 * se)
+    np.testing.assert_allclose(s.var(0), np.diag(cond), rtol=0.15)
+    assert 0.1 < acc.mean() / 2500 < 0.9
 
 
 def test_demczs_with_delayed_acceptance_keeps_the_posterior():
