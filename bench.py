@@ -591,7 +591,10 @@ def section_mcmc(args, setup, prior):
     # measured in burn-in say that the whole run would not fit its time budget
     s_gen = t_burn / BURN
     s_gen_da = t_db / args.da_burn if args.da_burn > 0 else 0.3e-3
-    reserve = 30.0 + 1.2 * G_da * s_gen_da + (45.0 if "opacity" in args._sections else 0.0)
+    G_f = args.fixed_tp_gens
+    reserve = (30.0 + 1.2 * G_da * s_gen_da + (45.0 if "opacity" in args._sections else 0.0)
+               + ((2 * G_f + args.fixed_tp_burn) * 1.2 * s_gen + 5 * G_f * 1.2 * s_gen_da + 25.0
+                  if G_f > 0 else 0.0))
     left = args.time_budget - (time.time() - args._t0) - reserve
     G_asked = G
     if 2 * G * s_gen > left:
@@ -676,6 +679,8 @@ def section_mcmc(args, setup, prior):
     ratio_mc = da["ess_multichain_per_s"] / plain_ps["ess_multichain_per_s"]
     # end to end: surrogate data and training charged to the delayed-acceptance run
     e2e = (da["ess_multichain_min"] / (w_d + t_local)) / plain_ps["ess_multichain_per_s"]
+    fixed_tp = (section_fixed_tp(args, model, prior, truth, cov, C, run_graph, stats, ms_ps, spectra,
+                                 train, dims) if G_f > 0 else None)
     log(f"mcmc: ESS/s per-sample {plain_ps['ess_per_s']:.2f}, batched {plain_b['ess_per_s']:.2f}, "
         f"delayed acceptance {da['ess_per_s']:.2f} -> {ratio:.1f}x (multi-chain ESS: {ratio_mc:.1f}x); "
         f"max |mean diff| delayed acceptance vs plain {np.abs(diff).max():.3f} sd "
@@ -720,7 +725,119 @@ def section_mcmc(args, setup, prior):
         "marginal_mean": {"plain": mu_b2.tolist(), "plain_replicate": mu_q.tolist(),
                           "delayed_acceptance": mu_d.tolist()},
         "marginal_sd": {"plain": sd_b2.tolist(), "delayed_acceptance": sd_d.tolist()},
+        "fixed_tp": fixed_tp,
     }
+
+
+def section_fixed_tp(args, model, prior, truth, cov, C, run_graph, stats, ms_ps, spectra, train, dims):
+    """The same retrieval with the five T(p) parameters held at the truth (prior lo = hi):
+    the posterior of the four abundances and the reference radius. Its slowest integrated
+    time is tens of generations, so runs of a few thousand generations resolve it, and its
+    effective sample sizes, Gelman-Rubin statistics and mean agreement are not bounded by the
+    run length as the full posterior's are. After a plain burn-in, a local surrogate is
+    fitted around the burned-in states as for the full posterior (this posterior's radius
+    is eight times narrower than the full one's, finer than that surrogate's BF16 inputs
+    resolve); then two plain batched runs and one delayed-acceptance run from the common
+    burned-in state. The per-sample sampler's cost per generation is the one measured on the
+    full posterior."""
+    import torch
+    from paper_2104_12522_amd.mcmc import Retrieval, gaussian_states
+    from paper_2104_12522_amd.surrogate import MLP, Surrogate, standardisation
+    d = prior.lo.size
+    free = np.arange(5, d)
+    lo_f, hi_f = prior.lo.copy(), prior.hi.copy()
+    lo_f[:5] = hi_f[:5] = truth[:5]
+    # starting states: the Laplace approximation of the free parameters given T(p)
+    cond = np.linalg.inv(np.linalg.inv(cov)[np.ix_(free, free)])
+
+    def states(n, seed):
+        x = np.repeat(np.asarray(truth, np.float64)[None], n, axis=0)
+        x[:, free] = gaussian_states(truth[free], cond, n, lo_f[free], hi_f[free], seed=seed)
+        return torch.as_tensor(x, device="cuda")
+
+    G, B = args.fixed_tp_gens, args.fixed_tp_burn
+    G_da = 5 * G
+    rb = Retrieval(model, C, lo_f, hi_f, seed=args.seed + 80, thin=10, hist_cap=B,
+                   z_cap=10 * C + C * (B // 10 + 2))
+    rb.resume(states(C, args.seed + 81), states(10 * C, args.seed + 82))
+    t_burn = run_graph(rb, B)
+    x0 = rb.s.x.clone()
+    m = rb.s.archive_size
+    z0 = rb.s.z[max(0, m - 10 * C):m].clone()
+    hb = rb.s.history[B // 2:B].cpu().numpy().reshape(-1, d)[:, free]
+    del rb
+    # local surrogate: free inputs on a +-5 sd box around the burned-in states, the held
+    # parameters at the truth (a unit-wide box, so that their inputs are a constant 1/2)
+    t0 = time.perf_counter()
+    mu_b, cov_b = hb.mean(0), np.cov(hb.T)
+    sd_b = np.sqrt(np.diag(cov_b))
+    lo_s, hi_s = truth - 0.5, truth + 0.5
+    lo_s[free] = np.maximum(mu_b - args.surrogate_box * sd_b, prior.lo[free])
+    hi_s[free] = np.minimum(mu_b + args.surrogate_box * sd_b, prior.hi[free])
+    xl = np.repeat(np.asarray(truth, np.float64)[None], args.local_spectra, axis=0)
+    xl[:, free] = gaussian_states(mu_b, cov_b, args.local_spectra, lo_s[free], hi_s[free],
+                                  seed=args.seed + 86, inflate=2.0)
+    Xl = torch.as_tensor(xl, device="cuda")
+    Yl = spectra(Xl)
+    mean_l, scale_l = standardisation(Yl)
+    lo_t, hi_t = torch.as_tensor(lo_s, device="cuda"), torch.as_tensor(hi_s, device="cuda")
+    net = MLP(dims, max_batch=5000, seed=9)
+    train(net, lo_t, hi_t, Xl, Yl, mean_l, scale_l, args.epochs, 1e-3, 10)
+    torch.cuda.synchronize()
+    t_local = time.perf_counter() - t0
+    sur = Surrogate(net, lo_t, hi_t, mean_l, scale_l, model.data, model.err, n_chains=5000)
+    del Xl, Yl
+    log(f"mcmc fixed T(p): burn-in {B} generations in {t_burn:.1f} s; local surrogate in "
+        f"{t_local:.1f} s")
+
+    def production(surrogate, n_gen, stream):
+        r = Retrieval(model, C, lo_f, hi_f, seed=args.seed + stream, thin=10, hist_cap=n_gen,
+                      surrogate=surrogate, z_cap=z0.shape[0] + C * (n_gen // 10 + 1))
+        r.resume(x0, z0)
+        torch.cuda.synchronize()
+        wall = run_graph(r, n_gen)
+        acc = r.s.n_accept.sum(0).cpu().numpy() / (C * n_gen)
+        return r.s.history[:n_gen][:, :, 5:], wall, acc
+
+    h, w, a = production(None, G, 83)
+    plain, mu_1, sd_1, tau_1 = stats(h, w, a, G)
+    h, w, a = production(None, G, 85)
+    plain_q, mu_2, sd_2, tau_2 = stats(h, w, a, G)
+    h, w, a = production(sur, G_da, 84)
+    da, mu_d, sd_d, tau_d = stats(h, w, a, G_da, stage1_pass_rate=float(a[0]))
+    del h
+    ps_wall = ms_ps * 1e-3 * G
+    ps = {"ms_per_generation": ms_ps, "ess_per_s": plain["ess"] / ps_wall,
+          "ess_multichain_per_s": plain["ess_multichain_min"] / ps_wall}
+    sd_ref = 0.5 * (sd_1 + sd_2)
+    mu_plain = 0.5 * (mu_1 + mu_2)
+    se = lambda tau, n: sd_ref * np.sqrt(tau / (n * C))  # noqa: E731
+    diff = (mu_d - mu_plain) / sd_ref
+    diff_se = np.sqrt(0.25 * (se(tau_1, G) ** 2 + se(tau_2, G) ** 2) + se(tau_d, G_da) ** 2) / sd_ref
+    diff_pp = (mu_2 - mu_1) / sd_ref
+    out = {"free_parameters": ["log10 x_1", "log10 x_2", "log10 x_3", "log10 x_4", "R_ref / R_J"],
+           "held": {"values": truth[:5].tolist(),
+                    "parameters": ["log10 kappa", "log10 gamma1", "log10 gamma2", "alpha", "beta"]},
+           "burn_in": B, "local_surrogate_s": t_local, "plain_per_sample": ps, "plain_batched": plain,
+           "plain_batched_replicate": plain_q, "delayed_acceptance": da,
+           "ess_per_s_ratio_vs_per_sample": da["ess_per_s"] / ps["ess_per_s"],
+           "ess_multichain_per_s_ratio_vs_per_sample":
+               da["ess_multichain_per_s"] / ps["ess_multichain_per_s"],
+           "ess_per_s_ratio_vs_batched": da["ess_per_s"] / plain["ess_per_s"],
+           "ess_multichain_per_s_ratio_end_to_end":
+               (da["ess_multichain_min"] / (da["wall_s"] + t_local)) / ps["ess_multichain_per_s"],
+           "agreement": {"marginal_mean_diff_sd_vs_plain": diff.tolist(),
+                         "max_abs_mean_diff_sd_vs_plain": float(np.abs(diff).max()),
+                         "standard_error_sd": diff_se.tolist(),
+                         "plain_vs_plain_diff_sd": diff_pp.tolist(),
+                         "max_abs_plain_vs_plain_diff_sd": float(np.abs(diff_pp).max())},
+           "marginal_mean": {"plain": mu_plain.tolist(), "delayed_acceptance": mu_d.tolist()},
+           "marginal_sd": {"plain": sd_ref.tolist(), "delayed_acceptance": sd_d.tolist()}}
+    log(f"mcmc fixed T(p): ESS plain {plain['ess']:.0f} / {plain_q['ess']:.0f} in {G} generations, "
+        f"delayed acceptance {da['ess']:.0f} in {G_da}; Gelman-Rubin {plain['gelman_rubin_max']:.4f} / "
+        f"{da['gelman_rubin_max']:.4f}; ESS/s vs per-sample {out['ess_per_s_ratio_vs_per_sample']:.1f}x; "
+        f"max |mean diff| {np.abs(diff).max():.3f} sd (plain vs plain {np.abs(diff_pp).max():.3f} sd)")
+    return out
 
 
 def section_mlp(args):
@@ -1059,6 +1176,10 @@ def main():
                     help="further burn-in generations with delayed acceptance before production "
                          "(two to three times the slowest integrated time of this posterior)")
     ap.add_argument("--per-sample-gens", type=int, default=200)
+    ap.add_argument("--fixed-tp-gens", type=int, default=4000,
+                    help="generations of each plain run on the posterior with T(p) held at the "
+                         "truth (five times as many with delayed acceptance); 0 skips it")
+    ap.add_argument("--fixed-tp-burn", type=int, default=2000)
     ap.add_argument("--train-spectra", type=int, default=200000)
     ap.add_argument("--surrogate-box", type=float, default=5.0,
                     help="half-width of the local surrogate's input box, in burn-in sd")
