@@ -28,6 +28,7 @@
 #pragma once
 #include <hip/hip_ext.h>
 #include <climits>
+#include <type_traits>
 
 #include "bm_forward.h"
 
@@ -70,9 +71,13 @@ struct StageSize {
     static constexpr int chunks_per_wave = (chunks + 7) / 8;  // 8 waves per workgroup
 };
 
+// FP64 chord sums: each wave streams its row block's chord weights through a private LDS
+// chunk of kChunkL layers (32 layers x 8 rows x 8 bytes = 2 KB, two 16-byte pieces per lane)
+constexpr int kChunkL = 32;
+
 template <typename T>
 struct FwdLds {
-    size_t es, cw, ciat, part, bins, total;
+    size_t es, cw, ciat, part, bins, wst, total;
     int es_rows;
     __host__ __device__ FwdLds(int L, int kWaves, int ntc, bool pipe = false) {
         if (sizeof(T) == 4)
@@ -96,6 +101,10 @@ struct FwdLds {
             size_t u2 = bins + sizeof(double) * kTileNu - o;
             o += (u1 > u2 ? u1 : u2);
         }
+        // FP64: the waves' chord-weight chunks, apart from every region that phase 2 reads
+        // or that a wave writes when its chord sums are done
+        wst = align_up(o, 16);
+        if (sizeof(T) == 8) o = wst + sizeof(double) * (size_t)kWaves * kChunkL * kRows;
         const size_t chi2_part = sizeof(double) * (size_t)kWaves * kWave;
         total = o > chi2_part ? o : chi2_part;
     }
@@ -490,6 +499,19 @@ __global__ void __launch_bounds__(kWaves * kWave)
                     dval = (flags & BM_FLAG_RADIUS) ? __builtin_nan("") : sum / rs2;
                 }
             } else {
+            // FP64: the first chord-weight chunk of this wave's first row block (block `wave`)
+            // is fetched before phase 1, so that it has arrived when phase 2 starts
+            using pre_t = typename std::conditional<sizeof(T) == 8, double2, float>::type;
+            pre_t pre0{}, pre1{};
+            if constexpr (sizeof(T) == 8) {
+                if (wave * kRows <= L - 2) {
+                    const double2* __restrict__ src =
+                        reinterpret_cast<const double2*>(rec.wb + ((size_t)wave * L + wave * kRows) * kRows);
+                    const int n_pieces = (L - wave * kRows) * kRows / 2;
+                    pre0 = src[min(lane, n_pieces - 1)];
+                    pre1 = src[min(lane + kWave, n_pieces - 1)];
+                }
+            }
             // ---- phase 1: extinction into LDS --------------------------------------------
             // wave w owns layers [w*per, (w+1)*per). Their record fields are loaded once, one
             // layer per lane, and broadcast with v_readlane, so the table loads of a group of
@@ -627,9 +649,17 @@ __global__ void __launch_bounds__(kWaves * kWave)
                     dval = s / rec.hdr->rs2;
                 }
             } else {
-                // FP64: vector ALU, 8-row register blocks, chord weights as uniform loads
+                // FP64: vector ALU, 8-row register blocks. The block's chord weights (layers
+                // j0 .. L-1, 8 rows each, contiguous) pass through the wave's LDS chunk: two
+                // coalesced 16-byte loads per lane per 32 layers, issued one chunk ahead, read
+                // back as broadcasts. (Uniform scalar loads in the layer loop waited on memory
+                // every few layers: the scalar-memory counter also counts the LDS reads of e,
+                // so no scalar load could be kept in flight across them.)
                 double acc = 0.0;
                 const int nbu = (L - 1 + kRows - 1) / kRows;
+                double* wst = reinterpret_cast<double*>(smem + lay.wst) + (size_t)wave * kChunkL * kRows;
+                constexpr int kPieces = kChunkL * kRows / 2;  // 16-byte pieces per chunk (2 per lane)
+                static_assert(kPieces == 2 * kWave, "two pieces per lane");
                 for (int blk = 0; blk < nbu; ++blk) {
                     const int round = blk / kWaves, pos = blk - round * kWaves;
                     const int owner = (round & 1) ? (kWaves - 1 - pos) : pos;
@@ -638,11 +668,31 @@ __global__ void __launch_bounds__(kWaves * kWave)
                     T t[kRows];
     #pragma unroll
                     for (int r = 0; r < kRows; ++r) t[r] = T(0);
-                    const T* __restrict__ wcol = rec.wb + (size_t)blk * L * kRows;
-                    for (int l = j0; l < L; ++l) {
-                        const T e = es[es_index<T>(l, lane)];
+                    // pieces from layer j0 on; indices past the block's end are clamped to its
+                    // last piece (in bounds; those layers are never read back)
+                    const double2* __restrict__ src =
+                        reinterpret_cast<const double2*>(rec.wb + ((size_t)blk * L + j0) * kRows);
+                    const int n_pieces = (L - j0) * kRows / 2;
+                    double2 nx0 = blk == wave ? pre0 : src[min(lane, n_pieces - 1)];
+                    double2 nx1 = blk == wave ? pre1 : src[min(lane + kWave, n_pieces - 1)];
+                    for (int c0 = j0; c0 < L; c0 += kChunkL) {
+                        const double2 cur0 = nx0, cur1 = nx1;
+                        if (c0 + kChunkL < L) {  // the next chunk, in flight during this one
+                            const int q = (c0 + kChunkL - j0) * kRows / 2 + lane;
+                            nx0 = src[min(q, n_pieces - 1)];
+                            nx1 = src[min(q + kWave, n_pieces - 1)];
+                        }
+                        __builtin_amdgcn_wave_barrier();  // the previous chunk's reads are issued
+                        reinterpret_cast<double2*>(wst)[lane] = cur0;
+                        reinterpret_cast<double2*>(wst)[lane + kWave] = cur1;
+                        __builtin_amdgcn_wave_barrier();
+                        const int c1 = min(c0 + kChunkL, L);
+                        for (int l = c0; l < c1; ++l) {
+                            const T e = es[es_index<T>(l, lane)];
+                            const double* w = wst + (l - c0) * kRows;
     #pragma unroll
-                        for (int r = 0; r < kRows; ++r) t[r] = fma(wcol[l * kRows + r], e, t[r]);
+                            for (int r = 0; r < kRows; ++r) t[r] = fma(w[r], e, t[r]);
+                        }
                     }
     #pragma unroll
                     for (int r = 0; r < kRows; ++r) {
