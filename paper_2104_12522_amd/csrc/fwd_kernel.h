@@ -98,13 +98,20 @@ struct FwdLds {
         } else {
             part = o;
             bins = part + sizeof(double) * (size_t)nparts * kTileNu;
-            size_t u2 = bins + sizeof(double) * kTileNu - o;
-            o += (u1 > u2 ? u1 : u2);
+            const size_t u2 = bins + sizeof(double) * kTileNu - o;
+            // FP64: the waves' chord-weight chunks follow the partial sums and bins, over
+            // the CIA rows' tail (the CIA rows are dead after phase 1, which a barrier
+            // closes; the partial sums and bins are written while other waves still read
+            // their chunks, so they stay apart)
+            wst = align_up(bins + sizeof(double) * kTileNu, 16);
+            size_t u = u1 > u2 ? u1 : u2;
+            if (sizeof(T) == 8) {
+                const size_t u3 = wst + sizeof(double) * (size_t)kWaves * kChunkL * kRows - o;
+                if (u3 > u) u = u3;
+            }
+            o += u;
         }
-        // FP64: the waves' chord-weight chunks, apart from every region that phase 2 reads
-        // or that a wave writes when its chord sums are done
-        wst = align_up(o, 16);
-        if (sizeof(T) == 8) o = wst + sizeof(double) * (size_t)kWaves * kChunkL * kRows;
+        if (pipe) wst = o;  // unused (FP32 only)
         const size_t chi2_part = sizeof(double) * (size_t)kWaves * kWave;
         total = o > chi2_part ? o : chi2_part;
     }

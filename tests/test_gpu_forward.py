@@ -141,6 +141,21 @@ def test_fused_fp64_config1_parity():
     _check_fused(s, sigma, None, params, rtol=1e-10)
 
 
+@pytest.mark.parametrize("L", [33, 100, 256])
+def test_fused_fp64_many_layers(L):
+    # FP64 with config-2 physics (4 absorbers, CIA, channels, chi^2): the chord weights of
+    # a row block pass through 32-layer chunks, so 33 layers end a block one layer into its
+    # second chunk, 100 take four, and 256 (the layer limit) take eight with the LDS
+    # layout at its largest; 130 wavenumbers give two full tiles and a ragged one
+    s, sigma, cia = small_config2(n_nu=130, n_layers=L, seed=140 + L)
+    nb = s.nu.size // s.bin_width
+    g = np.random.default_rng(141)
+    data = 0.024 + 1e-4 * g.random(nb)
+    err = np.full(nb, 60e-6)
+    params = wl.line2013_prior(4).draw(2, seed=142 + L)
+    _check_fused(s, sigma.astype(np.float64), cia, params, rtol=1e-10, data=data, err=err)
+
+
 @pytest.mark.parametrize("n_nu", [1000, 1, 63, 65, 129])
 def test_fused_fp32_config2_parity(n_nu):
     s, sigma, cia = small_config2(n_nu=n_nu)
