@@ -50,7 +50,8 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 //   cw    impact-parameter weights [L] (double)
 //   u     CIA rows of the tile [NTc][64] (double) during phase 1; afterwards the
 //         per-row-block partial sums [blocks][64] and the tile's depths [64] (pipelined:
-//         separate regions, since row blocks finish while CIA rows are still read)
+//         separate regions, since row blocks finish while CIA rows are still read), and
+//         in FP64 after those the waves' chord-weight chunks [waves][kChunkL][8] (double)
 // Staged configurations keep the sample's FP32 chord-weight fragments in a static LDS
 // array, copied from the record straight into LDS at kernel start; it holds the fragments
 // of up to kStageMaxLayers layers (36 KB), or kPipeMaxLayers (28 KB) when pipelined.
