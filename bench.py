@@ -592,8 +592,13 @@ def section_mcmc(args, setup, prior):
     s_gen = t_burn / BURN
     s_gen_da = t_db / args.da_burn if args.da_burn > 0 else 0.3e-3
     G_f = args.fixed_tp_gens
-    reserve = (30.0 + 1.2 * G_da * s_gen_da + (45.0 if "opacity" in args._sections else 0.0)
-               + ((2 * G_f + args.fixed_tp_burn) * 1.2 * s_gen + 5 * G_f * 1.2 * s_gen_da + 25.0
+    # what the sections after the plain runs take: the delayed-acceptance run, the T(p)-fixed
+    # runs (two plain runs and a burn-in at the plain rate; two delayed-acceptance runs of
+    # 5 G_f generations that cost about 0.31 and 0.13 of a plain generation there, where a
+    # fifth and a thirteenth of the proposals pass the surrogate), the opacity section, with
+    # a 20 % margin
+    reserve = (20.0 + 1.2 * G_da * s_gen_da + (30.0 if "opacity" in args._sections else 0.0)
+               + (1.2 * ((2 * G_f + args.fixed_tp_burn) + 5 * G_f * (0.31 + 0.13)) * s_gen + 15.0
                   if G_f > 0 else 0.0))
     left = args.time_budget - (time.time() - args._t0) - reserve
     G_asked = G
@@ -790,9 +795,10 @@ def section_fixed_tp(args, model, prior, truth, cov, C, run_graph, stats, ms_ps,
     log(f"mcmc fixed T(p): burn-in {B} generations in {t_burn:.1f} s; local surrogate in "
         f"{t_local:.1f} s")
 
-    def production(surrogate, n_gen, stream):
+    def production(surrogate, n_gen, stream, gamma_scale=1.0):
         r = Retrieval(model, C, lo_f, hi_f, seed=args.seed + stream, thin=10, hist_cap=n_gen,
-                      surrogate=surrogate, z_cap=z0.shape[0] + C * (n_gen // 10 + 1))
+                      surrogate=surrogate, z_cap=z0.shape[0] + C * (n_gen // 10 + 1),
+                      gamma_scale=gamma_scale)
         r.resume(x0, z0)
         torch.cuda.synchronize()
         wall = run_graph(r, n_gen)
@@ -805,6 +811,11 @@ def section_fixed_tp(args, model, prior, truth, cov, C, run_graph, stats, ms_ps,
     plain_q, mu_2, sd_2, tau_2 = stats(h, w, a, G)
     h, w, a = production(sur, G_da, 84)
     da, mu_d, sd_d, tau_d = stats(h, w, a, G_da, stage1_pass_rate=float(a[0]))
+    # the same sampler with larger DE steps: the surrogate makes rejected proposals cheap, so
+    # delayed acceptance can trade acceptance for step length
+    gw = args.fixed_tp_da_gamma
+    h, w, a = production(sur, G_da, 86, gamma_scale=gw)
+    daw, mu_w, sd_w, tau_w = stats(h, w, a, G_da, stage1_pass_rate=float(a[0]), gamma_scale=gw)
     del h
     ps_wall = ms_ps * 1e-3 * G
     ps = {"ms_per_generation": ms_ps, "ess_per_s": plain["ess"] / ps_wall,
@@ -815,6 +826,8 @@ def section_fixed_tp(args, model, prior, truth, cov, C, run_graph, stats, ms_ps,
     diff = (mu_d - mu_plain) / sd_ref
     diff_se = np.sqrt(0.25 * (se(tau_1, G) ** 2 + se(tau_2, G) ** 2) + se(tau_d, G_da) ** 2) / sd_ref
     diff_pp = (mu_2 - mu_1) / sd_ref
+    diff_w = (mu_w - mu_plain) / sd_ref
+    diff_w_se = np.sqrt(0.25 * (se(tau_1, G) ** 2 + se(tau_2, G) ** 2) + se(tau_w, G_da) ** 2) / sd_ref
     out = {"free_parameters": ["log10 x_1", "log10 x_2", "log10 x_3", "log10 x_4", "R_ref / R_J"],
            "held": {"values": truth[:5].tolist(),
                     "parameters": ["log10 kappa", "log10 gamma1", "log10 gamma2", "alpha", "beta"]},
@@ -831,12 +844,29 @@ def section_fixed_tp(args, model, prior, truth, cov, C, run_graph, stats, ms_ps,
                          "standard_error_sd": diff_se.tolist(),
                          "plain_vs_plain_diff_sd": diff_pp.tolist(),
                          "max_abs_plain_vs_plain_diff_sd": float(np.abs(diff_pp).max())},
-           "marginal_mean": {"plain": mu_plain.tolist(), "delayed_acceptance": mu_d.tolist()},
-           "marginal_sd": {"plain": sd_ref.tolist(), "delayed_acceptance": sd_d.tolist()}}
+           "delayed_acceptance_larger_steps": {
+               **daw,
+               "ess_per_s_ratio_vs_per_sample": daw["ess_per_s"] / ps["ess_per_s"],
+               "ess_multichain_per_s_ratio_vs_per_sample":
+                   daw["ess_multichain_per_s"] / ps["ess_multichain_per_s"],
+               "ess_per_s_ratio_vs_batched": daw["ess_per_s"] / plain["ess_per_s"],
+               "ess_multichain_per_s_ratio_end_to_end":
+                   (daw["ess_multichain_min"] / (daw["wall_s"] + t_local)) / ps["ess_multichain_per_s"],
+               "marginal_mean_diff_sd_vs_plain": diff_w.tolist(),
+               "max_abs_mean_diff_sd_vs_plain": float(np.abs(diff_w).max()),
+               "standard_error_sd": diff_w_se.tolist()},
+           "marginal_mean": {"plain": mu_plain.tolist(), "delayed_acceptance": mu_d.tolist(),
+                             "delayed_acceptance_larger_steps": mu_w.tolist()},
+           "marginal_sd": {"plain": sd_ref.tolist(), "delayed_acceptance": sd_d.tolist(),
+                           "delayed_acceptance_larger_steps": sd_w.tolist()}}
     log(f"mcmc fixed T(p): ESS plain {plain['ess']:.0f} / {plain_q['ess']:.0f} in {G} generations, "
         f"delayed acceptance {da['ess']:.0f} in {G_da}; Gelman-Rubin {plain['gelman_rubin_max']:.4f} / "
         f"{da['gelman_rubin_max']:.4f}; ESS/s vs per-sample {out['ess_per_s_ratio_vs_per_sample']:.1f}x; "
-        f"max |mean diff| {np.abs(diff).max():.3f} sd (plain vs plain {np.abs(diff_pp).max():.3f} sd)")
+        f"max |mean diff| {np.abs(diff).max():.3f} sd (plain vs plain {np.abs(diff_pp).max():.3f} sd); "
+        f"with {gw}x DE steps: ESS {daw['ess']:.0f}, Gelman-Rubin {daw['gelman_rubin_max']:.4f}, "
+        f"ESS/s vs per-sample {out['delayed_acceptance_larger_steps']['ess_per_s_ratio_vs_per_sample']:.1f}x "
+        f"({out['delayed_acceptance_larger_steps']['ess_multichain_per_s_ratio_vs_per_sample']:.1f}x "
+        f"multi-chain), max |mean diff| {np.abs(diff_w).max():.3f} sd")
     return out
 
 
@@ -1180,6 +1210,9 @@ def main():
                     help="generations of each plain run on the posterior with T(p) held at the "
                          "truth (five times as many with delayed acceptance); 0 skips it")
     ap.add_argument("--fixed-tp-burn", type=int, default=2000)
+    ap.add_argument("--fixed-tp-da-gamma", type=float, default=2.0,
+                    help="DE step factor of the second delayed-acceptance run on the T(p)-fixed "
+                         "posterior (the first uses the plain runs' factor, 1)")
     ap.add_argument("--train-spectra", type=int, default=200000)
     ap.add_argument("--surrogate-box", type=float, default=5.0,
                     help="half-width of the local surrogate's input box, in burn-in sd")
