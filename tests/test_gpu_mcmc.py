@@ -187,6 +187,27 @@ def test_retrieval_graph_replay_matches_eager():
     assert torch.equal(eager.s.z, graphed.s.z)
 
 
+def test_retrieval_with_fixed_parameters():
+    # the five T(p) parameters held at the truth (lo = hi): every state of a graph-captured
+    # run with snooker moves keeps them, the others move, and the sampler counts five free
+    # parameters
+    model, truth = _retrieval_setup()
+    lo, hi = PRIOR.lo.copy(), PRIOR.hi.copy()
+    lo[:5] = hi[:5] = truth[:5]
+    r = Retrieval(model, 32, lo, hi, seed=77, thin=2, hist_cap=20)
+    assert r.s.struct.n_free == 5
+    r.start()
+    g = r.capture(10)
+    g.replay()
+    g.replay()
+    torch.cuda.synchronize()
+    h = _np(r.s.history)
+    assert np.all(h[:, :, :5] == truth[:5])
+    assert np.all(_np(r.s.z)[:r.s.archive_size, :5] == truth[:5])
+    assert int(r.s.n_accept[:, 1].sum()) > 0
+    assert np.all(h[-1, :, 5:].std(axis=0) > 0)
+
+
 def test_retrieval_chi2_matches_oracle_for_accepted_states():
     model, _ = _retrieval_setup()
     r = Retrieval(model, 32, PRIOR.lo, PRIOR.hi, seed=9, thin=2)
