@@ -166,3 +166,17 @@ def test_noalloc_size_limit_is_checked_on_the_host(lib):
     assert f(C.byref(m), 1, None, dummy, 10, B, None, dummy, None, None, dummy, None) == _abi.BM_ESCRATCH
     lib.bm_status_string.restype = C.c_char_p
     assert b"scratch" in lib.bm_status_string(_abi.BM_ESCRATCH)
+
+
+def test_sampler_free_count_is_checked_on_the_host(lib):
+    # n_free (the parameters with a prior box of non-zero width) beyond 0..d is rejected
+    # before any launch; the pointers are never dereferenced on the host
+    from paper_2104_12522_amd._abi import BmDemcz
+    s = BmDemcz()
+    s.n_chains, s.n_params, s.z_cap, s.thin = 8, 3, 16, 1
+    for name in ("x", "lp", "prop", "z", "counters", "n_accept", "lo", "hi"):
+        setattr(s, name, C.c_void_p(64))
+    lib.bm_demcz_propose.argtypes = [C.c_void_p, C.c_void_p]
+    for bad in (-1, 4):
+        s.n_free = bad
+        assert lib.bm_demcz_propose(C.byref(s), None) == -2, bad
