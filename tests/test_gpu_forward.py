@@ -82,6 +82,24 @@ def test_steps_match_oracle(dtype):
     np.testing.assert_allclose(_np(depth), d_ref, rtol=rt_depth)
 
 
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_absorbed_fraction_accuracy(dtype):
+    # two layers with r0 = 0 and Rs = r1 make the transit depth the top chord's absorbed
+    # fraction 1 - exp(-tau) itself; FP32 evaluates it without expm1f (a Taylor polynomial
+    # below tau = 0.35, the hardware exp2 above), claimed within 3e-7 relative everywhere
+    tau1 = np.concatenate([np.logspace(-10, 2.5, 4001), np.linspace(0.34, 0.36, 2001), [0.0, 1e3]])
+    tau1 = tau1.astype(np.float32 if dtype == torch.float32 else np.float64)
+    tau = torch.zeros(2, tau1.size, dtype=dtype, device="cuda")
+    tau[1] = torch.as_tensor(tau1, device="cuda")
+    r1 = 7.0e9
+    got = _np(bm.transit_depth(np.array([0.0, r1]), tau, r1))
+    want = -np.expm1(-tau1.astype(np.float64))
+    rtol = 3e-7 if dtype == torch.float32 else 1e-15
+    m = want > 0
+    print(f"{dtype}: max relative error {np.max(np.abs(got[m] - want[m]) / want[m]):.3g}")
+    np.testing.assert_allclose(got, want, rtol=rtol, atol=1e-300)
+
+
 def test_bin_chi2_matches_oracle():
     g = np.random.default_rng(3)
     depth = 0.02 + 1e-3 * g.random((3, 95))
